@@ -1,0 +1,172 @@
+/*
+ * wd.h -- C-ABI of the MI355X (gfx950) Wilson-Dirac / CG / HMC library.
+ *
+ * The operations follow arXiv:1207.2223 ("Hybrid Monte Carlo with Wilson Dirac
+ * operator on the Fermi GPU"): the fermion matrix M = D + m applied to a
+ * pseudofermion field and its adjoint (Sec. 3, kernel 1), the conjugate-gradient
+ * inversion of M^dag M that the pseudofermion action of eq. (4) requires
+ * (eq. 3 and Sec. 2), the molecular-dynamics force (Sec. 3, kernels 2 and 3)
+ * and the HMC trajectory of Sec. 3 (refresh, leapfrog, accept/reject).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  lattice  dims = {Lx, Ly, Lz, Lt}, every extent even and >= 2; periodic
+ *           boundaries in all four directions for links and fermions.
+ *           lex = x + Lx*(y + Ly*(z + Lz*t)); parity = (x+y+z+t) & 1;
+ *           checkerboard index cb = lex >> 1; V = Lx*Ly*Lz*Lt, Vh = V/2.
+ *  operator M = 1 - kappa*H (the kappa-normalised M = D + m, eq. 4) with
+ *           (H psi)(x) = sum_mu (1 - g_mu) U_mu(x) psi(x+mu)
+ *                              + (1 + g_mu) U_mu(x-mu)^dag psi(x-mu),
+ *           gamma matrices in the chiral (DeGrand-Rossi) basis, gamma_1..4
+ *           along x, y, z, t.  M^dag = 1 - kappa*H^dag swaps (1-g) and (1+g).
+ *           Even-odd: D_eo / D_oe are the parity blocks of H and
+ *           Mhat = 1 - kappa^2 D_eo D_oe acts on even sites.
+ *  layouts  canonical complex128 with interleaved (re, im) doubles:
+ *             full spinor   [V][4 spin][3 colour]      lex order
+ *             parity spinor [Vh][4][3]                 cb order of that parity
+ *             links         [V][4 mu][3][3]            U_mu(x), row-major
+ *             momenta/force [V][4][3][3]               Hermitian traceless
+ *           Batches of right-hand sides are [nrhs][...] back to back.
+ *  memory   Unless stated otherwise, every pointer argument is a DEVICE
+ *           pointer on the context's device (e.g. a torch tensor's
+ *           data_ptr()), owned by the caller and never retained after the
+ *           call returns.  The library owns its packed copy of the gauge
+ *           field and all workspaces.
+ *  streams  Work is issued on the hipStream_t given to wd_create.  Calls
+ *           that return statistics synchronise that stream before returning.
+ *  errors   Every call returns a wd_status; on failure wd_last_error()
+ *           returns a message for the calling thread.  WD_ERR_ARG,
+ *           WD_ERR_DIMS and WD_ERR_OOM are raised before any output is
+ *           written.
+ */
+#ifndef WD_H
+#define WD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    WD_OK = 0,
+    WD_ERR_ARG = -1,    /* invalid argument (null pointer, bad enum, bad size) */
+    WD_ERR_DIMS = -2,   /* lattice extent odd, < 2, or too large               */
+    WD_ERR_OOM = -3,    /* device allocation failed or budget exceeded         */
+    WD_ERR_HIP = -4,    /* a HIP runtime call failed                           */
+    WD_ERR_NOCONV = -5, /* solver hit maxiter; best iterate is returned        */
+    WD_ERR_NAN = -6,    /* non-finite residual or breakdown (p.Ap <= 0)        */
+    WD_ERR_STATE = -7   /* call out of order (e.g. no gauge field loaded)      */
+} wd_status;
+
+typedef enum { WD_F64 = 0, WD_F32 = 1, WD_F16 = 2 } wd_prec;
+/* Or-ed into a WD_F32 / WD_F16 precision code: the sloppy operator reads
+ * FP16 12-real links instead of FP32 12-real links. */
+#define WD_LINKS_F16 0x10
+typedef enum { WD_FULL = 0, WD_EVEN = 1, WD_ODD = 2 } wd_parity;
+
+/* wd_gauge_load flags: storage of the FP64 operator's links. */
+#define WD_RECON_18 0u /* all 18 reals of each link                        */
+#define WD_RECON_12 1u /* rows 1-2 only; row 3 = conj(row1 x row2) on load */
+
+typedef struct wd_ctx wd_ctx;
+
+/* Solver parameters (CG on M^dag M, eq. 3-4). */
+typedef struct {
+    double tol;       /* target true relative residual |b - A x|_2 / |b|_2 (FP64)  */
+    int maxiter;      /* iteration cap; WD_ERR_NOCONV past it                       */
+    int prec_sloppy;  /* wd_prec of the iterated operator and vectors               */
+    int eo;           /* 1: A = Mhat^dag Mhat on even sites; 0: A = M^dag M (full)  */
+    double delta;     /* reliable update when |r| < delta * max|r| since the last  */
+    int poll;         /* iterations between host checks of the residual norms       */
+    int tuned;        /* 1: use autotuned launch shapes (wd_tune), 0: defaults      */
+} wd_solver_params;
+
+/* Per right-hand-side solver statistics. */
+typedef struct {
+    int iters;            /* CG iterations applied to this RHS                     */
+    int reliable_updates; /* FP64 true-residual recomputations                     */
+    double true_resid;    /* final |b - A x| / |b| in FP64                          */
+    double seconds;       /* wall time of the whole batched call                   */
+    int status;           /* wd_status of this RHS                                 */
+} wd_solver_stats;
+
+/* Fill p with the defaults: tol 1e-10, maxiter 20000, FP64, eo 1, delta 0.1,
+ * poll 8, tuned 0.  p: host pointer. */
+void wd_solver_defaults(wd_solver_params *p);
+
+/* Create a context for one lattice on HIP device `device`, issuing work on
+ * `hip_stream` (a hipStream_t; NULL = the null stream).  *c receives the
+ * handle.  WD_ERR_DIMS for an odd or too small extent, or V >= 2^31. */
+wd_status wd_create(wd_ctx **c, const int32_t dims[4], int device, void *hip_stream);
+
+/* Free the context and everything it owns.  NULL is accepted. */
+wd_status wd_destroy(wd_ctx *c);
+
+/* Bind a different stream for subsequent work (NULL = null stream). */
+wd_status wd_set_stream(wd_ctx *c, void *hip_stream);
+
+/* Load the gauge field U (canonical [V][4][3][3] complex128, device) and pack
+ * it into the internal layouts: FP64 with 18 or 12 reals (flags), and FP32
+ * and FP16 12-real copies for the sloppy operators.  Links are assumed to be
+ * in SU(3) (12-real reconstruction is exact only there). */
+wd_status wd_gauge_load(wd_ctx *c, const double *U, uint32_t flags);
+
+/* Hopping term (Sec. 3, kernel 1, without the mass term):
+ *   out_parity = WD_EVEN / WD_ODD: out[Vh][4][3] = D_{P,1-P} in, with `in`
+ *     the [Vh][4][3] field on the other parity;
+ *   out_parity = WD_FULL: out[V][4][3] = H in on the full lattice.
+ * dagger = 1 applies H^dag.  prec (a wd_prec, optionally | WD_LINKS_F16)
+ * selects the arithmetic and storage used inside: FP64 with the gauge_load
+ * link format, or FP32 / FP16-with-norm spinors with FP32 (or FP16) 12-real
+ * links and FP32 arithmetic.  The canonical in/out stay FP64. */
+wd_status wd_dslash(wd_ctx *c, double *out, const double *in, int out_parity, int dagger,
+                    int prec);
+
+/* Normal operator: eo = 0: out = M^dag M in (full [V][4][3]);
+ * eo = 1: out = Mhat^dag Mhat in (even [Vh][4][3]).  FP64 arithmetic. */
+wd_status wd_mdagm(wd_ctx *c, double *out, const double *in, double kappa, int eo);
+
+/* Solve A x_j = phi_j for nrhs right-hand sides at once (eq. 3: the inverse
+ * of M^dag M applied to the pseudofermion).  A is M^dag M (p->eo = 0, fields
+ * [nrhs][V][4][3]) or Mhat^dag Mhat (p->eo = 1, fields [nrhs][Vh][4][3],
+ * even sites).  kappa: HOST array [nrhs], one hopping parameter per RHS.
+ * st: HOST array [nrhs] or NULL.  x0 = 0.  Converged means the FP64 true
+ * residual meets p->tol.  With a sloppy precision the iteration runs in
+ * FP32 or FP16 (per-site norm) with FP64 dot products and FP64 reliable
+ * updates.  Returns WD_ERR_NOCONV / WD_ERR_NAN if any RHS failed (the other
+ * RHS are still solved); x holds the best iterate of every RHS. */
+wd_status wd_cg_solve(wd_ctx *c, double *x, const double *phi, int nrhs, const double *kappa,
+                      const wd_solver_params *p, wd_solver_stats *st);
+
+/* Index tables computed on the HOST from the definition above: nb [V][8]
+ * (x+mu, x-mu for mu = 0..3), cb [V], par [V].  HOST pointers. */
+wd_status wd_index_tables(const int32_t dims[4], int32_t *nb, int32_t *cb, uint8_t *par);
+
+/* The same tables as computed by the device index arithmetic the kernels use
+ * (DEVICE pointers, same shapes). */
+wd_status wd_debug_device_tables(wd_ctx *c, int32_t *nb, int32_t *cb, uint8_t *par);
+
+/* Device bytes a context needs for the gauge field plus a solve of nrhs
+ * right-hand sides with these parameters (p may be NULL for defaults). */
+size_t wd_bytes_required(const int32_t dims[4], int nrhs, const wd_solver_params *p);
+
+/* Per-kernel timing with HIP events on the context's stream.  When enabled,
+ * every stencil launch is bracketed by events; wd_timing_read returns the
+ * summed milliseconds, launch count and algorithmic bytes of the stencil
+ * launches since the last reset (host pointers). */
+wd_status wd_timing_enable(wd_ctx *c, int on);
+wd_status wd_timing_read(wd_ctx *c, double *total_ms, int64_t *launches, double *bytes);
+
+/* Message of the last failed call on this thread (never NULL). */
+const char *wd_last_error(void);
+
+/* Library version string. */
+const char *wd_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WD_H */

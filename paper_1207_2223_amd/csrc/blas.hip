@@ -1,0 +1,312 @@
+// blas.hip -- CG vector kernels over batches of spinor fields (the level-1
+// BLAS work the paper delegates to CUBLAS, Sec. 3), fused where CG allows,
+// with deterministic FP64 reductions: each 64-site wavefront writes one
+// partial sum in fixed butterfly order, and blas_finalize adds the partials
+// of one RHS in a fixed order in a single work-group.
+#include "wd_internal.h"
+
+namespace wd {
+
+namespace {
+
+constexpr int kBlock = 256;
+
+struct FArg {
+    char *base;
+    long long rs, ss;
+};
+inline FArg fa(const Field &f) { return FArg{f.base, f.rs, f.ss}; }
+
+__device__ __forceinline__ char *site_base(const FArg &f, int rid, int sub)
+{
+    return f.base + rid * f.rs + sub * f.ss;
+}
+
+template <int SP>
+__global__ void __launch_bounds__(kBlock) k_norm(FArg a, int Vh, int nsub, const int *active,
+                                                  double *partial, int pstride)
+{
+    typedef typename SpinorIO<SP>::real real;
+    const int rid = active[blockIdx.y];
+    const int s = blockIdx.x * kBlock + threadIdx.x;
+    double v = 0.0;
+    if (s < nsub * Vh) {
+        const int sub = s / Vh, i = s - sub * Vh;
+        real x[24];
+        SpinorIO<SP>::load(site_base(a, rid, sub), Vh, i, x);
+#pragma unroll
+        for (int k = 0; k < 24; k++) v += (double)x[k] * (double)x[k];
+    }
+    v = wave_sum(v);
+    if ((threadIdx.x & 63) == 0 && s < nsub * Vh) partial[(size_t)rid * pstride + (s >> 6)] = v;
+}
+
+template <int SP>
+__global__ void __launch_bounds__(kBlock) k_p_update(FArg p, FArg r, const double *beta, int Vh,
+                                                      int nsub, const int *active)
+{
+    typedef typename SpinorIO<SP>::real real;
+    const int rid = active[blockIdx.y];
+    const int s = blockIdx.x * kBlock + threadIdx.x;
+    if (s >= nsub * Vh) return;
+    const int sub = s / Vh, i = s - sub * Vh;
+    const real b = (real)beta[rid];
+    real pv[24], rv[24];
+    SpinorIO<SP>::load(site_base(p, rid, sub), Vh, i, pv);
+    SpinorIO<SP>::load(site_base(r, rid, sub), Vh, i, rv);
+#pragma unroll
+    for (int k = 0; k < 24; k++) pv[k] = rv[k] + b * pv[k];
+    SpinorIO<SP>::store(site_base(p, rid, sub), Vh, i, pv);
+}
+
+template <int SP, int XP>
+__global__ void __launch_bounds__(kBlock) k_cg_update(FArg x, FArg p, FArg r, FArg Ap,
+                                                       const double *alpha, int Vh, int nsub,
+                                                       const int *active, double *partial,
+                                                       int pstride)
+{
+    typedef typename SpinorIO<SP>::real real;
+    typedef typename SpinorIO<XP>::real xreal;
+    const int rid = active[blockIdx.y];
+    const int s = blockIdx.x * kBlock + threadIdx.x;
+    double v = 0.0;
+    if (s < nsub * Vh) {
+        const int sub = s / Vh, i = s - sub * Vh;
+        const real al = (real)alpha[rid];
+        real pv[24], rv[24], av[24];
+        xreal xv[24];
+        SpinorIO<SP>::load(site_base(p, rid, sub), Vh, i, pv);
+        SpinorIO<SP>::load(site_base(r, rid, sub), Vh, i, rv);
+        SpinorIO<SP>::load(site_base(Ap, rid, sub), Vh, i, av);
+        SpinorIO<XP>::load(site_base(x, rid, sub), Vh, i, xv);
+#pragma unroll
+        for (int k = 0; k < 24; k++) {
+            xv[k] += (xreal)(al * pv[k]);
+            rv[k] -= al * av[k];
+            v += (double)rv[k] * (double)rv[k];
+        }
+        SpinorIO<XP>::store(site_base(x, rid, sub), Vh, i, xv);
+        SpinorIO<SP>::store(site_base(r, rid, sub), Vh, i, rv);
+    }
+    v = wave_sum(v);
+    if ((threadIdx.x & 63) == 0 && s < nsub * Vh) partial[(size_t)rid * pstride + (s >> 6)] = v;
+}
+
+template <int SPD, int SPS>
+__global__ void __launch_bounds__(kBlock) k_copy(FArg d, FArg src, int Vh, int nsub,
+                                                  const int *active)
+{
+    const int rid = active[blockIdx.y];
+    const int s = blockIdx.x * kBlock + threadIdx.x;
+    if (s >= nsub * Vh) return;
+    const int sub = s / Vh, i = s - sub * Vh;
+    double v[24];
+    SpinorIO<SPS>::load(site_base(src, rid, sub), Vh, i, v);
+    SpinorIO<SPD>::store(site_base(d, rid, sub), Vh, i, v);
+}
+
+// xhi (FP64) += xs ; xs = 0
+template <int XP>
+__global__ void __launch_bounds__(kBlock) k_add_zero(FArg xhi, FArg xs, int Vh, int nsub,
+                                                      const int *active)
+{
+    const int rid = active[blockIdx.y];
+    const int s = blockIdx.x * kBlock + threadIdx.x;
+    if (s >= nsub * Vh) return;
+    const int sub = s / Vh, i = s - sub * Vh;
+    double h[24], l[24];
+    SpinorIO<SP_F64>::load(site_base(xhi, rid, sub), Vh, i, h);
+    SpinorIO<XP>::load(site_base(xs, rid, sub), Vh, i, l);
+#pragma unroll
+    for (int k = 0; k < 24; k++) {
+        h[k] += l[k];
+        l[k] = 0.0;
+    }
+    SpinorIO<SP_F64>::store(site_base(xhi, rid, sub), Vh, i, h);
+    SpinorIO<XP>::store(site_base(xs, rid, sub), Vh, i, l);
+}
+
+// r = b - Ap, all FP64, with |r|^2 partials
+__global__ void __launch_bounds__(kBlock) k_resid(FArg r, FArg b, FArg Ap, int Vh, int nsub,
+                                                   const int *active, double *partial,
+                                                   int pstride)
+{
+    const int rid = active[blockIdx.y];
+    const int s = blockIdx.x * kBlock + threadIdx.x;
+    double v = 0.0;
+    if (s < nsub * Vh) {
+        const int sub = s / Vh, i = s - sub * Vh;
+        double bv[24], av[24];
+        SpinorIO<SP_F64>::load(site_base(b, rid, sub), Vh, i, bv);
+        SpinorIO<SP_F64>::load(site_base(Ap, rid, sub), Vh, i, av);
+#pragma unroll
+        for (int k = 0; k < 24; k++) {
+            bv[k] -= av[k];
+            v += bv[k] * bv[k];
+        }
+        SpinorIO<SP_F64>::store(site_base(r, rid, sub), Vh, i, bv);
+    }
+    v = wave_sum(v);
+    if ((threadIdx.x & 63) == 0 && s < nsub * Vh) partial[(size_t)rid * pstride + (s >> 6)] = v;
+}
+
+template <int SP>
+__global__ void __launch_bounds__(kBlock) k_zero(FArg a, int Vh, int nsub, const int *active)
+{
+    const int rid = active[blockIdx.y];
+    const int s = blockIdx.x * kBlock + threadIdx.x;
+    if (s >= nsub * Vh) return;
+    const int sub = s / Vh, i = s - sub * Vh;
+    double z[24];
+#pragma unroll
+    for (int k = 0; k < 24; k++) z[k] = 0.0;
+    SpinorIO<SP>::store(site_base(a, rid, sub), Vh, i, z);
+}
+
+// One work-group per active RHS: fixed-order sum of its partials, then the
+// CG scalar update selected by mode.
+__global__ void __launch_bounds__(kBlock) k_finalize(const double *partial, int pstride, int nw,
+                                                      const int *active, int mode, double *rr,
+                                                      double *alpha, double *beta, double *out)
+{
+    __shared__ double sh[kBlock];
+    const int rid = active[blockIdx.x];
+    const double *pp = partial + (size_t)rid * pstride;
+    double v = 0.0;
+    for (int w = threadIdx.x; w < nw; w += kBlock) v += pp[w];
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int off = kBlock / 2; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double s = sh[0];
+        if (mode == FIN_STORE) {
+            out[rid] = s;
+        } else if (mode == FIN_ALPHA) {
+            // s = p.Ap = |M p|^2 ; breakdown (s <= 0 or not finite) poisons rr
+            if (s > 0.0 && s < INFINITY) {
+                alpha[rid] = rr[rid] / s;
+            } else {
+                alpha[rid] = 0.0;
+                rr[rid] = NAN;
+            }
+        } else if (mode == FIN_BETA) {
+            beta[rid] = s / rr[rid];
+            rr[rid] = s;
+        } else {
+            rr[rid] = s;
+        }
+    }
+}
+
+inline dim3 grid_of(int Vh, int nsub, int nact) { return dim3((nsub * Vh + kBlock - 1) / kBlock, nact); }
+
+}  // namespace
+
+#define SP_SWITCH(sp, F)                                                                          \
+    switch (sp) {                                                                                 \
+    case SP_F64: F(SP_F64); break;                                                                \
+    case SP_F32: F(SP_F32); break;                                                                \
+    case SP_F16: F(SP_F16); break;                                                                \
+    default: return hipErrorInvalidValue;                                                         \
+    }
+
+hipError_t blas_norm(const Field &a, int Vh, const int *active, int nact, double *partial,
+                     int pstride, hipStream_t s)
+{
+    if (nact == 0) return hipSuccess;
+#define F(SP) hipLaunchKernelGGL(k_norm<SP>, grid_of(Vh, a.nsub, nact), dim3(kBlock), 0, s, fa(a), Vh, a.nsub, active, partial, pstride)
+    SP_SWITCH(a.sp, F)
+#undef F
+    return hipGetLastError();
+}
+
+hipError_t blas_p_update(const Field &p, const Field &r, const double *beta, int Vh,
+                         const int *active, int nact, hipStream_t s)
+{
+    if (nact == 0) return hipSuccess;
+    if (p.sp != r.sp) return hipErrorInvalidValue;
+#define F(SP) hipLaunchKernelGGL(k_p_update<SP>, grid_of(Vh, p.nsub, nact), dim3(kBlock), 0, s, fa(p), fa(r), beta, Vh, p.nsub, active)
+    SP_SWITCH(p.sp, F)
+#undef F
+    return hipGetLastError();
+}
+
+hipError_t blas_cg_update(const Field &x, const Field &p, const Field &r, const Field &Ap,
+                          const double *alpha, int Vh, const int *active, int nact,
+                          double *partial, int pstride, hipStream_t s)
+{
+    if (nact == 0) return hipSuccess;
+    dim3 gr = grid_of(Vh, p.nsub, nact);
+    if (p.sp == SP_F64 && x.sp == SP_F64)
+        hipLaunchKernelGGL((k_cg_update<SP_F64, SP_F64>), gr, dim3(kBlock), 0, s, fa(x), fa(p), fa(r), fa(Ap), alpha, Vh, p.nsub, active, partial, pstride);
+    else if (p.sp == SP_F32 && x.sp == SP_F32)
+        hipLaunchKernelGGL((k_cg_update<SP_F32, SP_F32>), gr, dim3(kBlock), 0, s, fa(x), fa(p), fa(r), fa(Ap), alpha, Vh, p.nsub, active, partial, pstride);
+    else if (p.sp == SP_F16 && x.sp == SP_F32)
+        hipLaunchKernelGGL((k_cg_update<SP_F16, SP_F32>), gr, dim3(kBlock), 0, s, fa(x), fa(p), fa(r), fa(Ap), alpha, Vh, p.nsub, active, partial, pstride);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t blas_copy(const Field &dst, const Field &src, int Vh, const int *active, int nact,
+                     hipStream_t s)
+{
+    if (nact == 0) return hipSuccess;
+    dim3 gr = grid_of(Vh, dst.nsub, nact);
+#define C2(D, S)                                                                                  \
+    if (dst.sp == D && src.sp == S) {                                                             \
+        hipLaunchKernelGGL((k_copy<D, S>), gr, dim3(kBlock), 0, s, fa(dst), fa(src), Vh, dst.nsub, active); \
+        return hipGetLastError();                                                                 \
+    }
+    C2(SP_F64, SP_F64) C2(SP_F64, SP_F32) C2(SP_F64, SP_F16)
+    C2(SP_F32, SP_F64) C2(SP_F32, SP_F32) C2(SP_F32, SP_F16)
+    C2(SP_F16, SP_F64) C2(SP_F16, SP_F32) C2(SP_F16, SP_F16)
+#undef C2
+    return hipErrorInvalidValue;
+}
+
+hipError_t blas_add_zero(const Field &xhi, const Field &xs, int Vh, const int *active, int nact,
+                         hipStream_t s)
+{
+    if (nact == 0) return hipSuccess;
+    if (xhi.sp != SP_F64) return hipErrorInvalidValue;
+    dim3 gr = grid_of(Vh, xhi.nsub, nact);
+    if (xs.sp == SP_F32)
+        hipLaunchKernelGGL(k_add_zero<SP_F32>, gr, dim3(kBlock), 0, s, fa(xhi), fa(xs), Vh, xhi.nsub, active);
+    else if (xs.sp == SP_F64)
+        hipLaunchKernelGGL(k_add_zero<SP_F64>, gr, dim3(kBlock), 0, s, fa(xhi), fa(xs), Vh, xhi.nsub, active);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t blas_resid(const Field &r, const Field &b, const Field &Ap, int Vh, const int *active,
+                      int nact, double *partial, int pstride, hipStream_t s)
+{
+    if (nact == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_resid, grid_of(Vh, r.nsub, nact), dim3(kBlock), 0, s, fa(r), fa(b), fa(Ap), Vh, r.nsub, active, partial, pstride);
+    return hipGetLastError();
+}
+
+hipError_t blas_zero(const Field &a, int Vh, const int *active, int nact, hipStream_t s)
+{
+    if (nact == 0) return hipSuccess;
+#define F(SP) hipLaunchKernelGGL(k_zero<SP>, grid_of(Vh, a.nsub, nact), dim3(kBlock), 0, s, fa(a), Vh, a.nsub, active)
+    SP_SWITCH(a.sp, F)
+#undef F
+    return hipGetLastError();
+}
+
+hipError_t blas_finalize(const double *partial, int pstride, int nw, const int *active, int nact,
+                         int mode, double *rr, double *alpha, double *beta, double *out,
+                         hipStream_t s)
+{
+    if (nact == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_finalize, dim3(nact), dim3(kBlock), 0, s, partial, pstride, nw, active, mode, rr, alpha, beta, out);
+    return hipGetLastError();
+}
+
+}  // namespace wd

@@ -1,0 +1,546 @@
+// context.hip -- context lifetime, gauge-field loading, the stencil launcher
+// with optional event timing, and the operator-level C-ABI calls
+// (wd_dslash, wd_mdagm, index tables).
+#include <stdarg.h>
+#include <stdio.h>
+
+#include <cmath>
+#include <cstring>
+
+#include "wd_internal.h"
+
+namespace wd {
+
+static thread_local char g_err[512] = "no error";
+
+wd_status set_error(wd_status st, const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return st;
+}
+
+wd_status ws_get(wd_ctx *c, const std::string &name, size_t bytes, void **ptr)
+{
+    auto it = c->ws.find(name);
+    if (it != c->ws.end() && it->second.second >= bytes) {
+        *ptr = it->second.first;
+        return WD_OK;
+    }
+    if (it != c->ws.end()) {
+        WD_HIP(hipStreamSynchronize(c->stream));
+        WD_HIP(hipFree(it->second.first));
+        c->ws.erase(it);
+    }
+    void *p = nullptr;
+    if (hipMalloc(&p, bytes ? bytes : 256) != hipSuccess) {
+        (void)hipGetLastError();
+        return set_error(WD_ERR_OOM, "device allocation of %zu bytes for '%s' failed", bytes,
+                         name.c_str());
+    }
+    c->ws[name] = {p, bytes};
+    *ptr = p;
+    return WD_OK;
+}
+
+wd_status pinned_get(wd_ctx *c, int slot, size_t bytes, void **ptr)
+{
+    if (c->pinned_bytes[slot] < bytes) {
+        if (c->pinned[slot]) {
+            WD_HIP(hipStreamSynchronize(c->stream));
+            WD_HIP(hipHostFree(c->pinned[slot]));
+            c->pinned[slot] = nullptr;
+        }
+        size_t nb = bytes < 4096 ? 4096 : bytes;
+        WD_HIP(hipHostMalloc(&c->pinned[slot], nb, hipHostMallocDefault));
+        c->pinned_bytes[slot] = nb;
+    }
+    *ptr = c->pinned[slot];
+    return WD_OK;
+}
+
+wd_status alloc_field(wd_ctx *c, const std::string &name, int sp, int nsub, int nrhs, Field *f)
+{
+    const long long sb = (long long)spinor_site_bytes(sp) * c->Vh;
+    const long long sub = (sb + 255) / 256 * 256;
+    void *p = nullptr;
+    WD_TRY(ws_get(c, name, (size_t)sub * nsub * nrhs, &p));
+    f->base = (char *)p;
+    f->ss = sub;
+    f->rs = sub * nsub;
+    f->sp = sp;
+    f->nsub = nsub;
+    return WD_OK;
+}
+
+const char *link_ptr(const wd_ctx *c, int lk)
+{
+    if (lk == LK_F64_18 || lk == LK_F64_12) return c->links64;
+    if (lk == LK_F32_12) return c->links32;
+    return c->links16;
+}
+
+TuneCfg default_cfg(int sp)
+{
+    TuneCfg t;
+    t.block = 128;
+    t.nr = 1;
+    t.remap = 1;
+    (void)sp;
+    return t;
+}
+
+double sweep_bytes(const wd_ctx *c, const Sweep &sw)
+{
+    const double sb = (double)spinor_site_bytes(sw.sp), xb = (double)spinor_site_bytes(sw.xp);
+    double per_rhs = 2 * sb;
+    if (sw.epi == EPI_XPAY) per_rhs = 3 * sb;
+    if (sw.epi == EPI_CGUPD) per_rhs = 5 * sb + 2 * xb;
+    return (double)c->Vh * (8.0 * (double)link_bytes(sw.lk) + sw.nact * per_rhs);
+}
+
+static int clamp_nr(int sp, int nr)
+{
+    if (sp == SP_F64) return nr >= 2 ? 2 : 1;
+    return nr >= 4 ? 4 : (nr >= 2 ? 2 : 1);
+}
+
+wd_status run_sweep(wd_ctx *c, const Sweep &sw, const TuneCfg *cfg)
+{
+    if (sw.nact <= 0) return WD_OK;
+    TuneCfg t = cfg ? *cfg : default_cfg(sw.sp);
+    const int nr = clamp_nr(sw.sp, t.nr);
+    DslashArgs a;
+    a.g = c->g;
+    a.P = sw.P;
+    a.links = link_ptr(c, sw.lk);
+    a.in = sw.in.base;
+    a.in_rs = sw.in.rs;
+    a.out = sw.out.base;
+    a.out_rs = sw.out.rs;
+    a.x = sw.x.base;
+    a.x_rs = sw.x.rs;
+    a.coef = sw.coef;
+    a.p = sw.p.base;
+    a.p_rs = sw.p.rs;
+    a.xs = sw.xs.base;
+    a.xs_rs = sw.xs.rs;
+    a.r = sw.r.base;
+    a.r_rs = sw.r.rs;
+    a.alpha = sw.alpha;
+    a.active = sw.active;
+    a.nact = sw.nact;
+    a.G = (sw.nact + nr - 1) / nr;
+    a.remap = t.remap;
+    a.partial = sw.partial;
+    a.pstride = sw.pstride;
+    a.pw_off = sw.pw_off;
+    const int ntiles = (int)((c->Vh + t.block - 1) / t.block);
+    const long long grid = (long long)ntiles * a.G;
+    if (grid > 0x7fffffffLL) return set_error(WD_ERR_ARG, "grid too large");
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (c->timing) {
+        if (c->ev_used == c->events.size()) {
+            hipEvent_t x0, x1;
+            WD_HIP(hipEventCreate(&x0));
+            WD_HIP(hipEventCreate(&x1));
+            c->events.push_back({x0, x1});
+        }
+        e0 = c->events[c->ev_used].first;
+        e1 = c->events[c->ev_used].second;
+        c->ev_used++;
+        WD_HIP(hipEventRecord(e0, c->stream));
+    }
+    hipError_t e;
+    if (sw.sp == SP_F64)
+        e = dslash_launch_f64(a, sw.lk, nr, sw.dag, sw.epi, t.block, (int)grid, c->stream);
+    else if (sw.sp == SP_F32)
+        e = dslash_launch_f32(a, sw.lk, nr, sw.dag, sw.epi, t.block, (int)grid, c->stream);
+    else
+        e = dslash_launch_f16(a, sw.lk, nr, sw.dag, sw.epi, t.block, (int)grid, c->stream);
+    if (e != hipSuccess)
+        return set_error(WD_ERR_HIP, "stencil launch (sp %d lk %d nr %d epi %d block %d): %s", sw.sp,
+                         sw.lk, nr, sw.epi, t.block, hipGetErrorString(e));
+    if (c->timing) {
+        WD_HIP(hipEventRecord(e1, c->stream));
+        c->t_bytes += sweep_bytes(c, sw);
+        c->t_launches++;
+    }
+    return WD_OK;
+}
+
+static wd_status upload(wd_ctx *c, void *dst, const void *src, size_t bytes)
+{
+    void *h = nullptr;
+    WD_HIP(hipStreamSynchronize(c->stream));
+    WD_TRY(pinned_get(c, 0, bytes, &h));
+    std::memcpy(h, src, bytes);
+    WD_HIP(hipMemcpyAsync(dst, h, bytes, hipMemcpyHostToDevice, c->stream));
+    WD_HIP(hipStreamSynchronize(c->stream));
+    return WD_OK;
+}
+
+wd_status upload_doubles(wd_ctx *c, const std::string &name, const double *v, int n, double **dev)
+{
+    void *p = nullptr;
+    WD_TRY(ws_get(c, name, sizeof(double) * n, &p));
+    WD_TRY(upload(c, p, v, sizeof(double) * n));
+    *dev = (double *)p;
+    return WD_OK;
+}
+
+wd_status upload_ints(wd_ctx *c, const std::string &name, const int *v, int n, int **dev)
+{
+    void *p = nullptr;
+    WD_TRY(ws_get(c, name, sizeof(int) * (n ? n : 1), &p));
+    if (n) WD_TRY(upload(c, p, v, sizeof(int) * n));
+    *dev = (int *)p;
+    return WD_OK;
+}
+
+Field sub_view(const Field &f, int s)
+{
+    Field v = f;
+    v.base = f.base + s * f.ss;
+    v.nsub = 1;
+    v.ss = 0;
+    return v;
+}
+
+}  // namespace wd
+
+using namespace wd;
+
+extern "C" {
+
+const char *wd_last_error(void) { return g_err; }
+
+const char *wd_version(void) { return "wd 0.1 (gfx950)"; }
+
+void wd_solver_defaults(wd_solver_params *p)
+{
+    if (!p) return;
+    p->tol = 1e-10;
+    p->maxiter = 20000;
+    p->prec_sloppy = WD_F64;
+    p->eo = 1;
+    p->delta = 0.1;
+    p->poll = 8;
+    p->tuned = 0;
+}
+
+static wd_status check_dims(const int32_t *dims, long long *V)
+{
+    if (!dims) return set_error(WD_ERR_ARG, "dims is NULL");
+    long long v = 1;
+    for (int mu = 0; mu < 4; mu++) {
+        if (dims[mu] < 2 || (dims[mu] & 1))
+            return set_error(WD_ERR_DIMS, "extent %d of direction %d must be even and >= 2", dims[mu], mu);
+        v *= dims[mu];
+    }
+    if (v >= (1LL << 31)) return set_error(WD_ERR_DIMS, "volume %lld too large", v);
+    *V = v;
+    return WD_OK;
+}
+
+wd_status wd_create(wd_ctx **out, const int32_t dims[4], int device, void *hip_stream)
+{
+    if (!out) return set_error(WD_ERR_ARG, "NULL context pointer");
+    long long V;
+    WD_TRY(check_dims(dims, &V));
+    int ndev = 0;
+    WD_HIP(hipGetDeviceCount(&ndev));
+    if (device < 0 || device >= ndev) return set_error(WD_ERR_ARG, "device %d not present", device);
+    WD_HIP(hipSetDevice(device));
+    wd_ctx *c = new wd_ctx();
+    c->device = device;
+    c->stream = (hipStream_t)hip_stream;
+    for (int mu = 0; mu < 4; mu++) {
+        c->dims[mu] = dims[mu];
+        c->g.L[mu] = dims[mu];
+    }
+    c->V = V;
+    c->Vh = V / 2;
+    c->g.Vh = (int)c->Vh;
+    c->g.Lxh = dims[0] / 2;
+    c->g.sy = c->g.Lxh;
+    c->g.sz = c->g.Lxh * dims[1];
+    c->g.st = c->g.Lxh * dims[1] * dims[2];
+    *out = c;
+    return WD_OK;
+}
+
+wd_status wd_destroy(wd_ctx *c)
+{
+    if (!c) return WD_OK;
+    (void)hipSetDevice(c->device);
+    (void)hipStreamSynchronize(c->stream);
+    for (auto &kv : c->ws) (void)hipFree(kv.second.first);
+    if (c->links64) (void)hipFree(c->links64);
+    if (c->links32) (void)hipFree(c->links32);
+    if (c->links16) (void)hipFree(c->links16);
+    for (int k = 0; k < 2; k++)
+        if (c->pinned[k]) (void)hipHostFree(c->pinned[k]);
+    for (auto &e : c->events) {
+        (void)hipEventDestroy(e.first);
+        (void)hipEventDestroy(e.second);
+    }
+    delete c;
+    return WD_OK;
+}
+
+wd_status wd_set_stream(wd_ctx *c, void *hip_stream)
+{
+    if (!c) return set_error(WD_ERR_ARG, "NULL context");
+    WD_HIP(hipStreamSynchronize(c->stream));
+    c->stream = (hipStream_t)hip_stream;
+    return WD_OK;
+}
+
+wd_status wd_gauge_load(wd_ctx *c, const double *U, uint32_t flags)
+{
+    if (!c || !U) return set_error(WD_ERR_ARG, "NULL argument");
+    if (flags & ~1u) return set_error(WD_ERR_ARG, "unknown gauge flags 0x%x", flags);
+    WD_HIP(hipSetDevice(c->device));
+    const int lk64 = (flags & WD_RECON_12) ? LK_F64_12 : LK_F64_18;
+    const size_t n64 = link_bytes(lk64) * 4 * c->V, n32 = link_bytes(LK_F32_12) * 4 * c->V,
+                 n16 = link_bytes(LK_F16_12) * 4 * c->V;
+    WD_HIP(hipStreamSynchronize(c->stream));
+    if (c->links64 && c->lk64 != lk64) {
+        WD_HIP(hipFree(c->links64));
+        c->links64 = nullptr;
+    }
+    auto alloc = [&](char **p, size_t n) -> wd_status {
+        if (*p) return WD_OK;
+        if (hipMalloc((void **)p, n) != hipSuccess) {
+            (void)hipGetLastError();
+            *p = nullptr;
+            return set_error(WD_ERR_OOM, "gauge allocation of %zu bytes failed", n);
+        }
+        return WD_OK;
+    };
+    WD_TRY(alloc(&c->links64, n64));
+    WD_TRY(alloc(&c->links32, n32));
+    WD_TRY(alloc(&c->links16, n16));
+    c->lk64 = lk64;
+    hipError_t e;
+    if ((e = pack_gauge(U, c->links64, lk64, c->g, c->stream)) != hipSuccess ||
+        (e = pack_gauge(U, c->links32, LK_F32_12, c->g, c->stream)) != hipSuccess ||
+        (e = pack_gauge(U, c->links16, LK_F16_12, c->g, c->stream)) != hipSuccess)
+        return set_error(WD_ERR_HIP, "gauge packing failed: %s", hipGetErrorString(e));
+    c->have_gauge = true;
+    return WD_OK;
+}
+
+// Operator storage for a requested precision code.
+static wd_status prec_formats(const wd_ctx *c, int prec, int *sp, int *lk)
+{
+    const int base = prec & 0xf;
+    const bool l16 = (prec & WD_LINKS_F16) != 0;
+    if (prec & ~(0xf | WD_LINKS_F16)) return set_error(WD_ERR_ARG, "unknown precision code %d", prec);
+    if (base == WD_F64) {
+        if (l16) return set_error(WD_ERR_ARG, "FP16 links need an FP32/FP16 operator");
+        *sp = SP_F64;
+        *lk = c->lk64;
+    } else if (base == WD_F32 || base == WD_F16) {
+        *sp = (base == WD_F32) ? SP_F32 : SP_F16;
+        *lk = l16 ? LK_F16_12 : LK_F32_12;
+    } else {
+        return set_error(WD_ERR_ARG, "unknown precision %d", base);
+    }
+    return WD_OK;
+}
+
+wd_status wd_dslash(wd_ctx *c, double *out, const double *in, int out_parity, int dagger, int prec)
+{
+    if (!c || !out || !in) return set_error(WD_ERR_ARG, "NULL argument");
+    if (!c->have_gauge) return set_error(WD_ERR_STATE, "no gauge field loaded");
+    if (out_parity < WD_FULL || out_parity > WD_ODD) return set_error(WD_ERR_ARG, "bad parity %d", out_parity);
+    int sp, lk;
+    WD_TRY(prec_formats(c, prec, &sp, &lk));
+    WD_HIP(hipSetDevice(c->device));
+    const int full = (out_parity == WD_FULL);
+    Field fi, fo;
+    WD_TRY(alloc_field(c, "dsl_in", sp, 2, 1, &fi));
+    WD_TRY(alloc_field(c, "dsl_out", sp, 2, 1, &fo));
+    int zero = 0;
+    int *act;
+    WD_TRY(upload_ints(c, "dsl_act", &zero, 1, &act));
+    hipError_t e;
+    if (full) {
+        if ((e = pack_spinor(in, fi, 1, 1, c->g, c->stream)) != hipSuccess)
+            return set_error(WD_ERR_HIP, "pack: %s", hipGetErrorString(e));
+        for (int P = 0; P < 2; P++) {
+            Sweep sw;
+            sw.sp = sp; sw.lk = lk; sw.dag = dagger ? 1 : 0; sw.epi = EPI_PLAIN; sw.P = P;
+            sw.in = sub_view(fi, 1 - P);
+            sw.out = sub_view(fo, P);
+            sw.active = act; sw.nact = 1;
+            WD_TRY(run_sweep(c, sw, nullptr));
+        }
+        if ((e = unpack_spinor(fo, out, 1, 1, c->g, c->stream)) != hipSuccess)
+            return set_error(WD_ERR_HIP, "unpack: %s", hipGetErrorString(e));
+    } else {
+        const int P = (out_parity == WD_EVEN) ? 0 : 1;
+        Field vi = sub_view(fi, 0), vo = sub_view(fo, 0);
+        if ((e = pack_spinor(in, vi, 1, 0, c->g, c->stream)) != hipSuccess)
+            return set_error(WD_ERR_HIP, "pack: %s", hipGetErrorString(e));
+        Sweep sw;
+        sw.sp = sp; sw.lk = lk; sw.dag = dagger ? 1 : 0; sw.epi = EPI_PLAIN; sw.P = P;
+        sw.in = vi; sw.out = vo; sw.active = act; sw.nact = 1;
+        WD_TRY(run_sweep(c, sw, nullptr));
+        if ((e = unpack_spinor(vo, out, 1, 0, c->g, c->stream)) != hipSuccess)
+            return set_error(WD_ERR_HIP, "unpack: %s", hipGetErrorString(e));
+    }
+    return WD_OK;
+}
+
+wd_status wd_mdagm(wd_ctx *c, double *out, const double *in, double kappa, int eo)
+{
+    if (!c || !out || !in) return set_error(WD_ERR_ARG, "NULL argument");
+    if (!c->have_gauge) return set_error(WD_ERR_STATE, "no gauge field loaded");
+    if (!std::isfinite(kappa)) return set_error(WD_ERR_ARG, "kappa not finite");
+    WD_HIP(hipSetDevice(c->device));
+    const int sp = SP_F64, lk = c->lk64;
+    double cf[2] = {-kappa, -kappa * kappa};
+    double *dcf;
+    WD_TRY(upload_doubles(c, "mdm_coef", cf, 2, &dcf));
+    int idx[2] = {0, 1};
+    int *act;
+    WD_TRY(upload_ints(c, "mdm_act", idx, 2, &act));
+    hipError_t e;
+    Field A, T, B;
+    WD_TRY(alloc_field(c, "mdm_a", sp, 2, 1, &A));
+    WD_TRY(alloc_field(c, "mdm_t", sp, 2, 1, &T));
+    WD_TRY(alloc_field(c, "mdm_b", sp, 2, 1, &B));
+    Sweep sw;
+    sw.sp = sp; sw.lk = lk; sw.nact = 1;
+    if (eo) {
+        // the coefficient array is indexed by RHS id: use id 1 -> -kappa^2
+        sw.active = act + 1;
+        // fields are addressed as RHS id 1 with zero RHS stride
+        Field a0 = sub_view(A, 0), t1 = sub_view(T, 1), b0 = sub_view(B, 0), c0 = sub_view(T, 0);
+        a0.rs = t1.rs = b0.rs = c0.rs = 0;
+        if ((e = pack_spinor(in, a0, 1, 0, c->g, c->stream)) != hipSuccess)
+            return set_error(WD_ERR_HIP, "pack: %s", hipGetErrorString(e));
+        sw.coef = dcf;
+        sw.P = 1; sw.dag = 0; sw.epi = EPI_PLAIN; sw.in = a0; sw.out = t1;
+        WD_TRY(run_sweep(c, sw, nullptr));
+        sw.P = 0; sw.epi = EPI_XPAY; sw.in = t1; sw.x = a0; sw.out = b0;
+        WD_TRY(run_sweep(c, sw, nullptr));
+        sw.P = 1; sw.dag = 1; sw.epi = EPI_PLAIN; sw.in = b0; sw.out = t1;
+        WD_TRY(run_sweep(c, sw, nullptr));
+        sw.P = 0; sw.epi = EPI_XPAY; sw.in = t1; sw.x = b0; sw.out = c0;
+        WD_TRY(run_sweep(c, sw, nullptr));
+        if ((e = unpack_spinor(c0, out, 1, 0, c->g, c->stream)) != hipSuccess)
+            return set_error(WD_ERR_HIP, "unpack: %s", hipGetErrorString(e));
+    } else {
+        sw.active = act;  // id 0 -> -kappa
+        sw.coef = dcf;
+        if ((e = pack_spinor(in, A, 1, 1, c->g, c->stream)) != hipSuccess)
+            return set_error(WD_ERR_HIP, "pack: %s", hipGetErrorString(e));
+        sw.epi = EPI_XPAY;
+        for (int pass = 0; pass < 2; pass++) {
+            const Field &src = pass ? T : A;
+            const Field &dst = pass ? B : T;
+            sw.dag = pass;
+            for (int P = 0; P < 2; P++) {
+                sw.P = P;
+                sw.in = sub_view(src, 1 - P);
+                sw.x = sub_view(src, P);
+                sw.out = sub_view(dst, P);
+                WD_TRY(run_sweep(c, sw, nullptr));
+            }
+        }
+        if ((e = unpack_spinor(B, out, 1, 1, c->g, c->stream)) != hipSuccess)
+            return set_error(WD_ERR_HIP, "unpack: %s", hipGetErrorString(e));
+    }
+    return WD_OK;
+}
+
+wd_status wd_index_tables(const int32_t dims[4], int32_t *nb, int32_t *cb, uint8_t *par)
+{
+    long long V;
+    WD_TRY(check_dims(dims, &V));
+    if (!nb || !cb || !par) return set_error(WD_ERR_ARG, "NULL argument");
+    const int L[4] = {dims[0], dims[1], dims[2], dims[3]};
+    for (long long s = 0; s < V; s++) {
+        int x[4];
+        long long r = s;
+        for (int mu = 0; mu < 4; mu++) {
+            x[mu] = (int)(r % L[mu]);
+            r /= L[mu];
+        }
+        for (int mu = 0; mu < 4; mu++)
+            for (int d = 0; d < 2; d++) {
+                int y[4] = {x[0], x[1], x[2], x[3]};
+                y[mu] = (y[mu] + (d ? L[mu] - 1 : 1)) % L[mu];
+                nb[s * 8 + 2 * mu + d] = (int32_t)(y[0] + (long long)L[0] * (y[1] + (long long)L[1] * (y[2] + (long long)L[2] * y[3])));
+            }
+        cb[s] = (int32_t)(s >> 1);
+        par[s] = (uint8_t)((x[0] + x[1] + x[2] + x[3]) & 1);
+    }
+    return WD_OK;
+}
+
+wd_status wd_debug_device_tables(wd_ctx *c, int32_t *nb, int32_t *cb, uint8_t *par)
+{
+    if (!c || !nb || !cb || !par) return set_error(WD_ERR_ARG, "NULL argument");
+    WD_HIP(hipSetDevice(c->device));
+    hipError_t e = debug_tables(c->g, nb, cb, par, c->stream);
+    if (e != hipSuccess) return set_error(WD_ERR_HIP, "debug tables: %s", hipGetErrorString(e));
+    return WD_OK;
+}
+
+wd_status wd_timing_enable(wd_ctx *c, int on)
+{
+    if (!c) return set_error(WD_ERR_ARG, "NULL context");
+    WD_HIP(hipStreamSynchronize(c->stream));
+    c->timing = on != 0;
+    c->ev_used = 0;
+    c->t_bytes = 0;
+    c->t_ms = 0;
+    c->t_launches = 0;
+    return WD_OK;
+}
+
+wd_status wd_timing_read(wd_ctx *c, double *total_ms, int64_t *launches, double *bytes)
+{
+    if (!c) return set_error(WD_ERR_ARG, "NULL context");
+    WD_HIP(hipStreamSynchronize(c->stream));
+    double ms = 0;
+    for (size_t k = 0; k < c->ev_used; k++) {
+        float t = 0;
+        WD_HIP(hipEventElapsedTime(&t, c->events[k].first, c->events[k].second));
+        ms += t;
+    }
+    if (total_ms) *total_ms = ms;
+    if (launches) *launches = c->t_launches;
+    if (bytes) *bytes = c->t_bytes;
+    c->ev_used = 0;
+    c->t_bytes = 0;
+    c->t_launches = 0;
+    return WD_OK;
+}
+
+size_t wd_bytes_required(const int32_t dims[4], int nrhs, const wd_solver_params *p)
+{
+    long long V;
+    if (check_dims(dims, &V) != WD_OK || nrhs < 0) return 0;
+    wd_solver_params d;
+    wd_solver_defaults(&d);
+    if (!p) p = &d;
+    const size_t Vh = (size_t)V / 2;
+    size_t links = (144 + 48 + 24) * 4 * (size_t)V;
+    const int sp = p->prec_sloppy & 0xf;
+    const size_t nsub = p->eo ? 1 : 2;
+    // FP64: b, x, r, two temporaries and Ap
+    size_t f64 = 6 * 192 * Vh * nsub;
+    size_t sl = 0;
+    if (sp != WD_F64) sl = 4 * spinor_site_bytes(sp == WD_F32 ? SP_F32 : SP_F16) * Vh * nsub + 96 * Vh * nsub;
+    return links + (size_t)nrhs * (f64 + sl) + (size_t)nrhs * 4096;
+}
+
+}  // extern "C"

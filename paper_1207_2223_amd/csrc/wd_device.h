@@ -1,0 +1,380 @@
+// wd_device.h -- device-side building blocks of the gfx950 stencil kernels:
+// lattice index arithmetic, per-precision spinor and link storage, the spin
+// projections of (1 +- gamma_mu) and the SU(3) matrix-vector products.
+//
+// Internal storage (structure of arrays, one parity "subfield" at a time):
+//   spinor F64: double2 [12][Vh]          (complex component k = 3*spin + colour)
+//   spinor F32: float4  [6][Vh]           (reals 4k..4k+3 of the 24)
+//   spinor F16: half8   [3][Vh] + float [Vh] norm  (reals 8k..8k+7, times norm)
+//   links  L64_18: double2 [9][Vh], L64_12: double2 [6][Vh],
+//          L32_12: float4 [3][Vh],  L16_12: half4 [3][Vh]
+//          per (parity, mu) block, blocks ordered (parity*4 + mu).
+// Consecutive threads take consecutive checkerboard sites, so every load
+// and store of a wavefront is one contiguous 1 KiB (16 B per lane) segment.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace wd {
+
+enum { SP_F64 = 0, SP_F32 = 1, SP_F16 = 2 };
+enum { LK_F64_18 = 0, LK_F64_12 = 1, LK_F32_12 = 2, LK_F16_12 = 3 };
+
+typedef _Float16 half8_t __attribute__((ext_vector_type(8)));
+typedef _Float16 half4_t __attribute__((ext_vector_type(4)));
+
+struct Geom {
+    int L[4];
+    int Vh;
+    int Lxh;          // Lx / 2
+    int sy, sz, st;   // checkerboard strides of y, z, t: Lxh, Lxh*Ly, Lxh*Ly*Lz
+};
+
+// Coordinates of checkerboard site i of parity P.  Because Lx is even,
+// cb = (x >> 1) + Lxh * (y + Ly*(z + Lz*t)) and x's low bit follows from
+// the parity.
+__device__ __forceinline__ void site_coords(const Geom &g, int i, int P, int c[4])
+{
+    int q = i / g.Lxh;
+    int x0 = 2 * (i - q * g.Lxh);
+    int y = q % g.L[1];
+    int zt = q / g.L[1];
+    int z = zt % g.L[2];
+    int t = zt / g.L[2];
+    c[0] = x0 + ((P + y + z + t) & 1);
+    c[1] = y;
+    c[2] = z;
+    c[3] = t;
+}
+
+// Checkerboard index of the neighbour x +- mu of site i with coordinates c
+// (periodic wrap).  The neighbour has the other parity.
+template <int MU, int DIR>
+__device__ __forceinline__ int neighbour(const Geom &g, int i, const int c[4])
+{
+    int L = g.L[MU];
+    int v = c[MU] + DIR;
+    v = (v == L) ? 0 : ((v < 0) ? L - 1 : v);
+    if (MU == 0) return i - (c[0] >> 1) + (v >> 1);
+    const int s = (MU == 1) ? g.sy : ((MU == 2) ? g.sz : g.st);
+    return i + (v - c[MU]) * s;
+}
+
+// ---------------------------------------------------------------------------
+// Spinor storage
+// ---------------------------------------------------------------------------
+template <int SP> struct SpinorIO;
+
+template <> struct SpinorIO<SP_F64> {
+    typedef double real;
+    static constexpr size_t site_bytes = 192;
+    template <typename T>
+    __device__ static __forceinline__ void load(const char *f, int Vh, int i, T v[24])
+    {
+        const double2 *p = reinterpret_cast<const double2 *>(f);
+#pragma unroll
+        for (int k = 0; k < 12; k++) {
+            double2 w = p[(size_t)k * Vh + i];
+            v[2 * k] = (T)w.x;
+            v[2 * k + 1] = (T)w.y;
+        }
+    }
+    template <typename T>
+    __device__ static __forceinline__ void store(char *f, int Vh, int i, const T v[24])
+    {
+        double2 *p = reinterpret_cast<double2 *>(f);
+#pragma unroll
+        for (int k = 0; k < 12; k++) p[(size_t)k * Vh + i] = make_double2((double)v[2 * k], (double)v[2 * k + 1]);
+    }
+};
+
+template <> struct SpinorIO<SP_F32> {
+    typedef float real;
+    static constexpr size_t site_bytes = 96;
+    template <typename T>
+    __device__ static __forceinline__ void load(const char *f, int Vh, int i, T v[24])
+    {
+        const float4 *p = reinterpret_cast<const float4 *>(f);
+#pragma unroll
+        for (int k = 0; k < 6; k++) {
+            float4 w = p[(size_t)k * Vh + i];
+            v[4 * k] = (T)w.x;
+            v[4 * k + 1] = (T)w.y;
+            v[4 * k + 2] = (T)w.z;
+            v[4 * k + 3] = (T)w.w;
+        }
+    }
+    template <typename T>
+    __device__ static __forceinline__ void store(char *f, int Vh, int i, const T v[24])
+    {
+        float4 *p = reinterpret_cast<float4 *>(f);
+#pragma unroll
+        for (int k = 0; k < 6; k++)
+            p[(size_t)k * Vh + i] = make_float4((float)v[4 * k], (float)v[4 * k + 1], (float)v[4 * k + 2],
+                                                (float)v[4 * k + 3]);
+    }
+};
+
+// FP16 with a per-site FP32 norm: stored value = v / n rounded to nearest
+// even, n = max |v| over the 24 reals of the site; a zero site stores n = 0.
+template <> struct SpinorIO<SP_F16> {
+    typedef float real;
+    static constexpr size_t site_bytes = 52;
+    template <typename T>
+    __device__ static __forceinline__ void load(const char *f, int Vh, int i, T v[24])
+    {
+        const half8_t *p = reinterpret_cast<const half8_t *>(f);
+        const float n = reinterpret_cast<const float *>(f + (size_t)48 * Vh)[i];
+#pragma unroll
+        for (int k = 0; k < 3; k++) {
+            half8_t w = p[(size_t)k * Vh + i];
+#pragma unroll
+            for (int j = 0; j < 8; j++) v[8 * k + j] = (T)((float)w[j] * n);
+        }
+    }
+    template <typename T>
+    __device__ static __forceinline__ void store(char *f, int Vh, int i, const T v[24])
+    {
+        float m = 0.f;
+#pragma unroll
+        for (int j = 0; j < 24; j++) m = fmaxf(m, fabsf((float)v[j]));
+        const float inv = (m > 0.f) ? 1.0f / m : 0.f;
+        half8_t *p = reinterpret_cast<half8_t *>(f);
+#pragma unroll
+        for (int k = 0; k < 3; k++) {
+            half8_t w;
+#pragma unroll
+            for (int j = 0; j < 8; j++) w[j] = (_Float16)((float)v[8 * k + j] * inv);
+            p[(size_t)k * Vh + i] = w;
+        }
+        reinterpret_cast<float *>(f + (size_t)48 * Vh)[i] = m;
+    }
+};
+
+__host__ __device__ constexpr size_t spinor_site_bytes(int sp)
+{
+    return sp == SP_F64 ? 192 : (sp == SP_F32 ? 96 : 52);
+}
+
+// ---------------------------------------------------------------------------
+// Link storage.  u[18] holds U row-major: u[2*(3a+b)] = Re U_ab, +1 = Im.
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ void reconstruct_row3(T u[18])
+{
+    // row 3 = conj(row1 x row2), exact for SU(3)
+#define RE(a, b) u[2 * (3 * (a) + (b))]
+#define IM(a, b) u[2 * (3 * (a) + (b)) + 1]
+#pragma unroll
+    for (int j = 0; j < 3; j++) {
+        const int k = (j + 1) % 3, l = (j + 2) % 3;
+        // (row1 x row2)_j = u0k u1l - u0l u1k
+        T re = RE(0, k) * RE(1, l) - IM(0, k) * IM(1, l) - (RE(0, l) * RE(1, k) - IM(0, l) * IM(1, k));
+        T im = RE(0, k) * IM(1, l) + IM(0, k) * RE(1, l) - (RE(0, l) * IM(1, k) + IM(0, l) * RE(1, k));
+        RE(2, j) = re;
+        IM(2, j) = -im;
+    }
+#undef RE
+#undef IM
+}
+
+template <int LK> struct LinkIO;
+
+template <> struct LinkIO<LK_F64_18> {
+    typedef double real;
+    static constexpr int nchunk = 9;
+    static constexpr size_t chunk_bytes = 16;
+    __device__ static __forceinline__ void load(const char *U, int Vh, int blk, int i, double u[18])
+    {
+        const double2 *p = reinterpret_cast<const double2 *>(U) + (size_t)blk * 9 * Vh;
+#pragma unroll
+        for (int k = 0; k < 9; k++) {
+            double2 w = p[(size_t)k * Vh + i];
+            u[2 * k] = w.x;
+            u[2 * k + 1] = w.y;
+        }
+    }
+};
+
+template <> struct LinkIO<LK_F64_12> {
+    typedef double real;
+    static constexpr int nchunk = 6;
+    static constexpr size_t chunk_bytes = 16;
+    __device__ static __forceinline__ void load(const char *U, int Vh, int blk, int i, double u[18])
+    {
+        const double2 *p = reinterpret_cast<const double2 *>(U) + (size_t)blk * 6 * Vh;
+#pragma unroll
+        for (int k = 0; k < 6; k++) {
+            double2 w = p[(size_t)k * Vh + i];
+            u[2 * k] = w.x;
+            u[2 * k + 1] = w.y;
+        }
+        reconstruct_row3(u);
+    }
+};
+
+template <> struct LinkIO<LK_F32_12> {
+    typedef float real;
+    static constexpr int nchunk = 3;
+    static constexpr size_t chunk_bytes = 16;
+    __device__ static __forceinline__ void load(const char *U, int Vh, int blk, int i, float u[18])
+    {
+        const float4 *p = reinterpret_cast<const float4 *>(U) + (size_t)blk * 3 * Vh;
+#pragma unroll
+        for (int k = 0; k < 3; k++) {
+            float4 w = p[(size_t)k * Vh + i];
+            u[4 * k] = w.x;
+            u[4 * k + 1] = w.y;
+            u[4 * k + 2] = w.z;
+            u[4 * k + 3] = w.w;
+        }
+        reconstruct_row3(u);
+    }
+};
+
+template <> struct LinkIO<LK_F16_12> {
+    typedef float real;
+    static constexpr int nchunk = 3;
+    static constexpr size_t chunk_bytes = 8;
+    __device__ static __forceinline__ void load(const char *U, int Vh, int blk, int i, float u[18])
+    {
+        const half4_t *p = reinterpret_cast<const half4_t *>(U) + (size_t)blk * 3 * Vh;
+#pragma unroll
+        for (int k = 0; k < 3; k++) {
+            half4_t w = p[(size_t)k * Vh + i];
+#pragma unroll
+            for (int j = 0; j < 4; j++) u[4 * k + j] = (float)w[j];
+        }
+        reconstruct_row3(u);
+    }
+};
+
+__host__ __device__ constexpr size_t link_bytes(int lk)
+{
+    return lk == LK_F64_18 ? 144 : (lk == LK_F64_12 ? 96 : (lk == LK_F32_12 ? 48 : 24));
+}
+
+// ---------------------------------------------------------------------------
+// Spin projection.  (1 + S g_mu) psi has only two independent spin rows
+// (h0, h1); rows 2 and 3 are fixed multiples of them.  Derived from the
+// chiral-basis gamma matrices:
+//   mu=x: h0 = p0 + S i p3, h1 = p1 + S i p2;  row2 = -S i h1, row3 = -S i h0
+//   mu=y: h0 = p0 - S p3,   h1 = p1 + S p2;    row2 =  S h1,   row3 = -S h0
+//   mu=z: h0 = p0 + S i p2, h1 = p1 - S i p3;  row2 = -S i h0, row3 =  S i h1
+//   mu=t: h0 = p0 + S p2,   h1 = p1 + S p3;    row2 =  S h0,   row3 =  S h1
+// v[24]: spin s colour c re/im at 6s + 2c (+1); h[12]: h0 at 0..5, h1 at 6..11.
+// ---------------------------------------------------------------------------
+template <int MU, int S, typename T>
+__device__ __forceinline__ void project(const T v[24], T h[12])
+{
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        const T p0r = v[2 * c], p0i = v[2 * c + 1];
+        const T p1r = v[6 + 2 * c], p1i = v[6 + 2 * c + 1];
+        const T p2r = v[12 + 2 * c], p2i = v[12 + 2 * c + 1];
+        const T p3r = v[18 + 2 * c], p3i = v[18 + 2 * c + 1];
+        if (MU == 0) {  // + S i p3 ; + S i p2      (i*(a+ib) = -b + ia)
+            h[2 * c] = p0r - S * p3i;
+            h[2 * c + 1] = p0i + S * p3r;
+            h[6 + 2 * c] = p1r - S * p2i;
+            h[6 + 2 * c + 1] = p1i + S * p2r;
+        } else if (MU == 1) {
+            h[2 * c] = p0r - S * p3r;
+            h[2 * c + 1] = p0i - S * p3i;
+            h[6 + 2 * c] = p1r + S * p2r;
+            h[6 + 2 * c + 1] = p1i + S * p2i;
+        } else if (MU == 2) {  // + S i p2 ; - S i p3
+            h[2 * c] = p0r - S * p2i;
+            h[2 * c + 1] = p0i + S * p2r;
+            h[6 + 2 * c] = p1r + S * p3i;
+            h[6 + 2 * c + 1] = p1i - S * p3r;
+        } else {
+            h[2 * c] = p0r + S * p2r;
+            h[2 * c + 1] = p0i + S * p2i;
+            h[6 + 2 * c] = p1r + S * p3r;
+            h[6 + 2 * c + 1] = p1i + S * p3i;
+        }
+    }
+}
+
+// acc += full 4-spinor rebuilt from the colour-rotated half spinor w.
+template <int MU, int S, typename T>
+__device__ __forceinline__ void accumulate(T acc[24], const T w[12])
+{
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        const T a0r = w[2 * c], a0i = w[2 * c + 1];
+        const T a1r = w[6 + 2 * c], a1i = w[6 + 2 * c + 1];
+        acc[2 * c] += a0r;
+        acc[2 * c + 1] += a0i;
+        acc[6 + 2 * c] += a1r;
+        acc[6 + 2 * c + 1] += a1i;
+        if (MU == 0) {  // row2 = -S i h1, row3 = -S i h0    (-S i (a+ib) = S b - S i a)
+            acc[12 + 2 * c] += S * a1i;
+            acc[12 + 2 * c + 1] -= S * a1r;
+            acc[18 + 2 * c] += S * a0i;
+            acc[18 + 2 * c + 1] -= S * a0r;
+        } else if (MU == 1) {  // row2 = S h1, row3 = -S h0
+            acc[12 + 2 * c] += S * a1r;
+            acc[12 + 2 * c + 1] += S * a1i;
+            acc[18 + 2 * c] -= S * a0r;
+            acc[18 + 2 * c + 1] -= S * a0i;
+        } else if (MU == 2) {  // row2 = -S i h0, row3 = S i h1
+            acc[12 + 2 * c] += S * a0i;
+            acc[12 + 2 * c + 1] -= S * a0r;
+            acc[18 + 2 * c] -= S * a1i;
+            acc[18 + 2 * c + 1] += S * a1r;
+        } else {  // row2 = S h0, row3 = S h1
+            acc[12 + 2 * c] += S * a0r;
+            acc[12 + 2 * c + 1] += S * a0i;
+            acc[18 + 2 * c] += S * a1r;
+            acc[18 + 2 * c + 1] += S * a1i;
+        }
+    }
+}
+
+// w = U h for both half-spinor rows (h, w: 12 reals), or U^dag h.
+template <bool ADJ, typename T>
+__device__ __forceinline__ void su3_mul_half(const T u[18], const T h[12], T w[12])
+{
+#pragma unroll
+    for (int r = 0; r < 2; r++) {
+#pragma unroll
+        for (int a = 0; a < 3; a++) {
+            T re = 0, im = 0;
+#pragma unroll
+            for (int b = 0; b < 3; b++) {
+                const int idx = ADJ ? 2 * (3 * b + a) : 2 * (3 * a + b);
+                const T ur = u[idx], ui = ADJ ? -u[idx + 1] : u[idx + 1];
+                const T hr = h[6 * r + 2 * b], hi = h[6 * r + 2 * b + 1];
+                re += ur * hr - ui * hi;
+                im += ur * hi + ui * hr;
+            }
+            w[6 * r + 2 * a] = re;
+            w[6 * r + 2 * a + 1] = im;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Block-to-tile mapping.  Work-groups are dispatched round-robin over the
+// 8 XCDs (each with its own L2); remapping gives each XCD a contiguous run
+// of tiles so that neighbouring lattice slabs share one L2.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int xcd_remap(int b, int nb)
+{
+    const int q = nb >> 3, rm = nb & 7;
+    const int x = b & 7, j = b >> 3;
+    return x * q + (x < rm ? x : rm) + j;
+}
+
+// Deterministic wavefront sum (fixed butterfly order).
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+}  // namespace wd

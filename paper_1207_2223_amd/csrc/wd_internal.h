@@ -1,0 +1,181 @@
+// wd_internal.h -- host-side internals shared by the library's translation
+// units: the context, field descriptors, kernel argument blocks, launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/wd.h"
+#include "wd_device.h"
+
+namespace wd {
+
+wd_status set_error(wd_status st, const char *fmt, ...);
+
+#define WD_HIP(call)                                                                              \
+    do {                                                                                          \
+        hipError_t e_ = (call);                                                                   \
+        if (e_ != hipSuccess)                                                                     \
+            return ::wd::set_error(WD_ERR_HIP, "%s failed: %s (%s:%d)", #call,                   \
+                                   hipGetErrorString(e_), __FILE__, __LINE__);                    \
+    } while (0)
+
+#define WD_TRY(expr)                                                                              \
+    do {                                                                                          \
+        wd_status s_ = (expr);                                                                    \
+        if (s_ != WD_OK) return s_;                                                               \
+    } while (0)
+
+enum { EPI_PLAIN = 0, EPI_XPAY = 1, EPI_CGUPD = 2 };
+
+// A batch of spinor fields of one precision: RHS id r, parity subfield s
+// starts at base + r*rs + s*ss.  nsub = 1 (one parity) or 2 (full lattice).
+struct Field {
+    char *base = nullptr;
+    long long rs = 0;
+    long long ss = 0;
+    int sp = SP_F64;
+    int nsub = 1;
+    char *sub(int rid, int s) const { return base + rid * rs + s * ss; }
+};
+
+// Stencil kernel arguments (passed by value).
+struct DslashArgs {
+    Geom g;
+    int P;                 // output parity
+    const char *links;
+    const char *in;        // input subfield of RHS 0 (parity 1-P)
+    long long in_rs;
+    char *out;             // output subfield of RHS 0 (parity P)
+    long long out_rs;
+    const char *x;         // xpay: out = x + coef*D in
+    long long x_rs;
+    const double *coef;    // [rid]
+    const char *p;         // CG update: xs += alpha p, r -= alpha (x + coef*D in)
+    long long p_rs;
+    char *xs;
+    long long xs_rs;
+    char *r;
+    long long r_rs;
+    const double *alpha;   // [rid]
+    const int *active;     // RHS ids processed by this launch
+    int nact;
+    int G;                 // RHS groups of NR per tile
+    int remap;             // XCD-aware tile order
+    double *partial;       // partial[rid*pstride + pw_off + wave] = sum |out|^2 (or |r|^2)
+    int pstride;
+    int pw_off;
+};
+
+struct TuneCfg {
+    int block = 128;
+    int nr = 1;
+    int remap = 1;
+};
+
+hipError_t dslash_launch_f64(const DslashArgs &a, int lk, int nr, int dag, int epi, int block,
+                             int grid, hipStream_t s);
+hipError_t dslash_launch_f32(const DslashArgs &a, int lk, int nr, int dag, int epi, int block,
+                             int grid, hipStream_t s);
+hipError_t dslash_launch_f16(const DslashArgs &a, int lk, int nr, int dag, int epi, int block,
+                             int grid, hipStream_t s);
+
+// BLAS-1 / reductions (blas.hip).  All take an active-RHS list.
+enum { FIN_STORE = 0, FIN_ALPHA = 1, FIN_BETA = 2, FIN_RR = 3 };
+hipError_t blas_norm(const Field &a, int Vh, const int *active, int nact, double *partial,
+                     int pstride, hipStream_t s);
+hipError_t blas_p_update(const Field &p, const Field &r, const double *beta, int Vh,
+                         const int *active, int nact, hipStream_t s);
+hipError_t blas_cg_update(const Field &x, const Field &p, const Field &r, const Field &Ap,
+                          const double *alpha, int Vh, const int *active, int nact,
+                          double *partial, int pstride, hipStream_t s);
+hipError_t blas_copy(const Field &dst, const Field &src, int Vh, const int *active, int nact,
+                     hipStream_t s);
+hipError_t blas_add_zero(const Field &xhi, const Field &xs, int Vh, const int *active, int nact,
+                         hipStream_t s);
+hipError_t blas_resid(const Field &r, const Field &b, const Field &Ap, int Vh, const int *active,
+                      int nact, double *partial, int pstride, hipStream_t s);
+hipError_t blas_zero(const Field &a, int Vh, const int *active, int nact, hipStream_t s);
+hipError_t blas_finalize(const double *partial, int pstride, int nw, const int *active, int nact,
+                         int mode, double *rr, double *alpha, double *beta, double *out,
+                         hipStream_t s);
+inline int nwaves_of(int nsites) { return (nsites + 63) / 64; }
+
+// Packing between the canonical complex128 layouts and the internal ones (pack.hip).
+hipError_t pack_gauge(const double *U, char *dst, int lk, const Geom &g, hipStream_t s);
+// mode 0: src/dst are parity fields ([Vh][4][3] cb order <-> one subfield);
+// mode 1: full fields ([V][4][3] lex order <-> two subfields).
+hipError_t pack_spinor(const double *src, const Field &dst, int nrhs, int mode, const Geom &g,
+                       hipStream_t s);
+hipError_t unpack_spinor(const Field &src, double *dst, int nrhs, int mode, const Geom &g,
+                         hipStream_t s);
+hipError_t debug_tables(const Geom &g, int32_t *nb, int32_t *cb, uint8_t *par, hipStream_t s);
+
+}  // namespace wd
+
+// The context: one lattice on one device.
+struct wd_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    int dims[4] = {0, 0, 0, 0};
+    long long V = 0, Vh = 0;
+    wd::Geom g{};
+
+    bool have_gauge = false;
+    int lk64 = wd::LK_F64_18;
+    char *links64 = nullptr;
+    char *links32 = nullptr;
+    char *links16 = nullptr;
+
+    // named, growable device workspaces
+    std::map<std::string, std::pair<void *, size_t>> ws;
+    void *pinned[2] = {nullptr, nullptr};   // [0] uploads, [1] downloads
+    size_t pinned_bytes[2] = {0, 0};
+
+    // stencil timing
+    bool timing = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
+    size_t ev_used = 0;
+    double t_bytes = 0;
+    double t_ms = 0;
+    long long t_launches = 0;
+
+    // launch shapes chosen by the autotuner, keyed by kernel description
+    std::map<std::string, wd::TuneCfg> tuned;
+};
+
+namespace wd {
+
+wd_status ws_get(wd_ctx *c, const std::string &name, size_t bytes, void **ptr);
+wd_status pinned_get(wd_ctx *c, int slot, size_t bytes, void **ptr);
+wd_status alloc_field(wd_ctx *c, const std::string &name, int sp, int nsub, int nrhs, Field *f);
+const char *link_ptr(const wd_ctx *c, int lk);
+
+// One stencil sweep over the active RHS (dispatch + optional timing).
+struct Sweep {
+    int sp = SP_F64;
+    int lk = LK_F64_18;
+    int xp = SP_F64;
+    int dag = 0;
+    int epi = EPI_PLAIN;
+    int P = 0;
+    Field in, out, x, p, xs, r;
+    const double *coef = nullptr;
+    const double *alpha = nullptr;
+    const int *active = nullptr;
+    int nact = 0;
+    double *partial = nullptr;
+    int pstride = 0;
+    int pw_off = 0;
+};
+wd_status run_sweep(wd_ctx *c, const Sweep &sw, const TuneCfg *cfg);
+wd_status upload_doubles(wd_ctx *c, const std::string &name, const double *v, int n, double **dev);
+wd_status upload_ints(wd_ctx *c, const std::string &name, const int *v, int n, int **dev);
+Field sub_view(const Field &f, int s);
+TuneCfg default_cfg(int sp);
+double sweep_bytes(const wd_ctx *c, const Sweep &sw);
+
+}  // namespace wd

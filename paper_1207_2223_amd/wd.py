@@ -1,0 +1,264 @@
+"""Thin ctypes binding of libwd.so (the C-ABI declared in include/wd.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+library.  Functions keep the C names (wd_create, wd_dslash, wd_cg_solve, ...)
+and take torch CUDA tensors where the C-ABI takes device pointers.  If the
+library has not been built, loading fails loudly; there is no fallback.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libwd.so")
+
+WD_OK, WD_ERR_ARG, WD_ERR_DIMS, WD_ERR_OOM, WD_ERR_HIP, WD_ERR_NOCONV, WD_ERR_NAN, WD_ERR_STATE = (
+    0, -1, -2, -3, -4, -5, -6, -7)
+WD_F64, WD_F32, WD_F16 = 0, 1, 2
+WD_LINKS_F16 = 0x10
+WD_FULL, WD_EVEN, WD_ODD = 0, 1, 2
+WD_RECON_18, WD_RECON_12 = 0, 1
+
+STATUS_NAMES = {0: "WD_OK", -1: "WD_ERR_ARG", -2: "WD_ERR_DIMS", -3: "WD_ERR_OOM", -4: "WD_ERR_HIP",
+                -5: "WD_ERR_NOCONV", -6: "WD_ERR_NAN", -7: "WD_ERR_STATE"}
+
+
+class WDError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class wd_solver_params(C.Structure):
+    _fields_ = [("tol", C.c_double), ("maxiter", C.c_int), ("prec_sloppy", C.c_int),
+                ("eo", C.c_int), ("delta", C.c_double), ("poll", C.c_int), ("tuned", C.c_int)]
+
+
+class wd_solver_stats(C.Structure):
+    _fields_ = [("iters", C.c_int), ("reliable_updates", C.c_int), ("true_resid", C.c_double),
+                ("seconds", C.c_double), ("status", C.c_int)]
+
+
+_P = C.c_void_p
+_I32x4 = C.c_int32 * 4
+_SIGS = {
+    "wd_solver_defaults": (None, [C.POINTER(wd_solver_params)]),
+    "wd_create": (C.c_int, [C.POINTER(_P), _I32x4, C.c_int, _P]),
+    "wd_destroy": (C.c_int, [_P]),
+    "wd_set_stream": (C.c_int, [_P, _P]),
+    "wd_gauge_load": (C.c_int, [_P, _P, C.c_uint32]),
+    "wd_dslash": (C.c_int, [_P, _P, _P, C.c_int, C.c_int, C.c_int]),
+    "wd_mdagm": (C.c_int, [_P, _P, _P, C.c_double, C.c_int]),
+    "wd_cg_solve": (C.c_int, [_P, _P, _P, C.c_int, C.POINTER(C.c_double),
+                              C.POINTER(wd_solver_params), C.POINTER(wd_solver_stats)]),
+    "wd_index_tables": (C.c_int, [_I32x4, _P, _P, _P]),
+    "wd_debug_device_tables": (C.c_int, [_P, _P, _P, _P]),
+    "wd_bytes_required": (C.c_size_t, [_I32x4, C.c_int, C.POINTER(wd_solver_params)]),
+    "wd_timing_enable": (C.c_int, [_P, C.c_int]),
+    "wd_timing_read": (C.c_int, [_P, C.POINTER(C.c_double), C.POINTER(C.c_int64),
+                                 C.POINTER(C.c_double)]),
+    "wd_last_error": (C.c_char_p, []),
+    "wd_version": (C.c_char_p, []),
+}
+
+_LIB = None
+
+
+def lib():
+    """Load libwd.so (built by paper_1207_2223_amd/build.py); raise if absent."""
+    global _LIB
+    if _LIB is None:
+        # torch ships its own HIP runtime (SONAME libamdhip64.so.7).  Loading it
+        # first makes libwd bind to that same runtime, so device pointers and
+        # streams from torch are valid inside the library: one runtime per
+        # process.
+        import torch  # noqa: F401
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with paper_1207_2223_amd/build.py "
+                              "(no CPU fallback exists)")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _LIB = L
+    return _LIB
+
+
+def _check(status):
+    if status != WD_OK:
+        raise WDError(status, lib().wd_last_error().decode())
+    return status
+
+
+def _dims(dims):
+    return _I32x4(*[int(v) for v in dims])
+
+
+def _ptr(t):
+    """Device pointer of a contiguous CUDA tensor."""
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("expected a CUDA (HIP) tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream_handle(stream):
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _c128(t, shape_tail, name):
+    import torch
+    if t.dtype != torch.complex128:
+        raise ValueError(f"{name} must be complex128")
+    if tuple(t.shape[-len(shape_tail):]) != tuple(shape_tail):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected [..., {shape_tail}]")
+    return t
+
+
+# ---------------------------------------------------------------------------
+# C-ABI calls under their C names
+# ---------------------------------------------------------------------------
+
+def wd_solver_defaults():
+    p = wd_solver_params()
+    lib().wd_solver_defaults(C.byref(p))
+    return p
+
+
+def wd_create(dims, device=0, stream=None):
+    h = C.c_void_p()
+    _check(lib().wd_create(C.byref(h), _dims(dims), int(device), _stream_handle(stream)))
+    return h
+
+
+def wd_destroy(ctx):
+    _check(lib().wd_destroy(ctx))
+
+
+def wd_set_stream(ctx, stream=None):
+    _check(lib().wd_set_stream(ctx, _stream_handle(stream)))
+
+
+def wd_gauge_load(ctx, U, flags=WD_RECON_18):
+    _c128(U, (4, 3, 3), "U")
+    _check(lib().wd_gauge_load(ctx, _ptr(U), int(flags)))
+
+
+def wd_dslash(ctx, out, inp, out_parity, dagger=0, prec=WD_F64):
+    _c128(out, (4, 3), "out")
+    _c128(inp, (4, 3), "in")
+    _check(lib().wd_dslash(ctx, _ptr(out), _ptr(inp), int(out_parity), int(dagger), int(prec)))
+
+
+def wd_mdagm(ctx, out, inp, kappa, eo=1):
+    _c128(out, (4, 3), "out")
+    _c128(inp, (4, 3), "in")
+    _check(lib().wd_mdagm(ctx, _ptr(out), _ptr(inp), float(kappa), int(eo)))
+
+
+def wd_cg_solve(ctx, x, phi, kappa, params=None, check=True):
+    """x, phi: complex128 [nrhs, sites, 4, 3] (or [sites, 4, 3]); kappa: float
+    or sequence of nrhs floats.  Returns (status, list of stats dicts)."""
+    _c128(x, (4, 3), "x")
+    _c128(phi, (4, 3), "phi")
+    nrhs = 1 if phi.dim() == 3 else phi.shape[0]
+    ks = [float(kappa)] * nrhs if np.isscalar(kappa) else [float(k) for k in kappa]
+    if len(ks) != nrhs:
+        raise ValueError("one kappa per right-hand side")
+    karr = (C.c_double * nrhs)(*ks)
+    p = params if params is not None else wd_solver_defaults()
+    st = (wd_solver_stats * nrhs)()
+    status = lib().wd_cg_solve(ctx, _ptr(x), _ptr(phi), nrhs, karr, C.byref(p), st)
+    if check and status not in (WD_OK, WD_ERR_NOCONV, WD_ERR_NAN):
+        _check(status)
+    stats = [dict(iters=s.iters, reliable_updates=s.reliable_updates, true_resid=s.true_resid,
+                  seconds=s.seconds, status=s.status) for s in st]
+    return status, stats
+
+
+def wd_index_tables(dims):
+    V = int(np.prod(dims))
+    nb = np.zeros((V, 8), np.int32)
+    cb = np.zeros(V, np.int32)
+    par = np.zeros(V, np.uint8)
+    _check(lib().wd_index_tables(_dims(dims), nb.ctypes.data_as(_P), cb.ctypes.data_as(_P),
+                                 par.ctypes.data_as(_P)))
+    return nb, cb, par
+
+
+def wd_debug_device_tables(ctx, nb, cb, par):
+    _check(lib().wd_debug_device_tables(ctx, _ptr(nb), _ptr(cb), _ptr(par)))
+
+
+def wd_bytes_required(dims, nrhs, params=None):
+    p = C.byref(params) if params is not None else None
+    return int(lib().wd_bytes_required(_dims(dims), int(nrhs), p))
+
+
+def wd_timing_enable(ctx, on=True):
+    _check(lib().wd_timing_enable(ctx, int(bool(on))))
+
+
+def wd_timing_read(ctx):
+    ms = C.c_double()
+    n = C.c_int64()
+    b = C.c_double()
+    _check(lib().wd_timing_read(ctx, C.byref(ms), C.byref(n), C.byref(b)))
+    return ms.value, n.value, b.value
+
+
+def wd_last_error():
+    return lib().wd_last_error().decode()
+
+
+def wd_version():
+    return lib().wd_version().decode()
+
+
+def solver_params(tol=1e-10, maxiter=20000, prec=WD_F64, eo=1, delta=0.1, poll=8, tuned=0):
+    p = wd_solver_defaults()
+    p.tol, p.maxiter, p.prec_sloppy, p.eo, p.delta, p.poll, p.tuned = (
+        float(tol), int(maxiter), int(prec), int(eo), float(delta), int(poll), int(tuned))
+    return p
+
+
+class Lattice:
+    """A context for one lattice (owns the packed gauge field)."""
+
+    def __init__(self, dims, device=0, stream=None):
+        self.dims = tuple(int(d) for d in dims)
+        self.V = int(np.prod(self.dims))
+        self.Vh = self.V // 2
+        self.device = device
+        self.ctx = wd_create(self.dims, device, stream)
+
+    def close(self):
+        if self.ctx is not None:
+            wd_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def gauge_load(self, U, recon=18):
+        wd_gauge_load(self.ctx, U, WD_RECON_12 if recon == 12 else WD_RECON_18)
+
+    def dslash(self, out, inp, out_parity, dagger=0, prec=WD_F64):
+        wd_dslash(self.ctx, out, inp, out_parity, dagger, prec)
+
+    def mdagm(self, out, inp, kappa, eo=1):
+        wd_mdagm(self.ctx, out, inp, kappa, eo)
+
+    def cg_solve(self, x, phi, kappa, params=None, check=True):
+        return wd_cg_solve(self.ctx, x, phi, kappa, params, check)

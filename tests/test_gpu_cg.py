@@ -1,0 +1,110 @@
+"""GPU parity of the CG solves of M^dag M (eq. 3-4) against the oracle:
+FP64 full-lattice CG on the 4^4 workload, even-odd FP64 and mixed-precision
+solves judged by their true FP64 residual recomputed by the oracle, batched
+right-hand sides equal to single ones, and the failure statuses."""
+import numpy as np
+import pytest
+
+import lattice_inputs as li
+from gpu_util import dev, empty_like_dev, host, note, rel_err
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def wd():
+    from paper_1207_2223_amd import wd
+    wd.lib()
+    return wd
+
+
+def true_resid(oracle, dims, U, kappa, x, b, eo):
+    Ax = oracle.mhatdag_mhat(dims, U, kappa, x) if eo else oracle.mdagm(dims, U, kappa, x)
+    return np.linalg.norm(b - Ax) / np.linalg.norm(b)
+
+
+def test_full_lattice_fp64_4444(wd, oracle):
+    """4^4, eps = 0.3, kappa = 0.15, plain FP64 CG on M^dag M to 1e-10."""
+    dims = (4, 4, 4, 4)
+    V = li.volume(dims)
+    U = li.random_su3_field(dims, 0.3, seed=li.config_seed(0))
+    b = li.gaussian_spinor(V, seed=li.config_seed(0) + 1)
+    lat = wd.Lattice(dims)
+    lat.gauge_load(dev(U))
+    x = empty_like_dev(b)
+    st, stats = lat.cg_solve(x, dev(b), 0.15, wd.solver_params(eo=0))
+    xg = host(x)
+    assert st == wd.WD_OK and stats[0]["status"] == wd.WD_OK
+    tr = true_resid(oracle, dims, U, 0.15, xg, b, eo=False)
+    note(f"4^4 full fp64: iters {stats[0]['iters']} gpu resid {stats[0]['true_resid']:.3e} "
+         f"oracle-recomputed {tr:.3e}")
+    assert tr <= 1.01e-10 and stats[0]["true_resid"] <= 1e-10
+    xo, it, tro, ok = oracle.cg(dims, U, 0.15, b, eo=False, tol=1e-12)
+    assert rel_err(xg, xo) <= 1e-7
+    lat.close()
+
+
+@pytest.mark.parametrize("prec", ["F64", "F32", "F16", "F16L"])
+@pytest.mark.parametrize("dims", [(8, 8, 8, 8), (6, 4, 4, 6)])
+def test_even_odd_solves(wd, oracle, prec, dims):
+    code = {"F64": wd.WD_F64, "F32": wd.WD_F32, "F16": wd.WD_F16,
+            "F16L": wd.WD_F16 | wd.WD_LINKS_F16}[prec]
+    V = li.volume(dims)
+    kappa = 0.155
+    U = li.random_su3_field(dims, 0.5, seed=li.config_seed(1))
+    b = li.gaussian_spinor(V // 2, seed=11)
+    lat = wd.Lattice(dims)
+    lat.gauge_load(dev(U), recon=12)
+    x = empty_like_dev(b)
+    st, stats = lat.cg_solve(x, dev(b), kappa, wd.solver_params(prec=code))
+    xg = host(x)
+    tr = true_resid(oracle, dims, U, kappa, xg, b, eo=True)
+    note(f"{dims} eo {prec}: status {st} iters {stats[0]['iters']} RU {stats[0]['reliable_updates']} "
+         f"gpu {stats[0]['true_resid']:.3e} oracle {tr:.3e}")
+    assert st == wd.WD_OK
+    assert tr <= 1.01e-10
+    lat.close()
+
+
+@pytest.mark.parametrize("prec", ["F64", "F16"])
+def test_multi_rhs_equals_single(wd, prec):
+    dims = (6, 4, 4, 6)
+    code = {"F64": wd.WD_F64, "F16": wd.WD_F16}[prec]
+    V = li.volume(dims)
+    U = li.random_su3_field(dims, 0.5, seed=21)
+    B = li.gaussian_spinor(V // 2, seed=22, nrhs=3)
+    kappas = [0.14, 0.155, 0.157]
+    lat = wd.Lattice(dims)
+    lat.gauge_load(dev(U), recon=12)
+    X = empty_like_dev(B)
+    st, stats = lat.cg_solve(X, dev(B), kappas, wd.solver_params(prec=code))
+    assert st == wd.WD_OK
+    Xb = host(X)
+    for j in range(3):
+        x1 = empty_like_dev(B[j])
+        s1, st1 = lat.cg_solve(x1, dev(B[j]), kappas[j], wd.solver_params(prec=code))
+        assert s1 == wd.WD_OK
+        assert st1[0]["iters"] == stats[j]["iters"]
+        assert np.array_equal(host(x1), Xb[j]), j
+    lat.close()
+
+
+def test_noconv_and_nan_and_zero(wd):
+    dims = (4, 4, 4, 4)
+    V = li.volume(dims)
+    U = li.random_su3_field(dims, 0.5, seed=31)
+    lat = wd.Lattice(dims)
+    lat.gauge_load(dev(U))
+    B = li.gaussian_spinor(V // 2, seed=32, nrhs=3)
+    B[1] = 0
+    B[2, 5, 1, 2] = np.nan
+    X = empty_like_dev(B)
+    st, stats = lat.cg_solve(X, dev(B), 0.15, wd.solver_params(maxiter=3))
+    assert stats[0]["status"] == wd.WD_ERR_NOCONV and stats[0]["iters"] == 3
+    assert stats[1]["status"] == wd.WD_OK and stats[1]["iters"] == 0
+    assert stats[2]["status"] == wd.WD_ERR_NAN
+    assert st == wd.WD_ERR_NAN
+    Xh = host(X)
+    assert np.all(Xh[1] == 0)
+    assert np.all(np.isfinite(Xh[0]))
+    lat.close()

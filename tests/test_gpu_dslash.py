@@ -1,0 +1,143 @@
+"""GPU parity of the index arithmetic and the hopping stencil (Sec. 3 kernel 1
+and the neighbour routine) against the oracle: index tables bit-exact, FP64
+stencil to 1e-12 relative, FP32 / FP16 to their rounding level."""
+import numpy as np
+import pytest
+
+import lattice_inputs as li
+from gpu_util import dev, empty_like_dev, host, maxabs_ratio, note, rel_err
+
+pytestmark = pytest.mark.gpu
+
+DIMS = [(2, 2, 2, 2), (4, 4, 4, 4), (6, 4, 4, 6), (4, 6, 2, 8), (8, 8, 8, 8)]
+
+
+@pytest.fixture(scope="module")
+def wd():
+    from paper_1207_2223_amd import wd
+    wd.lib()
+    return wd
+
+
+@pytest.mark.parametrize("dims", DIMS + [(12, 12, 12, 24), (16, 16, 16, 32)])
+def test_device_tables_bit_exact(wd, oracle, dims):
+    import torch
+    note(f"device tables {dims}")
+    V = li.volume(dims)
+    lat = wd.Lattice(dims)
+    nb = torch.zeros((V, 8), dtype=torch.int32, device="cuda")
+    cb = torch.zeros(V, dtype=torch.int32, device="cuda")
+    par = torch.zeros(V, dtype=torch.uint8, device="cuda")
+    wd.wd_debug_device_tables(lat.ctx, nb, cb, par)
+    onb, ocb, opar, _ = oracle.index_tables(dims)
+    assert np.array_equal(host(nb), onb)
+    assert np.array_equal(host(cb), ocb)
+    assert np.array_equal(host(par), opar)
+    lat.close()
+
+
+@pytest.mark.parametrize("dims", DIMS)
+@pytest.mark.parametrize("recon", [18, 12])
+def test_dslash_fp64_parity_blocks(wd, oracle, dims, recon):
+    note(f"dslash fp64 {dims} recon {recon}")
+    V = li.volume(dims)
+    U = li.random_su3_field(dims, 0.5, seed=1001)
+    lat = wd.Lattice(dims)
+    lat.gauge_load(dev(U), recon=recon)
+    for out_par in (0, 1):
+        psi = li.gaussian_spinor(V // 2, seed=7 + out_par)
+        for dag in (0, 1):
+            ref = oracle.hop_eo(dims, U, psi, out_par, dagger=bool(dag))
+            out = empty_like_dev(psi)
+            lat.dslash(out, dev(psi), wd.WD_EVEN if out_par == 0 else wd.WD_ODD, dag, wd.WD_F64)
+            got = host(out)
+            assert rel_err(got, ref) <= 1e-12, (out_par, dag, rel_err(got, ref))
+            assert maxabs_ratio(got, ref) <= 1e-12
+    lat.close()
+
+
+@pytest.mark.parametrize("dims", [(4, 4, 4, 4), (6, 4, 4, 6)])
+def test_dslash_fp64_full_lattice(wd, oracle, dims):
+    V = li.volume(dims)
+    U = li.random_su3_field(dims, 0.5, seed=3)
+    psi = li.gaussian_spinor(V, seed=4)
+    lat = wd.Lattice(dims)
+    lat.gauge_load(dev(U))
+    for dag in (0, 1):
+        out = empty_like_dev(psi)
+        lat.dslash(out, dev(psi), wd.WD_FULL, dag, wd.WD_F64)
+        assert rel_err(host(out), oracle.hop(dims, U, psi, dagger=bool(dag))) <= 1e-12
+    lat.close()
+
+
+@pytest.mark.parametrize("prec,tol", [("F32", 2e-6), ("F16", 4e-3), ("F16L", 5e-3), ("F32L", 2e-3)])
+def test_dslash_sloppy_precisions(wd, oracle, prec, tol):
+    dims = (6, 4, 4, 6)
+    code = {"F32": wd.WD_F32, "F16": wd.WD_F16, "F16L": wd.WD_F16 | wd.WD_LINKS_F16,
+            "F32L": wd.WD_F32 | wd.WD_LINKS_F16}[prec]
+    V = li.volume(dims)
+    U = li.random_su3_field(dims, 0.5, seed=5)
+    lat = wd.Lattice(dims)
+    lat.gauge_load(dev(U))
+    psi = li.gaussian_spinor(V // 2, seed=6)
+    for dag in (0, 1):
+        ref = oracle.hop_eo(dims, U, psi, 0, dagger=bool(dag))
+        out = empty_like_dev(psi)
+        lat.dslash(out, dev(psi), wd.WD_EVEN, dag, code)
+        e = rel_err(host(out), ref)
+        note(f"dslash {prec} dag {dag}: rel err {e:.2e}")
+        assert e <= tol
+    lat.close()
+
+
+@pytest.mark.parametrize("dims", [(4, 4, 4, 4), (6, 4, 4, 6)])
+def test_mdagm_matches_oracle(wd, oracle, dims):
+    V = li.volume(dims)
+    U = li.random_su3_field(dims, 0.5, seed=8)
+    kappa = 0.155
+    lat = wd.Lattice(dims)
+    lat.gauge_load(dev(U), recon=12)
+    pe = li.gaussian_spinor(V // 2, seed=9)
+    out = empty_like_dev(pe)
+    lat.mdagm(out, dev(pe), kappa, eo=1)
+    assert rel_err(host(out), oracle.mhatdag_mhat(dims, U, kappa, pe)) <= 1e-12
+    pf = li.gaussian_spinor(V, seed=10)
+    out = empty_like_dev(pf)
+    lat.mdagm(out, dev(pf), kappa, eo=0)
+    assert rel_err(host(out), oracle.mdagm(dims, U, kappa, pf)) <= 1e-12
+    lat.close()
+
+
+def test_unit_gauge_free_field_plane_wave(wd):
+    """U = 1: H e^{ipx} s = e^{ipx} sum_mu [2 cos p_mu - 2i g_mu sin p_mu] s
+    (closed form, no oracle involved)."""
+    from brute import GAMMA, sites
+    dims = (4, 6, 4, 8)
+    V = li.volume(dims)
+    c = sites(dims)
+    n = np.array([1, 2, 3, 5])
+    p = 2 * np.pi * n / np.array(dims)
+    rng = np.random.default_rng(0)
+    s = rng.standard_normal((4, 3)) + 1j * rng.standard_normal((4, 3))
+    psi = np.exp(1j * (c @ p))[:, None, None] * s[None]
+    K = sum(2 * np.cos(p[m]) * np.eye(4) - 2j * GAMMA[m] * np.sin(p[m]) for m in range(4))
+    ref = np.exp(1j * (c @ p))[:, None, None] * (K @ s)[None]
+    lat = wd.Lattice(dims)
+    lat.gauge_load(dev(li.unit_field(dims)))
+    out = empty_like_dev(psi)
+    lat.dslash(out, dev(psi), wd.WD_FULL, 0, wd.WD_F64)
+    assert rel_err(host(out), ref) <= 1e-13
+    lat.close()
+
+
+def test_errors(wd):
+    import torch
+    with pytest.raises(wd.WDError) as e:
+        wd.Lattice((4, 4, 5, 4))
+    assert e.value.status == wd.WD_ERR_DIMS
+    lat = wd.Lattice((4, 4, 4, 4))
+    x = torch.zeros((128, 4, 3), dtype=torch.complex128, device="cuda")
+    with pytest.raises(wd.WDError) as e:
+        lat.dslash(x, x.clone(), wd.WD_EVEN)
+    assert e.value.status == wd.WD_ERR_STATE
+    lat.close()
