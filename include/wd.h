@@ -159,6 +159,12 @@ size_t wd_bytes_required(const int32_t dims[4], int nrhs, const wd_solver_params
 wd_status wd_timing_enable(wd_ctx *c, int on);
 wd_status wd_timing_read(wd_ctx *c, double *total_ms, int64_t *launches, double *bytes);
 
+/* Per-kernel breakdown of the same timed launches, without resetting them:
+ * one line per stencil instance, "name;launches;total_ms;algorithmic_bytes\n",
+ * written to the HOST buffer buf of len bytes (WD_ERR_ARG if too small).
+ * The name is the kernel's template instance as profilers print it. */
+wd_status wd_timing_report(wd_ctx *c, char *buf, size_t len);
+
 /* Message of the last failed call on this thread (never NULL). */
 const char *wd_last_error(void);
 

@@ -6,6 +6,7 @@
 
 #include <cmath>
 #include <cstring>
+#include <tuple>
 
 #include "wd_internal.h"
 
@@ -165,7 +166,13 @@ wd_status run_sweep(wd_ctx *c, const Sweep &sw, const TuneCfg *cfg)
                          sw.lk, nr, sw.epi, t.block, hipGetErrorString(e));
     if (c->timing) {
         WD_HIP(hipEventRecord(e1, c->stream));
-        c->t_bytes += sweep_bytes(c, sw);
+        const double b = sweep_bytes(c, sw);
+        char name[96];
+        snprintf(name, sizeof(name), "dslash_kernel<%d, %d, %d, %s, %d, %d>", sw.sp, sw.lk, nr,
+                 sw.dag ? "true" : "false", sw.epi, sw.sp == SP_F64 ? SP_F64 : SP_F32);
+        if (c->ev_info.size() < c->ev_used) c->ev_info.resize(c->ev_used);
+        c->ev_info[c->ev_used - 1] = std::make_tuple(std::string(name), b, (double)c->Vh * sw.nact);
+        c->t_bytes += b;
         c->t_launches++;
     }
     return WD_OK;
@@ -522,6 +529,33 @@ wd_status wd_timing_read(wd_ctx *c, double *total_ms, int64_t *launches, double 
     c->ev_used = 0;
     c->t_bytes = 0;
     c->t_launches = 0;
+    return WD_OK;
+}
+
+wd_status wd_timing_report(wd_ctx *c, char *buf, size_t len)
+{
+    if (!c || !buf || len == 0) return set_error(WD_ERR_ARG, "NULL argument");
+    WD_HIP(hipStreamSynchronize(c->stream));
+    std::map<std::string, std::tuple<long long, double, double, double>> agg;
+    for (size_t k = 0; k < c->ev_used; k++) {
+        float t = 0;
+        WD_HIP(hipEventElapsedTime(&t, c->events[k].first, c->events[k].second));
+        auto &a = agg[std::get<0>(c->ev_info[k])];
+        std::get<0>(a) += 1;
+        std::get<1>(a) += t;
+        std::get<2>(a) += std::get<1>(c->ev_info[k]);
+        std::get<3>(a) += std::get<2>(c->ev_info[k]);
+    }
+    std::string out;
+    for (auto &kv : agg) {
+        char line[256];
+        snprintf(line, sizeof(line), "%s;%lld;%.6f;%.1f;%.1f\n", kv.first.c_str(),
+                 std::get<0>(kv.second), std::get<1>(kv.second), std::get<2>(kv.second),
+                 std::get<3>(kv.second));
+        out += line;
+    }
+    if (out.size() + 1 > len) return set_error(WD_ERR_ARG, "report needs %zu bytes", out.size() + 1);
+    memcpy(buf, out.c_str(), out.size() + 1);
     return WD_OK;
 }
 

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <map>
+#include <tuple>
 #include <string>
 #include <vector>
 
@@ -138,6 +139,7 @@ struct wd_ctx {
     // stencil timing
     bool timing = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
+    std::vector<std::tuple<std::string, double, double>> ev_info;  // name, bytes, site-RHS
     size_t ev_used = 0;
     double t_bytes = 0;
     double t_ms = 0;

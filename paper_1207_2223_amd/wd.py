@@ -58,6 +58,7 @@ _SIGS = {
     "wd_timing_enable": (C.c_int, [_P, C.c_int]),
     "wd_timing_read": (C.c_int, [_P, C.POINTER(C.c_double), C.POINTER(C.c_int64),
                                  C.POINTER(C.c_double)]),
+    "wd_timing_report": (C.c_int, [_P, C.c_char_p, C.c_size_t]),
     "wd_last_error": (C.c_char_p, []),
     "wd_version": (C.c_char_p, []),
 }
@@ -213,6 +214,18 @@ def wd_timing_read(ctx):
     b = C.c_double()
     _check(lib().wd_timing_read(ctx, C.byref(ms), C.byref(n), C.byref(b)))
     return ms.value, n.value, b.value
+
+
+def wd_timing_report(ctx):
+    """{kernel name: (launches, total_ms, algorithmic_bytes, output_site_rhs)} since the last
+    reset."""
+    buf = C.create_string_buffer(1 << 16)
+    _check(lib().wd_timing_report(ctx, buf, len(buf)))
+    out = {}
+    for line in buf.value.decode().splitlines():
+        name, n, ms, b, u = line.split(";")
+        out[name] = (int(n), float(ms), float(b), float(u))
+    return out
 
 
 def wd_last_error():
