@@ -33,9 +33,10 @@ WORKLOADS = {
     "c2_16c32": dict(dims=(16, 16, 16, 32), eps=0.5, kappa=0.155, nrhs=8, cfg=1),
     "c1_4c4": dict(dims=(4, 4, 4, 4), eps=0.3, kappa=0.15, nrhs=1, cfg=0),
 }
-PRECS = {"f64": 0, "f32": 1, "f16": 2, "f16l16": 2 | 0x10, "f32l16": 1 | 0x10}
+PRECS = {"f64": 0, "f32": 1, "f16": 2, "f16l16": 2 | 0x10, "f32l16": 1 | 0x10,
+         "f16r18": 2 | 0x20, "f32r18": 1 | 0x20}
 DTYPE = {"f64": "f64", "f32": "f32", "f16": "f16+norm/f32", "f16l16": "f16+norm/f32",
-         "f32l16": "f32"}
+         "f32l16": "f32", "f16r18": "f16+norm/f32", "f32r18": "f32"}
 
 
 def log(msg):
@@ -52,7 +53,11 @@ def parse():
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison solve")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--tuned", type=int, default=0)
+    ap.add_argument("--tuned", type=int, default=1, help="autotune launch shapes before timing")
+    ap.add_argument("--tune-only", action="store_true",
+                    help="autotune (filling WD_TUNE_CACHE when set) and exit")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run one plain 1 GiB device copy (counter calibration)")
     return ap.parse_args()
 
 
@@ -111,12 +116,31 @@ def main():
     lat = wd.Lattice(dims)
     lat.gauge_load(Ud, recon=12)
     params = wd.solver_params(prec=PRECS[args.prec], eo=1, tuned=args.tuned)
+    if args.tuned:
+        t = time.time()
+        for code in {PRECS[args.prec], 0}:
+            for row in wd.wd_tune(lat.ctx, nrhs, code):
+                log(f"[bench] tuned {code:#x} {row['sweep']}: block {row['block']} nr {row['nr']} "
+                    f"rl {row['rl']} remap {row['remap']} {row['us']:.1f} us")
+        log(f"[bench] autotune {time.time() - t:.1f}s")
+    if args.tune_only:
+        lat.close()
+        return
     torch.cuda.synchronize()
 
     def solve(p):
         st, stats = lat.cg_solve(Xd, Bd, [kappa] * nrhs, p)
         return st, stats
 
+    if args.copy_probe:
+        a = torch.empty(1 << 27, dtype=torch.float64, device=dev)
+        b = torch.empty_like(a)
+        a.fill_(1.0)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log("[bench] copy probe: 1 GiB read + 1 GiB written by one copy kernel")
+        del a, b
     for k in range(args.warmup):
         st, stats = solve(params)
         log(f"[bench] warmup {k}: status {st} iters {[s['iters'] for s in stats][:4]}...")
@@ -152,7 +176,7 @@ def main():
 
     fp64 = None
     if not args.no_fp64 and args.prec != "f64":
-        p64 = wd.solver_params(prec=0, eo=1)
+        p64 = wd.solver_params(prec=0, eo=1, tuned=args.tuned)
         torch.cuda.synchronize()
         ts = time.perf_counter()
         st64, s64 = solve(p64)

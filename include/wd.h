@@ -62,8 +62,10 @@ typedef enum {
 
 typedef enum { WD_F64 = 0, WD_F32 = 1, WD_F16 = 2 } wd_prec;
 /* Or-ed into a WD_F32 / WD_F16 precision code: the sloppy operator reads
- * FP16 12-real links instead of FP32 12-real links. */
+ * FP16 12-real links (WD_LINKS_F16) or FP32 links with all 18 reals
+ * (WD_LINKS_R18, no reconstruction) instead of FP32 12-real links. */
 #define WD_LINKS_F16 0x10
+#define WD_LINKS_R18 0x20
 typedef enum { WD_FULL = 0, WD_EVEN = 1, WD_ODD = 2 } wd_parity;
 
 /* wd_gauge_load flags: storage of the FP64 operator's links. */
@@ -109,7 +111,7 @@ wd_status wd_set_stream(wd_ctx *c, void *hip_stream);
 
 /* Load the gauge field U (canonical [V][4][3][3] complex128, device) and pack
  * it into the internal layouts: FP64 with 18 or 12 reals (flags), and FP32
- * and FP16 12-real copies for the sloppy operators.  Links are assumed to be
+ * 12-real, FP32 18-real and FP16 12-real copies for the sloppy operators.  Links are assumed to be
  * in SU(3) (12-real reconstruction is exact only there). */
 wd_status wd_gauge_load(wd_ctx *c, const double *U, uint32_t flags);
 
@@ -117,7 +119,8 @@ wd_status wd_gauge_load(wd_ctx *c, const double *U, uint32_t flags);
  *   out_parity = WD_EVEN / WD_ODD: out[Vh][4][3] = D_{P,1-P} in, with `in`
  *     the [Vh][4][3] field on the other parity;
  *   out_parity = WD_FULL: out[V][4][3] = H in on the full lattice.
- * dagger = 1 applies H^dag.  prec (a wd_prec, optionally | WD_LINKS_F16)
+ * dagger = 1 applies H^dag.  prec (a wd_prec, optionally | WD_LINKS_F16 or
+ * | WD_LINKS_R18)
  * selects the arithmetic and storage used inside: FP64 with the gauge_load
  * link format, or FP32 / FP16-with-norm spinors with FP32 (or FP16) 12-real
  * links and FP32 arithmetic.  The canonical in/out stay FP64. */
@@ -164,6 +167,27 @@ wd_status wd_timing_read(wd_ctx *c, double *total_ms, int64_t *launches, double 
  * written to the HOST buffer buf of len bytes (WD_ERR_ARG if too small).
  * The name is the kernel's template instance as profilers print it. */
 wd_status wd_timing_report(wd_ctx *c, char *buf, size_t len);
+
+/* Autotune the launch shapes of the even-odd solver's four stencil sweeps for
+ * nrhs right-hand sides in precision prec (wd_prec, | WD_LINKS_F16).  Every
+ * supported shape (threads per work-group, RHS per lane, lanes per site, XCD
+ * tile order) is timed with HIP events on synthetic fields; a shape whose
+ * vectors or norm partials are not bitwise identical to the reference shape
+ * is rejected.  The fastest shapes are kept in the context and used by
+ * solves with wd_solver_params.tuned = 1.  report: HOST buffer of len bytes
+ * receiving one line per sweep (may be NULL).  Needs a loaded gauge field.
+ * If the environment variable WD_TUNE_CACHE names a file, shapes found there
+ * for the same lattice, nrhs and formats are reused without timing, and new
+ * results are appended to it. */
+wd_status wd_tune(wd_ctx *c, int nrhs, int prec, char *report, size_t len);
+
+/* Stencil micro-benchmark: `iters` back-to-back sweeps of the stencil with
+ * epilogue epi (0 plain D_oe, 1 xpay+norm D_eo, 2 fused CG update D_eo) on
+ * nrhs synthetic fields of precision prec, with the tuned shape if tuned = 1
+ * and one was kept, else the default.  *ms (HOST) receives the HIP-event
+ * time per sweep, *bytes (HOST, may be NULL) its algorithmic bytes. */
+wd_status wd_bench_dslash(wd_ctx *c, int nrhs, int prec, int epi, int iters, int tuned,
+                          double *ms, double *bytes);
 
 /* Message of the last failed call on this thread (never NULL). */
 const char *wd_last_error(void);

@@ -2,7 +2,8 @@
 
 Every source compiles to an object in parallel, then one shared library is
 linked next to this file.  Packed-FP32 instructions are disabled for all HIP
-code (-packed-fp32-ops).
+code (-packed-fp32-ops), and floating-point contraction is off: the kernels
+spell out their fused multiply-adds, so every instantiation rounds alike.
 """
 import concurrent.futures as cf
 import os
@@ -16,7 +17,7 @@ LIB = os.path.join(HERE, "libwd.so")
 ARCH = os.environ.get("WD_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-Wall",
+FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-Wall", "-ffp-contract=off",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I", os.path.join(HERE, "..", "include")]
 

@@ -1,8 +1,8 @@
 // blas.hip -- CG vector kernels over batches of spinor fields (the level-1
 // BLAS work the paper delegates to CUBLAS, Sec. 3), fused where CG allows,
-// with deterministic FP64 reductions: each 64-site wavefront writes one
-// partial sum in fixed butterfly order, and blas_finalize adds the partials
-// of one RHS in a fixed order in a single work-group.
+// with deterministic FP64 reductions: each group of 16 consecutive sites
+// writes one partial sum in a fixed pairing order, and blas_finalize adds the
+// partials of one RHS in a fixed order in a single work-group.
 #include "wd_internal.h"
 
 namespace wd {
@@ -10,12 +10,21 @@ namespace wd {
 namespace {
 
 constexpr int kBlock = 256;
+constexpr int kFinBlock = 1024;
+
+__device__ __forceinline__ double sum16(double v)
+{
+#pragma unroll
+    for (int off = 8; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
 
 struct FArg {
     char *base;
     long long rs, ss;
+    int cs;
 };
-inline FArg fa(const Field &f) { return FArg{f.base, f.rs, f.ss}; }
+inline FArg fa(const Field &f) { return FArg{f.base, f.rs, f.ss, f.cs}; }
 
 __device__ __forceinline__ char *site_base(const FArg &f, int rid, int sub)
 {
@@ -33,12 +42,12 @@ __global__ void __launch_bounds__(kBlock) k_norm(FArg a, int Vh, int nsub, const
     if (s < nsub * Vh) {
         const int sub = s / Vh, i = s - sub * Vh;
         real x[24];
-        SpinorIO<SP>::load(site_base(a, rid, sub), Vh, i, x);
+        SpinorIO<SP>::load(site_base(a, rid, sub), a.cs, i, x);
 #pragma unroll
-        for (int k = 0; k < 24; k++) v += (double)x[k] * (double)x[k];
+        for (int k = 0; k < 24; k++) v = fmaT((double)x[k], (double)x[k], v);
     }
-    v = wave_sum(v);
-    if ((threadIdx.x & 63) == 0 && s < nsub * Vh) partial[(size_t)rid * pstride + (s >> 6)] = v;
+    v = sum16(v);
+    if ((threadIdx.x & 15) == 0 && s < nsub * Vh) partial[(size_t)rid * pstride + (s >> 4)] = v;
 }
 
 template <int SP>
@@ -52,11 +61,11 @@ __global__ void __launch_bounds__(kBlock) k_p_update(FArg p, FArg r, const doubl
     const int sub = s / Vh, i = s - sub * Vh;
     const real b = (real)beta[rid];
     real pv[24], rv[24];
-    SpinorIO<SP>::load(site_base(p, rid, sub), Vh, i, pv);
-    SpinorIO<SP>::load(site_base(r, rid, sub), Vh, i, rv);
+    SpinorIO<SP>::load(site_base(p, rid, sub), p.cs, i, pv);
+    SpinorIO<SP>::load(site_base(r, rid, sub), r.cs, i, rv);
 #pragma unroll
-    for (int k = 0; k < 24; k++) pv[k] = rv[k] + b * pv[k];
-    SpinorIO<SP>::store(site_base(p, rid, sub), Vh, i, pv);
+    for (int k = 0; k < 24; k++) pv[k] = fmaT(b, pv[k], rv[k]);
+    SpinorIO<SP>::store(site_base(p, rid, sub), p.cs, i, pv);
 }
 
 template <int SP, int XP>
@@ -75,21 +84,21 @@ __global__ void __launch_bounds__(kBlock) k_cg_update(FArg x, FArg p, FArg r, FA
         const real al = (real)alpha[rid];
         real pv[24], rv[24], av[24];
         xreal xv[24];
-        SpinorIO<SP>::load(site_base(p, rid, sub), Vh, i, pv);
-        SpinorIO<SP>::load(site_base(r, rid, sub), Vh, i, rv);
-        SpinorIO<SP>::load(site_base(Ap, rid, sub), Vh, i, av);
-        SpinorIO<XP>::load(site_base(x, rid, sub), Vh, i, xv);
+        SpinorIO<SP>::load(site_base(p, rid, sub), p.cs, i, pv);
+        SpinorIO<SP>::load(site_base(r, rid, sub), r.cs, i, rv);
+        SpinorIO<SP>::load(site_base(Ap, rid, sub), Ap.cs, i, av);
+        SpinorIO<XP>::load(site_base(x, rid, sub), x.cs, i, xv);
 #pragma unroll
         for (int k = 0; k < 24; k++) {
-            xv[k] += (xreal)(al * pv[k]);
-            rv[k] -= al * av[k];
-            v += (double)rv[k] * (double)rv[k];
+            xv[k] = fmaT((xreal)al, (xreal)pv[k], xv[k]);
+            rv[k] = fmaT(-al, av[k], rv[k]);
+            v = fmaT((double)rv[k], (double)rv[k], v);
         }
-        SpinorIO<XP>::store(site_base(x, rid, sub), Vh, i, xv);
-        SpinorIO<SP>::store(site_base(r, rid, sub), Vh, i, rv);
+        SpinorIO<XP>::store(site_base(x, rid, sub), x.cs, i, xv);
+        SpinorIO<SP>::store(site_base(r, rid, sub), r.cs, i, rv);
     }
-    v = wave_sum(v);
-    if ((threadIdx.x & 63) == 0 && s < nsub * Vh) partial[(size_t)rid * pstride + (s >> 6)] = v;
+    v = sum16(v);
+    if ((threadIdx.x & 15) == 0 && s < nsub * Vh) partial[(size_t)rid * pstride + (s >> 4)] = v;
 }
 
 template <int SPD, int SPS>
@@ -101,8 +110,8 @@ __global__ void __launch_bounds__(kBlock) k_copy(FArg d, FArg src, int Vh, int n
     if (s >= nsub * Vh) return;
     const int sub = s / Vh, i = s - sub * Vh;
     double v[24];
-    SpinorIO<SPS>::load(site_base(src, rid, sub), Vh, i, v);
-    SpinorIO<SPD>::store(site_base(d, rid, sub), Vh, i, v);
+    SpinorIO<SPS>::load(site_base(src, rid, sub), src.cs, i, v);
+    SpinorIO<SPD>::store(site_base(d, rid, sub), d.cs, i, v);
 }
 
 // xhi (FP64) += xs ; xs = 0
@@ -115,15 +124,15 @@ __global__ void __launch_bounds__(kBlock) k_add_zero(FArg xhi, FArg xs, int Vh, 
     if (s >= nsub * Vh) return;
     const int sub = s / Vh, i = s - sub * Vh;
     double h[24], l[24];
-    SpinorIO<SP_F64>::load(site_base(xhi, rid, sub), Vh, i, h);
-    SpinorIO<XP>::load(site_base(xs, rid, sub), Vh, i, l);
+    SpinorIO<SP_F64>::load(site_base(xhi, rid, sub), xhi.cs, i, h);
+    SpinorIO<XP>::load(site_base(xs, rid, sub), xs.cs, i, l);
 #pragma unroll
     for (int k = 0; k < 24; k++) {
         h[k] += l[k];
         l[k] = 0.0;
     }
-    SpinorIO<SP_F64>::store(site_base(xhi, rid, sub), Vh, i, h);
-    SpinorIO<XP>::store(site_base(xs, rid, sub), Vh, i, l);
+    SpinorIO<SP_F64>::store(site_base(xhi, rid, sub), xhi.cs, i, h);
+    SpinorIO<XP>::store(site_base(xs, rid, sub), xs.cs, i, l);
 }
 
 // r = b - Ap, all FP64, with |r|^2 partials
@@ -137,17 +146,17 @@ __global__ void __launch_bounds__(kBlock) k_resid(FArg r, FArg b, FArg Ap, int V
     if (s < nsub * Vh) {
         const int sub = s / Vh, i = s - sub * Vh;
         double bv[24], av[24];
-        SpinorIO<SP_F64>::load(site_base(b, rid, sub), Vh, i, bv);
-        SpinorIO<SP_F64>::load(site_base(Ap, rid, sub), Vh, i, av);
+        SpinorIO<SP_F64>::load(site_base(b, rid, sub), b.cs, i, bv);
+        SpinorIO<SP_F64>::load(site_base(Ap, rid, sub), Ap.cs, i, av);
 #pragma unroll
         for (int k = 0; k < 24; k++) {
             bv[k] -= av[k];
-            v += bv[k] * bv[k];
+            v = fmaT(bv[k], bv[k], v);
         }
-        SpinorIO<SP_F64>::store(site_base(r, rid, sub), Vh, i, bv);
+        SpinorIO<SP_F64>::store(site_base(r, rid, sub), r.cs, i, bv);
     }
-    v = wave_sum(v);
-    if ((threadIdx.x & 63) == 0 && s < nsub * Vh) partial[(size_t)rid * pstride + (s >> 6)] = v;
+    v = sum16(v);
+    if ((threadIdx.x & 15) == 0 && s < nsub * Vh) partial[(size_t)rid * pstride + (s >> 4)] = v;
 }
 
 template <int SP>
@@ -160,23 +169,96 @@ __global__ void __launch_bounds__(kBlock) k_zero(FArg a, int Vh, int nsub, const
     double z[24];
 #pragma unroll
     for (int k = 0; k < 24; k++) z[k] = 0.0;
-    SpinorIO<SP>::store(site_base(a, rid, sub), Vh, i, z);
+    SpinorIO<SP>::store(site_base(a, rid, sub), a.cs, i, z);
+}
+
+// <a, b> = sum conj(a) b, real and imaginary partials
+template <int SP>
+__global__ void __launch_bounds__(kBlock) k_cdot(FArg a, FArg b, int Vh, int nsub, const int *active,
+                                                  double *pre, double *pim, int pstride)
+{
+    typedef typename SpinorIO<SP>::real real;
+    const int rid = active[blockIdx.y];
+    const int s = blockIdx.x * kBlock + threadIdx.x;
+    double vr = 0.0, vi = 0.0;
+    if (s < nsub * Vh) {
+        const int sub = s / Vh, i = s - sub * Vh;
+        real x[24], y[24];
+        SpinorIO<SP>::load(site_base(a, rid, sub), a.cs, i, x);
+        SpinorIO<SP>::load(site_base(b, rid, sub), b.cs, i, y);
+#pragma unroll
+        for (int k = 0; k < 12; k++) {
+            const double ar = x[2 * k], ai = x[2 * k + 1], br = y[2 * k], bi = y[2 * k + 1];
+            vr = fmaT(ar, br, vr);
+            vr = fmaT(ai, bi, vr);
+            vi = fmaT(ar, bi, vi);
+            vi = fmaT(-ai, br, vi);
+        }
+    }
+    vr = sum16(vr);
+    vi = sum16(vi);
+    if ((threadIdx.x & 15) == 0 && s < nsub * Vh) {
+        pre[(size_t)rid * pstride + (s >> 4)] = vr;
+        pim[(size_t)rid * pstride + (s >> 4)] = vi;
+    }
+}
+
+// p -= c r with c = <r, p> / rr (complex), per RHS
+template <int SP>
+__global__ void __launch_bounds__(kBlock) k_orth(FArg p, FArg r, const double *dre, const double *dim,
+                                                  const double *rr, int Vh, int nsub, const int *active)
+{
+    typedef typename SpinorIO<SP>::real real;
+    const int rid = active[blockIdx.y];
+    const int s = blockIdx.x * kBlock + threadIdx.x;
+    if (s >= nsub * Vh) return;
+    const int sub = s / Vh, i = s - sub * Vh;
+    const double n = rr[rid];
+    const real cr = (real)(n > 0.0 ? dre[rid] / n : 0.0), ci = (real)(n > 0.0 ? dim[rid] / n : 0.0);
+    real pv[24], rv[24];
+    SpinorIO<SP>::load(site_base(p, rid, sub), p.cs, i, pv);
+    SpinorIO<SP>::load(site_base(r, rid, sub), r.cs, i, rv);
+#pragma unroll
+    for (int k = 0; k < 12; k++) {
+        const real ar = rv[2 * k], ai = rv[2 * k + 1];
+        pv[2 * k] = fmaT(-cr, ar, fmaT(ci, ai, pv[2 * k]));
+        pv[2 * k + 1] = fmaT(-cr, ai, fmaT(-ci, ar, pv[2 * k + 1]));
+    }
+    SpinorIO<SP>::store(site_base(p, rid, sub), p.cs, i, pv);
+}
+
+// p += a r  (a a real constant)
+template <int SP>
+__global__ void __launch_bounds__(kBlock) k_axpy_const(FArg p, FArg r, double a, int Vh, int nsub,
+                                                        const int *active)
+{
+    typedef typename SpinorIO<SP>::real real;
+    const int rid = active[blockIdx.y];
+    const int s = blockIdx.x * kBlock + threadIdx.x;
+    if (s >= nsub * Vh) return;
+    const int sub = s / Vh, i = s - sub * Vh;
+    real pv[24], rv[24];
+    SpinorIO<SP>::load(site_base(p, rid, sub), p.cs, i, pv);
+    SpinorIO<SP>::load(site_base(r, rid, sub), r.cs, i, rv);
+#pragma unroll
+    for (int k = 0; k < 24; k++) pv[k] = fmaT((real)a, rv[k], pv[k]);
+    SpinorIO<SP>::store(site_base(p, rid, sub), p.cs, i, pv);
 }
 
 // One work-group per active RHS: fixed-order sum of its partials, then the
 // CG scalar update selected by mode.
-__global__ void __launch_bounds__(kBlock) k_finalize(const double *partial, int pstride, int nw,
-                                                      const int *active, int mode, double *rr,
-                                                      double *alpha, double *beta, double *out)
+__global__ void __launch_bounds__(kFinBlock) k_finalize(const double *partial, int pstride, int nw,
+                                                         const int *active, int mode, double *rr,
+                                                         double *alpha, double *beta, double *out)
 {
-    __shared__ double sh[kBlock];
+    __shared__ double sh[kFinBlock];
     const int rid = active[blockIdx.x];
     const double *pp = partial + (size_t)rid * pstride;
     double v = 0.0;
-    for (int w = threadIdx.x; w < nw; w += kBlock) v += pp[w];
+    for (int w = threadIdx.x; w < nw; w += kFinBlock) v += pp[w];
     sh[threadIdx.x] = v;
     __syncthreads();
-    for (int off = kBlock / 2; off > 0; off >>= 1) {
+    for (int off = kFinBlock / 2; off > 0; off >>= 1) {
         if ((int)threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
         __syncthreads();
     }
@@ -300,12 +382,45 @@ hipError_t blas_zero(const Field &a, int Vh, const int *active, int nact, hipStr
     return hipGetLastError();
 }
 
+hipError_t blas_cdot(const Field &a, const Field &b, int Vh, const int *active, int nact,
+                     double *pre, double *pim, int pstride, hipStream_t s)
+{
+    if (nact == 0) return hipSuccess;
+    if (a.sp != b.sp) return hipErrorInvalidValue;
+#define F(SP) hipLaunchKernelGGL(k_cdot<SP>, grid_of(Vh, a.nsub, nact), dim3(kBlock), 0, s, fa(a), fa(b), Vh, a.nsub, active, pre, pim, pstride)
+    SP_SWITCH(a.sp, F)
+#undef F
+    return hipGetLastError();
+}
+
+hipError_t blas_orth(const Field &p, const Field &r, const double *dre, const double *dim,
+                     const double *rr, int Vh, const int *active, int nact, hipStream_t s)
+{
+    if (nact == 0) return hipSuccess;
+    if (p.sp != r.sp) return hipErrorInvalidValue;
+#define F(SP) hipLaunchKernelGGL(k_orth<SP>, grid_of(Vh, p.nsub, nact), dim3(kBlock), 0, s, fa(p), fa(r), dre, dim, rr, Vh, p.nsub, active)
+    SP_SWITCH(p.sp, F)
+#undef F
+    return hipGetLastError();
+}
+
+hipError_t blas_axpy_const(const Field &p, const Field &r, double a, int Vh, const int *active,
+                           int nact, hipStream_t s)
+{
+    if (nact == 0) return hipSuccess;
+    if (p.sp != r.sp) return hipErrorInvalidValue;
+#define F(SP) hipLaunchKernelGGL(k_axpy_const<SP>, grid_of(Vh, p.nsub, nact), dim3(kBlock), 0, s, fa(p), fa(r), a, Vh, p.nsub, active)
+    SP_SWITCH(p.sp, F)
+#undef F
+    return hipGetLastError();
+}
+
 hipError_t blas_finalize(const double *partial, int pstride, int nw, const int *active, int nact,
                          int mode, double *rr, double *alpha, double *beta, double *out,
                          hipStream_t s)
 {
     if (nact == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_finalize, dim3(nact), dim3(kBlock), 0, s, partial, pstride, nw, active, mode, rr, alpha, beta, out);
+    hipLaunchKernelGGL(k_finalize, dim3(nact), dim3(kFinBlock), 0, s, partial, pstride, nw, active, mode, rr, alpha, beta, out);
     return hipGetLastError();
 }
 

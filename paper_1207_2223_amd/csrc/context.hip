@@ -64,7 +64,7 @@ wd_status pinned_get(wd_ctx *c, int slot, size_t bytes, void **ptr)
 
 wd_status alloc_field(wd_ctx *c, const std::string &name, int sp, int nsub, int nrhs, Field *f)
 {
-    const long long sb = (long long)spinor_site_bytes(sp) * c->Vh;
+    const long long sb = (long long)spinor_site_bytes(sp) * c->g.cs;
     const long long sub = (sb + 255) / 256 * 256;
     void *p = nullptr;
     WD_TRY(ws_get(c, name, (size_t)sub * nsub * nrhs, &p));
@@ -73,6 +73,7 @@ wd_status alloc_field(wd_ctx *c, const std::string &name, int sp, int nsub, int 
     f->rs = sub * nsub;
     f->sp = sp;
     f->nsub = nsub;
+    f->cs = c->g.cs;
     return WD_OK;
 }
 
@@ -80,7 +81,21 @@ const char *link_ptr(const wd_ctx *c, int lk)
 {
     if (lk == LK_F64_18 || lk == LK_F64_12) return c->links64;
     if (lk == LK_F32_12) return c->links32;
+    if (lk == LK_F32_18) return c->links32r;
     return c->links16;
+}
+
+wd_status decode_prec(const wd_ctx *c, int prec, int *sp, int *lk, int *xp)
+{
+    const int base = prec & 0xf;
+    const bool l16 = (prec & WD_LINKS_F16) != 0, r18 = (prec & WD_LINKS_R18) != 0;
+    if ((prec & ~(0xf | WD_LINKS_F16 | WD_LINKS_R18)) || base > WD_F16 || (base == WD_F64 && (l16 || r18)) ||
+        (l16 && r18))
+        return set_error(WD_ERR_ARG, "bad precision code 0x%x", prec);
+    *sp = base == WD_F64 ? SP_F64 : (base == WD_F32 ? SP_F32 : SP_F16);
+    *lk = *sp == SP_F64 ? c->lk64 : (l16 ? LK_F16_12 : (r18 ? LK_F32_18 : LK_F32_12));
+    *xp = *sp == SP_F64 ? SP_F64 : SP_F32;
+    return WD_OK;
 }
 
 TuneCfg default_cfg(int sp)
@@ -88,6 +103,7 @@ TuneCfg default_cfg(int sp)
     TuneCfg t;
     t.block = 128;
     t.nr = 1;
+    t.rl = 1;
     t.remap = 1;
     (void)sp;
     return t;
@@ -102,17 +118,14 @@ double sweep_bytes(const wd_ctx *c, const Sweep &sw)
     return (double)c->Vh * (8.0 * (double)link_bytes(sw.lk) + sw.nact * per_rhs);
 }
 
-static int clamp_nr(int sp, int nr)
-{
-    if (sp == SP_F64) return nr >= 2 ? 2 : 1;
-    return nr >= 4 ? 4 : (nr >= 2 ? 2 : 1);
-}
-
 wd_status run_sweep(wd_ctx *c, const Sweep &sw, const TuneCfg *cfg)
 {
     if (sw.nact <= 0) return WD_OK;
+    if (!cfg && c->use_tuned) cfg = tuned_cfg(c, sw);
     TuneCfg t = cfg ? *cfg : default_cfg(sw.sp);
-    const int nr = clamp_nr(sw.sp, t.nr);
+    if (!dslash_shape_supported(sw.sp, t.nr, t.rl) || t.block < 64 || t.block > 256 || (t.block & 63))
+        return set_error(WD_ERR_ARG, "unsupported launch shape block %d nr %d rl %d", t.block, t.nr, t.rl);
+    const int nr = t.nr, rl = t.rl;
     DslashArgs a;
     a.g = c->g;
     a.P = sw.P;
@@ -133,12 +146,21 @@ wd_status run_sweep(wd_ctx *c, const Sweep &sw, const TuneCfg *cfg)
     a.alpha = sw.alpha;
     a.active = sw.active;
     a.nact = sw.nact;
-    a.G = (sw.nact + nr - 1) / nr;
+    a.G = (sw.nact + nr * rl - 1) / (nr * rl);
     a.remap = t.remap;
     a.partial = sw.partial;
     a.pstride = sw.pstride;
     a.pw_off = sw.pw_off;
-    const int ntiles = (int)((c->Vh + t.block - 1) / t.block);
+    const int spb = t.block / rl;
+    const int ntiles = (int)((c->Vh + spb - 1) / spb);
+    a.tpp = 1;
+    a.nzl = 1;
+    if (t.remap == 2) {
+        if (!slab_order_ok(c->g, spb))
+            return set_error(WD_ERR_ARG, "z-slab tile order needs Lz %% 8 == 0 and whole tiles per plane");
+        a.tpp = c->g.Lxh * c->g.L[1] / spb;
+        a.nzl = c->g.L[2] / 8;
+    }
     const long long grid = (long long)ntiles * a.G;
     if (grid > 0x7fffffffLL) return set_error(WD_ERR_ARG, "grid too large");
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -154,28 +176,28 @@ wd_status run_sweep(wd_ctx *c, const Sweep &sw, const TuneCfg *cfg)
         c->ev_used++;
         WD_HIP(hipEventRecord(e0, c->stream));
     }
-    hipError_t e;
-    if (sw.sp == SP_F64)
-        e = dslash_launch_f64(a, sw.lk, nr, sw.dag, sw.epi, t.block, (int)grid, c->stream);
-    else if (sw.sp == SP_F32)
-        e = dslash_launch_f32(a, sw.lk, nr, sw.dag, sw.epi, t.block, (int)grid, c->stream);
-    else
-        e = dslash_launch_f16(a, sw.lk, nr, sw.dag, sw.epi, t.block, (int)grid, c->stream);
+    hipError_t e = dslash_launch(a, sw.sp, sw.lk, nr, rl, sw.dag, sw.epi, t.block, (int)grid, c->stream);
     if (e != hipSuccess)
-        return set_error(WD_ERR_HIP, "stencil launch (sp %d lk %d nr %d epi %d block %d): %s", sw.sp,
-                         sw.lk, nr, sw.epi, t.block, hipGetErrorString(e));
+        return set_error(WD_ERR_HIP, "stencil launch (sp %d lk %d nr %d rl %d epi %d block %d): %s",
+                         sw.sp, sw.lk, nr, rl, sw.epi, t.block, hipGetErrorString(e));
     if (c->timing) {
         WD_HIP(hipEventRecord(e1, c->stream));
         const double b = sweep_bytes(c, sw);
         char name[96];
-        snprintf(name, sizeof(name), "dslash_kernel<%d, %d, %d, %s, %d, %d>", sw.sp, sw.lk, nr,
-                 sw.dag ? "true" : "false", sw.epi, sw.sp == SP_F64 ? SP_F64 : SP_F32);
+        snprintf(name, sizeof(name), "dslash_kernel<%d, %d, %d, %d, %s, %d, %d>", sw.sp, sw.lk, nr,
+                 rl, sw.dag ? "true" : "false", sw.epi, sw.sp == SP_F64 ? SP_F64 : SP_F32);
         if (c->ev_info.size() < c->ev_used) c->ev_info.resize(c->ev_used);
         c->ev_info[c->ev_used - 1] = std::make_tuple(std::string(name), b, (double)c->Vh * sw.nact);
         c->t_bytes += b;
         c->t_launches++;
     }
     return WD_OK;
+}
+
+bool slab_order_ok(const Geom &g, int spb)
+{
+    const int plane = g.Lxh * g.L[1];
+    return g.L[2] % 8 == 0 && spb > 0 && plane % spb == 0;
 }
 
 static wd_status upload(wd_ctx *c, void *dst, const void *src, size_t bytes)
@@ -275,6 +297,10 @@ wd_status wd_create(wd_ctx **out, const int32_t dims[4], int device, void *hip_s
     c->g.sy = c->g.Lxh;
     c->g.sz = c->g.Lxh * dims[1];
     c->g.st = c->g.Lxh * dims[1] * dims[2];
+    c->g.cs = padded_stride((int)c->Vh);
+    c->g.dxh = make_fastdiv(c->g.Lxh);
+    c->g.dy = make_fastdiv(dims[1]);
+    c->g.dz = make_fastdiv(dims[2]);
     *out = c;
     return WD_OK;
 }
@@ -288,6 +314,7 @@ wd_status wd_destroy(wd_ctx *c)
     if (c->links64) (void)hipFree(c->links64);
     if (c->links32) (void)hipFree(c->links32);
     if (c->links16) (void)hipFree(c->links16);
+    if (c->links32r) (void)hipFree(c->links32r);
     for (int k = 0; k < 2; k++)
         if (c->pinned[k]) (void)hipHostFree(c->pinned[k]);
     for (auto &e : c->events) {
@@ -312,8 +339,9 @@ wd_status wd_gauge_load(wd_ctx *c, const double *U, uint32_t flags)
     if (flags & ~1u) return set_error(WD_ERR_ARG, "unknown gauge flags 0x%x", flags);
     WD_HIP(hipSetDevice(c->device));
     const int lk64 = (flags & WD_RECON_12) ? LK_F64_12 : LK_F64_18;
-    const size_t n64 = link_bytes(lk64) * 4 * c->V, n32 = link_bytes(LK_F32_12) * 4 * c->V,
-                 n16 = link_bytes(LK_F16_12) * 4 * c->V;
+    const size_t nl = (size_t)8 * c->g.cs;  // (parity, mu) blocks of cs link slots
+    const size_t n64 = link_bytes(lk64) * nl, n32 = link_bytes(LK_F32_12) * nl,
+                 n16 = link_bytes(LK_F16_12) * nl, n32r = link_bytes(LK_F32_18) * nl;
     WD_HIP(hipStreamSynchronize(c->stream));
     if (c->links64 && c->lk64 != lk64) {
         WD_HIP(hipFree(c->links64));
@@ -331,42 +359,26 @@ wd_status wd_gauge_load(wd_ctx *c, const double *U, uint32_t flags)
     WD_TRY(alloc(&c->links64, n64));
     WD_TRY(alloc(&c->links32, n32));
     WD_TRY(alloc(&c->links16, n16));
+    WD_TRY(alloc(&c->links32r, n32r));
     c->lk64 = lk64;
     hipError_t e;
     if ((e = pack_gauge(U, c->links64, lk64, c->g, c->stream)) != hipSuccess ||
         (e = pack_gauge(U, c->links32, LK_F32_12, c->g, c->stream)) != hipSuccess ||
-        (e = pack_gauge(U, c->links16, LK_F16_12, c->g, c->stream)) != hipSuccess)
+        (e = pack_gauge(U, c->links16, LK_F16_12, c->g, c->stream)) != hipSuccess ||
+        (e = pack_gauge(U, c->links32r, LK_F32_18, c->g, c->stream)) != hipSuccess)
         return set_error(WD_ERR_HIP, "gauge packing failed: %s", hipGetErrorString(e));
     c->have_gauge = true;
     return WD_OK;
 }
 
-// Operator storage for a requested precision code.
-static wd_status prec_formats(const wd_ctx *c, int prec, int *sp, int *lk)
-{
-    const int base = prec & 0xf;
-    const bool l16 = (prec & WD_LINKS_F16) != 0;
-    if (prec & ~(0xf | WD_LINKS_F16)) return set_error(WD_ERR_ARG, "unknown precision code %d", prec);
-    if (base == WD_F64) {
-        if (l16) return set_error(WD_ERR_ARG, "FP16 links need an FP32/FP16 operator");
-        *sp = SP_F64;
-        *lk = c->lk64;
-    } else if (base == WD_F32 || base == WD_F16) {
-        *sp = (base == WD_F32) ? SP_F32 : SP_F16;
-        *lk = l16 ? LK_F16_12 : LK_F32_12;
-    } else {
-        return set_error(WD_ERR_ARG, "unknown precision %d", base);
-    }
-    return WD_OK;
-}
 
 wd_status wd_dslash(wd_ctx *c, double *out, const double *in, int out_parity, int dagger, int prec)
 {
     if (!c || !out || !in) return set_error(WD_ERR_ARG, "NULL argument");
     if (!c->have_gauge) return set_error(WD_ERR_STATE, "no gauge field loaded");
     if (out_parity < WD_FULL || out_parity > WD_ODD) return set_error(WD_ERR_ARG, "bad parity %d", out_parity);
-    int sp, lk;
-    WD_TRY(prec_formats(c, prec, &sp, &lk));
+    int sp, lk, xp;
+    WD_TRY(decode_prec(c, prec, &sp, &lk, &xp));
     WD_HIP(hipSetDevice(c->device));
     const int full = (out_parity == WD_FULL);
     Field fi, fo;
@@ -567,7 +579,7 @@ size_t wd_bytes_required(const int32_t dims[4], int nrhs, const wd_solver_params
     wd_solver_defaults(&d);
     if (!p) p = &d;
     const size_t Vh = (size_t)V / 2;
-    size_t links = (144 + 48 + 24) * 4 * (size_t)V;
+    size_t links = (144 + 48 + 24 + 72) * 4 * (size_t)V;
     const int sp = p->prec_sloppy & 0xf;
     const size_t nsub = p->eo ? 1 : 2;
     // FP64: b, x, r, two temporaries and Ap

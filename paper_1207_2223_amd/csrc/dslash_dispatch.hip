@@ -1,0 +1,32 @@
+// Stencil launch dispatch over spinor precision and dagger.
+#include "wd_internal.h"
+
+namespace wd {
+
+hipError_t dslash_launch_f64_d0(const DslashArgs &a, int lk, int nr, int rl, int epi, int block, int grid, hipStream_t s);
+hipError_t dslash_launch_f64_d1(const DslashArgs &a, int lk, int nr, int rl, int epi, int block, int grid, hipStream_t s);
+hipError_t dslash_launch_f32_d0(const DslashArgs &a, int lk, int nr, int rl, int epi, int block, int grid, hipStream_t s);
+hipError_t dslash_launch_f32_d1(const DslashArgs &a, int lk, int nr, int rl, int epi, int block, int grid, hipStream_t s);
+hipError_t dslash_launch_f16_d0(const DslashArgs &a, int lk, int nr, int rl, int epi, int block, int grid, hipStream_t s);
+hipError_t dslash_launch_f16_d1(const DslashArgs &a, int lk, int nr, int rl, int epi, int block, int grid, hipStream_t s);
+
+hipError_t dslash_launch(const DslashArgs &a, int sp, int lk, int nr, int rl, int dag, int epi, int block,
+                         int grid, hipStream_t s)
+{
+    if (sp == SP_F64) return dag ? dslash_launch_f64_d1(a, lk, nr, rl, epi, block, grid, s)
+                         : dslash_launch_f64_d0(a, lk, nr, rl, epi, block, grid, s);
+    if (sp == SP_F32) return dag ? dslash_launch_f32_d1(a, lk, nr, rl, epi, block, grid, s)
+                         : dslash_launch_f32_d0(a, lk, nr, rl, epi, block, grid, s);
+    if (sp == SP_F16) return dag ? dslash_launch_f16_d1(a, lk, nr, rl, epi, block, grid, s)
+                         : dslash_launch_f16_d0(a, lk, nr, rl, epi, block, grid, s);
+    return hipErrorInvalidValue;
+}
+
+bool dslash_shape_supported(int sp, int nr, int rl)
+{
+    if (rl != 1 && rl != 2 && rl != 4) return false;
+    if (sp == SP_F64) return nr == 1 || nr == 2;
+    return nr >= 1 && nr <= 4;
+}
+
+}  // namespace wd

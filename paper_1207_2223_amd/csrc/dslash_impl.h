@@ -1,12 +1,16 @@
 // dslash_impl.h -- the even-odd Wilson hopping stencil (D_eo / D_oe and their
 // adjoints) as one templated gfx950 kernel, with fused epilogues.
 //
-// One thread computes one output site for NR right-hand sides: for each of
-// the 8 directions it loads the link once (reconstructing row 3 from 12
-// reals if compressed), then for every RHS loads the neighbour spinor,
-// projects it to a half spinor with (1 -+ gamma_mu), applies U or U^dag to
-// the two colour vectors and accumulates the rebuilt 4-spinor.  Arithmetic is
-// FP64 for FP64 fields and FP32 otherwise.
+// Work mapping: RL consecutive lanes share one output site and each lane
+// carries NR right-hand sides in registers, so one link load (and its 12-real
+// reconstruction) serves NR RHS per lane, and the RL lanes that ask for the
+// same link address are merged into one memory request.  A work-group covers
+// blockDim/RL sites for RL*NR RHS.  For each of the 8 directions a lane loads
+// the link once, then per RHS loads the neighbour spinor, projects it to a
+// half spinor with (1 -+ gamma_mu), applies U or U^dag to the two colour
+// vectors and accumulates the rebuilt 4-spinor.  FP64 fields use FP64
+// arithmetic, FP32 / FP16 fields FP32 arithmetic (FP16 values are projected
+// first and scaled by their site norm after).
 //
 // Epilogues:
 //   EPI_PLAIN  out = D in
@@ -14,13 +18,34 @@
 //   EPI_CGUPD  Ap  = x + coef[rid] * D in;  xs += alpha p;  r -= alpha Ap
 //              (+ |r|^2 partial sums) -- the last sweep of Mhat^dag Mhat p
 //              fused with the CG vector updates.
-// Partial sums are per 64-site wavefront (independent of block size and of
-// NR), so every launch shape gives bitwise-identical results.
+// Partial sums cover 16 consecutive sites of one RHS and are formed with the
+// same pairing tree for every (NR, RL, block) choice, so every launch shape
+// gives bitwise-identical vectors and norms.
 #pragma once
 
 #include "wd_internal.h"
 
 namespace wd {
+
+// Neighbour spinor in compute precision.  For FP16 the per-site norm is
+// returned separately (scale) so that it can be applied after projection.
+template <int SP, typename real>
+__device__ __forceinline__ real load_nb(const char *f, int cs, int j, real v[24])
+{
+    if constexpr (SP == SP_F16) {
+        const half8_t *p = reinterpret_cast<const half8_t *>(f);
+#pragma unroll
+        for (int k = 0; k < 3; k++) {
+            half8_t w = p[(size_t)k * cs + j];
+#pragma unroll
+            for (int q = 0; q < 8; q++) v[8 * k + q] = (real)(float)w[q];
+        }
+        return (real)reinterpret_cast<const float *>(f + (size_t)48 * cs)[j];
+    } else {
+        SpinorIO<SP>::load(f, cs, j, v);
+        return (real)1;
+    }
+}
 
 template <int MU, int SP, int LK, int NR, bool DAG, typename real>
 __device__ __forceinline__ void hop_dir(const DslashArgs &a, int i, const int c[4],
@@ -28,52 +53,88 @@ __device__ __forceinline__ void hop_dir(const DslashArgs &a, int i, const int c[
 {
     constexpr int SF = DAG ? +1 : -1;  // forward: (1 - g) for H, (1 + g) for H^dag
     constexpr int SB = -SF;            // backward: the opposite projector
-    const int Vh = a.g.Vh;
+    const int cs = a.g.cs;
     real u[18];
     {
         const int j = neighbour<MU, +1>(a.g, i, c);
-        LinkIO<LK>::load(a.links, Vh, a.P * 4 + MU, i, u);
+        LinkIO<LK>::load(a.links, cs, a.P * 4 + MU, i, u);
 #pragma unroll
         for (int r = 0; r < NR; r++) {
             if (!rv[r]) continue;
             real v[24], h[12], w[12];
-            SpinorIO<SP>::load(a.in + rid[r] * a.in_rs, Vh, j, v);
+            const real sc = load_nb<SP>(a.in + rid[r] * a.in_rs, cs, j, v);
             project<MU, SF>(v, h);
+            if constexpr (SP == SP_F16) {
+#pragma unroll
+                for (int k = 0; k < 12; k++) h[k] *= sc;
+            }
             su3_mul_half<false>(u, h, w);
             accumulate<MU, SF>(acc[r], w);
         }
     }
     {
         const int j = neighbour<MU, -1>(a.g, i, c);
-        LinkIO<LK>::load(a.links, Vh, (1 - a.P) * 4 + MU, j, u);
+        LinkIO<LK>::load(a.links, cs, (1 - a.P) * 4 + MU, j, u);
 #pragma unroll
         for (int r = 0; r < NR; r++) {
             if (!rv[r]) continue;
             real v[24], h[12], w[12];
-            SpinorIO<SP>::load(a.in + rid[r] * a.in_rs, Vh, j, v);
+            const real sc = load_nb<SP>(a.in + rid[r] * a.in_rs, cs, j, v);
             project<MU, SB>(v, h);
+            if constexpr (SP == SP_F16) {
+#pragma unroll
+                for (int k = 0; k < 12; k++) h[k] *= sc;
+            }
             su3_mul_half<true>(u, h, w);
             accumulate<MU, SB>(acc[r], w);
         }
     }
 }
 
-template <int SP, int LK, int NR, bool DAG, int EPI, int XP>
+// Sum over the 16 sites of a site group for lanes of equal RHS slot
+// (lane = site * RL + slot): the same pairing tree for every RL.
+template <int RL>
+__device__ __forceinline__ double group16_sum(double v)
+{
+#pragma unroll
+    for (int off = 8 * RL; off >= RL; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+template <int SP, int LK, int NR, int RL, bool DAG, int EPI, int XP>
 __global__ void __launch_bounds__(256) dslash_kernel(DslashArgs a)
 {
     typedef typename SpinorIO<SP>::real real;
     static_assert(sizeof(typename LinkIO<LK>::real) == sizeof(real), "link/spinor precision pair");
-    const int L = a.remap ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
-    const int tile = L / a.G, grp = L - tile * a.G;
-    const int i = tile * blockDim.x + threadIdx.x;
-    const int Vh = a.g.Vh;
+    int tile, grp;
+    if (a.remap == 2) {
+        // XCD x (= block id mod 8, the dispatch round-robin) owns z-planes
+        // [x*nzl, (x+1)*nzl) for all t; its j-th block takes RHS group
+        // j mod G of the (j / G)-th tile in (t, z, tile-in-plane) order,
+        // z fastest among planes, so the t and z neighbours of a tile were
+        // read a few tiles earlier on the same XCD (same L2).
+        const int x = blockIdx.x & 7, j = blockIdx.x >> 3;
+        const int sidx = j / a.G;
+        grp = j - sidx * a.G;
+        const int q = sidx % a.tpp, zt = sidx / a.tpp;
+        const int zl = zt % a.nzl, t = zt / a.nzl;
+        tile = ((t * a.g.L[2]) + x * a.nzl + zl) * a.tpp + q;
+    } else {
+        const int L = a.remap ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+        tile = L / a.G;
+        grp = L - tile * a.G;
+    }
+    const int spb = blockDim.x / RL;
+    const int i = tile * spb + (int)threadIdx.x / RL;
+    const int lr = (int)threadIdx.x % RL;
+    const int Vh = a.g.Vh, cs = a.g.cs;
     const bool live = i < Vh;
 
     int rid[NR];
     bool rv[NR];
 #pragma unroll
     for (int r = 0; r < NR; r++) {
-        const int slot = grp * NR + r;
+        const int slot = (grp * RL + lr) * NR + r;
         rv[r] = slot < a.nact;
         rid[r] = rv[r] ? a.active[slot] : 0;
     }
@@ -98,70 +159,68 @@ __global__ void __launch_bounds__(256) dslash_kernel(DslashArgs a)
         double nrm = 0.0;
         if (live && rv[r]) {
             if (EPI == EPI_PLAIN) {
-                SpinorIO<SP>::store(a.out + rid[r] * a.out_rs, Vh, i, acc[r]);
+                SpinorIO<SP>::store(a.out + rid[r] * a.out_rs, cs, i, acc[r]);
             } else if (EPI == EPI_XPAY) {
                 const real cf = (real)a.coef[rid[r]];
                 real xv[24];
-                SpinorIO<SP>::load(a.x + rid[r] * a.x_rs, Vh, i, xv);
+                SpinorIO<SP>::load(a.x + rid[r] * a.x_rs, cs, i, xv);
 #pragma unroll
                 for (int k = 0; k < 24; k++) {
-                    xv[k] += cf * acc[r][k];
-                    nrm += (double)xv[k] * (double)xv[k];
+                    xv[k] = fmaT(cf, acc[r][k], xv[k]);
+                    nrm = fmaT((double)xv[k], (double)xv[k], nrm);
                 }
-                SpinorIO<SP>::store(a.out + rid[r] * a.out_rs, Vh, i, xv);
+                SpinorIO<SP>::store(a.out + rid[r] * a.out_rs, cs, i, xv);
             } else {
                 const real cf = (real)a.coef[rid[r]];
                 const real al = (real)a.alpha[rid[r]];
                 real ap[24], pv[24], rv_[24];
                 typename SpinorIO<XP>::real xv[24];
-                SpinorIO<SP>::load(a.x + rid[r] * a.x_rs, Vh, i, ap);
-                SpinorIO<SP>::load(a.p + rid[r] * a.p_rs, Vh, i, pv);
-                SpinorIO<SP>::load(a.r + rid[r] * a.r_rs, Vh, i, rv_);
-                SpinorIO<XP>::load(a.xs + rid[r] * a.xs_rs, Vh, i, xv);
+                SpinorIO<SP>::load(a.x + rid[r] * a.x_rs, cs, i, ap);
+                SpinorIO<SP>::load(a.p + rid[r] * a.p_rs, cs, i, pv);
+                SpinorIO<SP>::load(a.r + rid[r] * a.r_rs, cs, i, rv_);
+                SpinorIO<XP>::load(a.xs + rid[r] * a.xs_rs, cs, i, xv);
+                typedef typename SpinorIO<XP>::real xreal;
 #pragma unroll
                 for (int k = 0; k < 24; k++) {
-                    ap[k] += cf * acc[r][k];
-                    xv[k] += (typename SpinorIO<XP>::real)(al * pv[k]);
-                    rv_[k] -= al * ap[k];
-                    nrm += (double)rv_[k] * (double)rv_[k];
+                    ap[k] = fmaT(cf, acc[r][k], ap[k]);
+                    xv[k] = fmaT((xreal)al, (xreal)pv[k], xv[k]);
+                    rv_[k] = fmaT(-al, ap[k], rv_[k]);
+                    nrm = fmaT((double)rv_[k], (double)rv_[k], nrm);
                 }
-                SpinorIO<XP>::store(a.xs + rid[r] * a.xs_rs, Vh, i, xv);
-                SpinorIO<SP>::store(a.r + rid[r] * a.r_rs, Vh, i, rv_);
+                SpinorIO<XP>::store(a.xs + rid[r] * a.xs_rs, cs, i, xv);
+                SpinorIO<SP>::store(a.r + rid[r] * a.r_rs, cs, i, rv_);
             }
         }
-        if (a.partial != nullptr && EPI != EPI_PLAIN) {
-            const double s = wave_sum(nrm);
-            if ((threadIdx.x & 63) == 0 && i < Vh && rv[r])
-                a.partial[(size_t)rid[r] * a.pstride + a.pw_off + (i >> 6)] = s;
+        if (EPI != EPI_PLAIN && a.partial != nullptr) {
+            const double s = group16_sum<RL>(nrm);
+            if ((i & 15) == 0 && i < Vh && rv[r] && ((int)threadIdx.x % (16 * RL)) < RL)
+                a.partial[(size_t)rid[r] * a.pstride + a.pw_off + (i >> 4)] = s;
         }
     }
 }
 
-// Runtime -> template dispatch for one (SP, XP) pair over link format, NR,
-// dagger and epilogue.
-#define WD_DSL_EPI(SP_, LK_, NR_, DAG_, XP_)                                                     \
+// Runtime -> template dispatch for one (SP, XP) pair.
+#define WD_DSL_EPI(SP_, LK_, NR_, RL_, DAG_, XP_)                                                \
     switch (epi) {                                                                                \
     case EPI_PLAIN:                                                                               \
-        hipLaunchKernelGGL((dslash_kernel<SP_, LK_, NR_, DAG_, EPI_PLAIN, XP_>), dim3(grid),      \
+        hipLaunchKernelGGL((dslash_kernel<SP_, LK_, NR_, RL_, DAG_, EPI_PLAIN, XP_>), dim3(grid),  \
                            dim3(block), 0, s, a);                                                 \
         return hipGetLastError();                                                                 \
     case EPI_XPAY:                                                                                \
-        hipLaunchKernelGGL((dslash_kernel<SP_, LK_, NR_, DAG_, EPI_XPAY, XP_>), dim3(grid),       \
+        hipLaunchKernelGGL((dslash_kernel<SP_, LK_, NR_, RL_, DAG_, EPI_XPAY, XP_>), dim3(grid),   \
                            dim3(block), 0, s, a);                                                 \
         return hipGetLastError();                                                                 \
     case EPI_CGUPD:                                                                               \
-        hipLaunchKernelGGL((dslash_kernel<SP_, LK_, NR_, DAG_, EPI_CGUPD, XP_>), dim3(grid),      \
+        hipLaunchKernelGGL((dslash_kernel<SP_, LK_, NR_, RL_, DAG_, EPI_CGUPD, XP_>), dim3(grid),  \
                            dim3(block), 0, s, a);                                                 \
         return hipGetLastError();                                                                 \
     default:                                                                                      \
         return hipErrorInvalidValue;                                                              \
     }
 
-#define WD_DSL_DAG(SP_, LK_, NR_, XP_)                                                           \
-    if (dag) {                                                                                    \
-        WD_DSL_EPI(SP_, LK_, NR_, true, XP_)                                                      \
-    } else {                                                                                      \
-        WD_DSL_EPI(SP_, LK_, NR_, false, XP_)                                                     \
+#define WD_DSL_SHAPE(SP_, LK_, NR_, RL_, DAG_, XP_)                                              \
+    if (nr == NR_ && rl == RL_) {                                                                 \
+        WD_DSL_EPI(SP_, LK_, NR_, RL_, DAG_, XP_)                                                 \
     }
 
 }  // namespace wd

@@ -38,22 +38,29 @@ __global__ void __launch_bounds__(kBlock) k_pack_gauge(const double *U, char *ds
     lex_to_eo(g, lex, &P, &cb);
     const double *u = U + idx * 18;
     const int blk = P * 4 + mu;
-    const size_t Vh = g.Vh;
+    const size_t cs = g.cs;
     if (LK == LK_F64_18 || LK == LK_F64_12) {
         const int nch = (LK == LK_F64_18) ? 9 : 6;
-        double2 *d = reinterpret_cast<double2 *>(dst) + (size_t)blk * nch * Vh;
-        for (int k = 0; k < nch; k++) d[k * Vh + cb] = make_double2(u[2 * k], u[2 * k + 1]);
+        double2 *d = reinterpret_cast<double2 *>(dst) + (size_t)blk * nch * cs;
+        for (int k = 0; k < nch; k++) d[k * cs + cb] = make_double2(u[2 * k], u[2 * k + 1]);
     } else if (LK == LK_F32_12) {
-        float4 *d = reinterpret_cast<float4 *>(dst) + (size_t)blk * 3 * Vh;
+        float4 *d = reinterpret_cast<float4 *>(dst) + (size_t)blk * 3 * cs;
         for (int k = 0; k < 3; k++)
-            d[k * Vh + cb] = make_float4((float)u[4 * k], (float)u[4 * k + 1], (float)u[4 * k + 2],
+            d[k * cs + cb] = make_float4((float)u[4 * k], (float)u[4 * k + 1], (float)u[4 * k + 2],
                                          (float)u[4 * k + 3]);
+    } else if (LK == LK_F32_18) {
+        float4 *d = reinterpret_cast<float4 *>(dst) + (size_t)blk * 4 * cs;
+        for (int k = 0; k < 4; k++)
+            d[k * cs + cb] = make_float4((float)u[4 * k], (float)u[4 * k + 1], (float)u[4 * k + 2],
+                                         (float)u[4 * k + 3]);
+        float2 *q = reinterpret_cast<float2 *>(reinterpret_cast<float4 *>(dst) + 32 * cs) + (size_t)blk * cs;
+        q[cb] = make_float2((float)u[16], (float)u[17]);
     } else {
-        half4_t *d = reinterpret_cast<half4_t *>(dst) + (size_t)blk * 3 * Vh;
+        half4_t *d = reinterpret_cast<half4_t *>(dst) + (size_t)blk * 3 * cs;
         for (int k = 0; k < 3; k++) {
             half4_t w;
             for (int j = 0; j < 4; j++) w[j] = (_Float16)u[4 * k + j];
-            d[k * Vh + cb] = w;
+            d[k * cs + cb] = w;
         }
     }
 }
@@ -73,7 +80,7 @@ __global__ void __launch_bounds__(kBlock) k_pack_spinor(const double *src, char 
     double v[24];
     const double *p = src + ((long long)rid * n + s) * 24;
     for (int k = 0; k < 24; k++) v[k] = p[k];
-    SpinorIO<SP>::store(base + rid * rs + P * ss, g.Vh, cb, v);
+    SpinorIO<SP>::store(base + rid * rs + P * ss, g.cs, cb, v);
 }
 
 template <int SP>
@@ -88,7 +95,7 @@ __global__ void __launch_bounds__(kBlock) k_unpack_spinor(const char *base, long
     int P = 0, cb = (int)s;
     if (mode) lex_to_eo(g, s, &P, &cb);
     double v[24];
-    SpinorIO<SP>::load(base + rid * rs + P * ss, g.Vh, cb, v);
+    SpinorIO<SP>::load(base + rid * rs + P * ss, g.cs, cb, v);
     double *p = dst + ((long long)rid * n + s) * 24;
     for (int k = 0; k < 24; k++) p[k] = v[k];
 }
@@ -139,6 +146,7 @@ hipError_t pack_gauge(const double *U, char *dst, int lk, const Geom &g, hipStre
     case LK_F64_12: hipLaunchKernelGGL(k_pack_gauge<LK_F64_12>, gr, dim3(kBlock), 0, s, U, dst, g); break;
     case LK_F32_12: hipLaunchKernelGGL(k_pack_gauge<LK_F32_12>, gr, dim3(kBlock), 0, s, U, dst, g); break;
     case LK_F16_12: hipLaunchKernelGGL(k_pack_gauge<LK_F16_12>, gr, dim3(kBlock), 0, s, U, dst, g); break;
+    case LK_F32_18: hipLaunchKernelGGL(k_pack_gauge<LK_F32_18>, gr, dim3(kBlock), 0, s, U, dst, g); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -19,6 +19,9 @@
 // the sloppy residual claims convergence, the FP64 solution is advanced and
 // the residual is recomputed as b - A x in FP64 (reliable update).
 // Convergence is declared only on that FP64 true residual.
+#include <stdio.h>
+#include <stdlib.h>
+
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -83,7 +86,7 @@ wd_status apply_A(const Ops &o, int sp, int lk, const Field &in, const Field &ou
                 sw.out = sub_view(dst, P);
                 sw.partial = (norm && pass == 0) ? o.s.partial : nullptr;
                 sw.pstride = o.s.pstride;
-                sw.pw_off = P * nwaves_of((int)c->Vh);
+                sw.pw_off = P * ngroups_of((int)c->Vh);
                 WD_TRY(run_sweep(c, sw, o.cfg));
             }
         }
@@ -118,26 +121,21 @@ extern "C" wd_status wd_cg_solve(wd_ctx *c, double *x, const double *phi, int nr
     if (!(p.tol > 0) || p.maxiter < 0 || p.poll < 1 || !(p.delta > 0 && p.delta < 1))
         return set_error(WD_ERR_ARG, "bad solver parameters (tol %g maxiter %d poll %d delta %g)",
                          p.tol, p.maxiter, p.poll, p.delta);
-    const int base = p.prec_sloppy & 0xf;
-    const bool l16 = (p.prec_sloppy & WD_LINKS_F16) != 0;
-    if ((p.prec_sloppy & ~(0xf | WD_LINKS_F16)) || base > WD_F16 || (base == WD_F64 && l16))
-        return set_error(WD_ERR_ARG, "bad sloppy precision %d", p.prec_sloppy);
-    if (!p.eo && base != WD_F64)
+    int sp, lk, xp;
+    WD_TRY(decode_prec(c, p.prec_sloppy, &sp, &lk, &xp));
+    if (!p.eo && sp != SP_F64)
         return set_error(WD_ERR_ARG, "the full-lattice solver runs in FP64 only");
     for (int j = 0; j < nrhs; j++)
         if (!std::isfinite(kappa[j])) return set_error(WD_ERR_ARG, "kappa[%d] not finite", j);
     WD_HIP(hipSetDevice(c->device));
 
-    const int sp = base == WD_F64 ? SP_F64 : (base == WD_F32 ? SP_F32 : SP_F16);
-    const int lk = sp == SP_F64 ? c->lk64 : (l16 ? LK_F16_12 : LK_F32_12);
-    const int xp = sp == SP_F64 ? SP_F64 : SP_F32;
     const bool mixed = sp != SP_F64;
     const int nsub = p.eo ? 1 : 2;
     const int Vh = (int)c->Vh;
     const hipStream_t s = c->stream;
 
     // scalars: bb, rr, alpha, beta, coef1, coef2 (nrhs each) + partials
-    const int nw1 = nwaves_of(Vh);
+    const int nw1 = ngroups_of(Vh);
     const int pstride = 2 * nw1 + 1;
     std::vector<double> hc1(nrhs), hc2(nrhs);
     for (int j = 0; j < nrhs; j++) {
@@ -146,18 +144,26 @@ extern "C" wd_status wd_cg_solve(wd_ctx *c, double *x, const double *phi, int nr
     }
     Scalars sc;
     void *vp;
-    WD_TRY(ws_get(c, "cg_scal", sizeof(double) * 4 * nrhs, &vp));
+    WD_TRY(ws_get(c, "cg_scal", sizeof(double) * 6 * nrhs, &vp));
     sc.bb = (double *)vp;
     sc.rr = sc.bb + nrhs;
     sc.alpha = sc.rr + nrhs;
     sc.beta = sc.alpha + nrhs;
+    double *dre = sc.beta + nrhs, *dim = dre + nrhs;  // <r, p> after a reliable update
     WD_TRY(upload_doubles(c, "cg_coef1", hc1.data(), nrhs, &sc.coef1));
     WD_TRY(upload_doubles(c, "cg_coef2", hc2.data(), nrhs, &sc.coef2));
-    WD_TRY(ws_get(c, "cg_partial", sizeof(double) * pstride * nrhs, &vp));
+    WD_TRY(ws_get(c, "cg_partial", sizeof(double) * pstride * nrhs * 2, &vp));
     sc.partial = (double *)vp;
+    double *partial2 = sc.partial + (size_t)pstride * nrhs;
     sc.pstride = pstride;
-    const TuneCfg *cfg = nullptr;
+    const TuneCfg *cfg = nullptr;  // per-sweep shapes come from the tuner when p.tuned
     Ops o{c, p.eo, sc, cfg};
+    struct TunedScope {
+        wd_ctx *c;
+        bool old;
+        ~TunedScope() { c->use_tuned = old; }
+    } tscope{c, c->use_tuned};
+    c->use_tuned = p.tuned != 0;
 
     // fields
     Field b64, x64, r64, to64, te64, Ap64;
@@ -191,7 +197,7 @@ extern "C" wd_status wd_cg_solve(wd_ctx *c, double *x, const double *phi, int nr
     hipError_t e;
     if ((e = pack_spinor(phi, b64, nrhs, p.eo ? 0 : 1, c->g, s)) != hipSuccess)
         return set_error(WD_ERR_HIP, "pack: %s", hipGetErrorString(e));
-    const int nwF = p.eo ? nw1 : nwaves_of(2 * Vh);  // BLAS partial count
+    const int nwF = p.eo ? nw1 : ngroups_of(2 * Vh);  // BLAS partial count
     const int nwD = p.eo ? nw1 : 2 * nw1;            // stencil partial count
     HIPCHK(blas_norm(b64, Vh, act_all, nrhs, sc.partial, pstride, s));
     HIPCHK(blas_finalize(sc.partial, pstride, nwF, act_all, nrhs, FIN_STORE, sc.rr, sc.alpha, sc.beta, sc.bb, s));
@@ -209,7 +215,8 @@ extern "C" wd_status wd_cg_solve(wd_ctx *c, double *x, const double *phi, int nr
     hbuf = (double *)vp;
     HIPCHK(hipMemcpyAsync(hbuf, sc.bb, sizeof(double) * nrhs, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
-    std::vector<double> bb(hbuf, hbuf + nrhs), maxrr(nrhs), rrh(nrhs);
+    std::vector<double> bb(hbuf, hbuf + nrhs), maxrr(nrhs), rrh(nrhs), prevtrue(hbuf, hbuf + nrhs);
+    std::vector<int> restart;
     std::vector<int> iters(nrhs, 0), rus(nrhs, 0), status(nrhs, WD_ERR_NOCONV);
     std::vector<double> tres(nrhs, 0.0);
     std::vector<int> active;
@@ -225,6 +232,9 @@ extern "C" wd_status wd_cg_solve(wd_ctx *c, double *x, const double *phi, int nr
         }
     }
     const double tol2 = p.tol * p.tol, d2 = p.delta * p.delta;
+    // WD_SOLVER_TRACE=1 prints the residual history to stderr (diagnostics)
+    const char *trace_env = getenv("WD_SOLVER_TRACE");
+    const bool trace = trace_env && trace_env[0] == '1';
 
     auto upload_active = [&](const std::vector<int> &v, const char *name, int **dev) -> wd_status {
         return upload_ints(c, name, v.data(), (int)v.size(), dev);
@@ -232,16 +242,25 @@ extern "C" wd_status wd_cg_solve(wd_ctx *c, double *x, const double *phi, int nr
     WD_TRY(upload_active(active, "cg_act", &act));
 
     // reliable update of the listed RHS: x64 += xs, r64 = b - A x64 (FP64),
-    // rr = |r64|^2, rs = r64.  Returns the new rr in rrh.
+    // rr = |r64|^2, rs = r64.  The search direction p = r + beta p_old was
+    // built from the replaced residual; it is rebuilt as r_new + q with
+    // q = p - r_old = beta p_old made orthogonal to r_new
+    // (q -= <r_new, q> / <r_new, r_new> r_new).  Returns the new rr in rrh.
     auto reliable = [&](const std::vector<int> &ids) -> wd_status {
         if (ids.empty()) return WD_OK;
         WD_TRY(upload_active(ids, "cg_act_ru", &act_ru));
         const int n = (int)ids.size();
+        HIPCHK(blas_axpy_const(ps, rs, -1.0, Vh, act_ru, n, s));
         if (mixed) HIPCHK(blas_add_zero(x64, xs, Vh, act_ru, n, s));
         WD_TRY(apply_A(o, SP_F64, c->lk64, x64, Ap64, to64, te64, act_ru, n, false));
         HIPCHK(blas_resid(r64, b64, Ap64, Vh, act_ru, n, sc.partial, pstride, s));
         HIPCHK(blas_finalize(sc.partial, pstride, nwF, act_ru, n, FIN_RR, sc.rr, sc.alpha, sc.beta, nullptr, s));
         if (mixed) HIPCHK(blas_copy(rs, r64, Vh, act_ru, n, s));
+        HIPCHK(blas_cdot(rs, ps, Vh, act_ru, n, sc.partial, partial2, pstride, s));
+        HIPCHK(blas_finalize(sc.partial, pstride, nwF, act_ru, n, FIN_STORE, sc.rr, sc.alpha, sc.beta, dre, s));
+        HIPCHK(blas_finalize(partial2, pstride, nwF, act_ru, n, FIN_STORE, sc.rr, sc.alpha, sc.beta, dim, s));
+        HIPCHK(blas_orth(ps, rs, dre, dim, sc.rr, Vh, act_ru, n, s));
+        HIPCHK(blas_axpy_const(ps, rs, 1.0, Vh, act_ru, n, s));
         HIPCHK(hipMemcpyAsync(hbuf, sc.rr, sizeof(double) * nrhs, hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
         for (int j : ids) rrh[j] = hbuf[j];
@@ -283,6 +302,8 @@ extern "C" wd_status wd_cg_solve(wd_ctx *c, double *x, const double *phi, int nr
         HIPCHK(hipMemcpyAsync(hbuf, sc.rr, sizeof(double) * nrhs, hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
         std::vector<int> ru, keep;
+        if (trace)
+            for (int j : active) fprintf(stderr, "[wd cg] it %d rhs %d sloppy |r|/|b| %.3e\n", it, j, std::sqrt(hbuf[j] / bb[j]));
         for (int j : active) {
             const double r2 = hbuf[j];
             if (!std::isfinite(r2)) {
@@ -301,6 +322,7 @@ extern "C" wd_status wd_cg_solve(wd_ctx *c, double *x, const double *phi, int nr
                 for (int q : ru)
                     if (q == j) {
                         rus[j]++;
+                        if (trace) fprintf(stderr, "[wd cg] it %d rhs %d reliable update: true |r|/|b| %.3e\n", it, j, std::sqrt(rrh[j] / bb[j]));
                         if (!std::isfinite(rrh[j])) {
                             status[j] = WD_ERR_NAN;
                             done = true;
@@ -310,11 +332,23 @@ extern "C" wd_status wd_cg_solve(wd_ctx *c, double *x, const double *phi, int nr
                             done = true;
                         } else {
                             maxrr[j] = rrh[j];
+                            // a replacement that did not halve the true residual
+                            // means the sloppy iteration has stalled: restart
+                            if (rrh[j] > 0.25 * prevtrue[j]) restart.push_back(j);
+                            prevtrue[j] = rrh[j];
                         }
                     }
                 if (!done) keep2.push_back(j);
             }
             keep.swap(keep2);
+            if (!restart.empty()) {
+                int *act_rs;
+                WD_TRY(upload_active(restart, "cg_act_rs", &act_rs));
+                HIPCHK(blas_copy(ps, rs, Vh, act_rs, (int)restart.size(), s));
+                if (trace)
+                    for (int j : restart) fprintf(stderr, "[wd cg] it %d rhs %d restart p = r\n", it, j);
+                restart.clear();
+            }
         }
         if (keep.size() != active.size()) {
             active.swap(keep);

@@ -1,0 +1,392 @@
+// tune.hip -- launch-shape autotuner for the stencil sweeps of the solver and
+// a stencil micro-benchmark.
+//
+// For each sweep the even-odd CG issues (plain D_oe, xpay+norm D_eo, plain
+// D_oe^dag, fused CG-update D_eo^dag) in a given precision and RHS count, the
+// tuner times every supported (block, RHS per lane, lanes per site, XCD
+// remap) shape with HIP events on synthetic fields, re-runs each shape on
+// identical inputs and rejects it unless its vectors and norm partials are
+// bitwise identical to the reference shape, and keeps the fastest in the
+// context.  Solves with wd_solver_params.tuned = 1 use the kept shapes.
+#include <stdio.h>
+#include <stdlib.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "wd_internal.h"
+
+namespace wd {
+
+namespace {
+
+constexpr int kBlock = 256;
+
+// deterministic pseudo-random fill in [-1, 1) (splitmix-style hash of the index)
+template <int SP>
+__global__ void __launch_bounds__(kBlock) k_fill(char *base, long long rs, int Vh, int cs, int nrhs,
+                                                  unsigned seed)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    const int rid = blockIdx.y;
+    if (i >= Vh || rid >= nrhs) return;
+    double v[24];
+    for (int k = 0; k < 24; k++) {
+        unsigned long long z = ((unsigned long long)seed << 40) ^ ((unsigned long long)rid << 32) ^
+                               ((unsigned long long)i * 24 + k);
+        z += 0x9E3779B97F4A7C15ull;
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        z ^= z >> 31;
+        v[k] = (double)(z >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+    }
+    SpinorIO<SP>::store(base + rid * rs, cs, i, v);
+}
+
+__global__ void __launch_bounds__(kBlock) k_count_diff(const unsigned *a, const unsigned *b,
+                                                        long long n, unsigned *count)
+{
+    const long long i = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n && a[i] != b[i]) atomicAdd(count, 1u);
+}
+
+hipError_t fill(const Field &f, int Vh, int nrhs, unsigned seed, hipStream_t s)
+{
+    dim3 gr((Vh + kBlock - 1) / kBlock, nrhs);
+    switch (f.sp) {
+    case SP_F64: hipLaunchKernelGGL(k_fill<SP_F64>, gr, dim3(kBlock), 0, s, f.base, f.rs, Vh, f.cs, nrhs, seed); break;
+    case SP_F32: hipLaunchKernelGGL(k_fill<SP_F32>, gr, dim3(kBlock), 0, s, f.base, f.rs, Vh, f.cs, nrhs, seed); break;
+    default: hipLaunchKernelGGL(k_fill<SP_F16>, gr, dim3(kBlock), 0, s, f.base, f.rs, Vh, f.cs, nrhs, seed); break;
+    }
+    return hipGetLastError();
+}
+
+std::string sweep_key(int sp, int lk, int dag, int epi)
+{
+    char b[64];
+    snprintf(b, sizeof(b), "%d/%d/%d/%d", sp, lk, dag, epi);
+    return b;
+}
+
+}  // namespace
+
+const TuneCfg *tuned_cfg(const wd_ctx *c, const Sweep &sw)
+{
+    auto it = c->tuned.find(sweep_key(sw.sp, sw.lk, sw.dag, sw.epi));
+    return it == c->tuned.end() ? nullptr : &it->second;
+}
+
+}  // namespace wd
+
+using namespace wd;
+
+#define HIPCHK(expr)                                                                               \
+    do {                                                                                          \
+        hipError_t e__ = (expr);                                                                  \
+        if (e__ != hipSuccess)                                                                    \
+            return set_error(WD_ERR_HIP, "%s: %s (%s:%d)", #expr, hipGetErrorString(e__), __FILE__, __LINE__); \
+    } while (0)
+
+static wd_status prec_decode(const wd_ctx *c, int prec, int *sp, int *lk, int *xp)
+{
+    return decode_prec(c, prec, sp, lk, xp);
+}
+
+struct TuneFields {
+    Field in, out, x, p, xs, r, xs0, r0, outref, xsref, rref;
+    double *coef, *alpha, *partial, *pref;
+    int *act;
+    int pstride;
+};
+
+static wd_status tune_fields(wd_ctx *c, int sp, int xp, int nrhs, TuneFields *t)
+{
+    WD_TRY(alloc_field(c, "tn_in", sp, 1, nrhs, &t->in));
+    WD_TRY(alloc_field(c, "tn_out", sp, 1, nrhs, &t->out));
+    WD_TRY(alloc_field(c, "tn_x", sp, 1, nrhs, &t->x));
+    WD_TRY(alloc_field(c, "tn_p", sp, 1, nrhs, &t->p));
+    WD_TRY(alloc_field(c, "tn_r", sp, 1, nrhs, &t->r));
+    WD_TRY(alloc_field(c, "tn_r0", sp, 1, nrhs, &t->r0));
+    WD_TRY(alloc_field(c, "tn_rref", sp, 1, nrhs, &t->rref));
+    WD_TRY(alloc_field(c, "tn_outref", sp, 1, nrhs, &t->outref));
+    WD_TRY(alloc_field(c, "tn_xs", xp, 1, nrhs, &t->xs));
+    WD_TRY(alloc_field(c, "tn_xs0", xp, 1, nrhs, &t->xs0));
+    WD_TRY(alloc_field(c, "tn_xsref", xp, 1, nrhs, &t->xsref));
+    const int Vh = (int)c->Vh;
+    t->pstride = 2 * ngroups_of(Vh) + 1;
+    std::vector<double> cf(nrhs), al(nrhs);
+    std::vector<int> ids(nrhs);
+    for (int j = 0; j < nrhs; j++) {
+        cf[j] = -0.0243 - 0.0001 * j;  // about -kappa^2
+        al[j] = 0.37 + 0.01 * j;
+        ids[j] = j;
+    }
+    WD_TRY(upload_doubles(c, "tn_coef", cf.data(), nrhs, &t->coef));
+    WD_TRY(upload_doubles(c, "tn_alpha", al.data(), nrhs, &t->alpha));
+    WD_TRY(upload_ints(c, "tn_act", ids.data(), nrhs, &t->act));
+    void *vp;
+    WD_TRY(ws_get(c, "tn_partial", sizeof(double) * t->pstride * nrhs, &vp));
+    t->partial = (double *)vp;
+    WD_TRY(ws_get(c, "tn_pref", sizeof(double) * t->pstride * nrhs, &vp));
+    t->pref = (double *)vp;
+    hipStream_t s = c->stream;
+    HIPCHK(fill(t->in, Vh, nrhs, 1, s));
+    HIPCHK(fill(t->x, Vh, nrhs, 2, s));
+    HIPCHK(fill(t->p, Vh, nrhs, 3, s));
+    HIPCHK(fill(t->r0, Vh, nrhs, 4, s));
+    HIPCHK(fill(t->xs0, Vh, nrhs, 5, s));
+    HIPCHK(hipMemsetAsync(t->partial, 0, sizeof(double) * t->pstride * nrhs, s));
+    return WD_OK;
+}
+
+// Bytes of the result fields of one sweep kind (for bitwise comparison).
+static wd_status compare(wd_ctx *c, const char *a, const char *b, size_t bytes, unsigned *dcount,
+                         unsigned *nd)
+{
+    hipStream_t s = c->stream;
+    HIPCHK(hipMemsetAsync(dcount, 0, sizeof(unsigned), s));
+    const long long n = (long long)(bytes / 4);
+    if (n > 0)
+        hipLaunchKernelGGL(k_count_diff, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
+                           (const unsigned *)a, (const unsigned *)b, n, dcount);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(nd, dcount, sizeof(unsigned), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return WD_OK;
+}
+
+// Tuning cache: a text file named by the environment variable
+// WD_TUNE_CACHE, one line per tuned sweep:
+//   Lx Ly Lz Lt nrhs sp lk dag epi block nr rl remap us
+static std::string cache_key(const wd_ctx *c, int nrhs, int sp, int lk, int dag, int epi)
+{
+    char b[128];
+    snprintf(b, sizeof(b), "%d %d %d %d %d %d %d %d %d", c->dims[0], c->dims[1], c->dims[2], c->dims[3],
+             nrhs, sp, lk, dag, epi);
+    return b;
+}
+
+static bool cache_lookup(const char *path, const std::string &key, TuneCfg *cfg, double *us)
+{
+    FILE *f = fopen(path, "r");
+    if (!f) return false;
+    char line[256];
+    bool found = false;
+    while (fgets(line, sizeof(line), f)) {
+        int d[9], b, nr, rl, rm;
+        double t;
+        if (sscanf(line, "%d %d %d %d %d %d %d %d %d %d %d %d %d %lf", &d[0], &d[1], &d[2], &d[3], &d[4],
+                   &d[5], &d[6], &d[7], &d[8], &b, &nr, &rl, &rm, &t) != 14)
+            continue;
+        char k[128];
+        snprintf(k, sizeof(k), "%d %d %d %d %d %d %d %d %d", d[0], d[1], d[2], d[3], d[4], d[5], d[6], d[7], d[8]);
+        if (key == k) {  // the last matching line wins
+            cfg->block = b;
+            cfg->nr = nr;
+            cfg->rl = rl;
+            cfg->remap = rm;
+            *us = t;
+            found = true;
+        }
+    }
+    fclose(f);
+    return found;
+}
+
+static void cache_store(const char *path, const std::string &key, const TuneCfg &cfg, double us)
+{
+    FILE *f = fopen(path, "a");
+    if (!f) return;
+    fprintf(f, "%s %d %d %d %d %.3f\n", key.c_str(), cfg.block, cfg.nr, cfg.rl, cfg.remap, us);
+    fclose(f);
+}
+
+extern "C" wd_status wd_tune(wd_ctx *c, int nrhs, int prec, char *report, size_t len)
+{
+    if (!c) return set_error(WD_ERR_ARG, "NULL context");
+    if (nrhs < 1 || nrhs > 64) return set_error(WD_ERR_ARG, "nrhs %d out of range 1..64", nrhs);
+    if (!c->have_gauge) return set_error(WD_ERR_STATE, "no gauge field loaded");
+    WD_HIP(hipSetDevice(c->device));
+    int sp, lk, xp;
+    WD_TRY(prec_decode(c, prec, &sp, &lk, &xp));
+    const int Vh = (int)c->Vh;
+    hipStream_t s = c->stream;
+    TuneFields t;
+    WD_TRY(tune_fields(c, sp, xp, nrhs, &t));
+    void *vp;
+    WD_TRY(ws_get(c, "tn_count", sizeof(unsigned) * 4, &vp));
+    unsigned *dcount = (unsigned *)vp;
+    void *hp;
+    WD_TRY(pinned_get(c, 1, 64, &hp));
+    unsigned *nd = (unsigned *)hp;
+    hipEvent_t e0, e1;
+    WD_HIP(hipEventCreate(&e0));
+    WD_HIP(hipEventCreate(&e1));
+    const bool was_timing = c->timing;
+    c->timing = false;
+
+    std::vector<TuneCfg> cands;
+    const int nrs[4] = {1, 2, 3, 4}, rls[3] = {1, 2, 4}, blocks[3] = {64, 128, 256};
+    for (int rl : rls)
+        for (int nr : nrs)
+            for (int b : blocks)
+                for (int rm = 0; rm < 3; rm++) {
+                    if (!dslash_shape_supported(sp, nr, rl)) continue;
+                    if (rm == 2 && !slab_order_ok(c->g, b / rl)) continue;
+                    if (nr * rl > 2 * nrhs && !(nr == 1 && rl == 1)) continue;  // mostly idle lanes
+                    TuneCfg q;
+                    q.block = b;
+                    q.nr = nr;
+                    q.rl = rl;
+                    q.remap = rm;
+                    cands.push_back(q);
+                }
+
+    struct Kind { int P, dag, epi; const char *name; };
+    const Kind kinds[4] = {{1, 0, EPI_PLAIN, "D_oe"}, {0, 0, EPI_XPAY, "xpay D_eo +norm"},
+                           {1, 1, EPI_PLAIN, "D_oe^dag"}, {0, 1, EPI_CGUPD, "cg-update D_eo^dag"}};
+    const size_t sb = (size_t)t.in.rs;  // bytes per RHS of a spinor field (padded)
+    const size_t xb = (size_t)t.xs.rs;
+    std::string rep;
+    wd_status st = WD_OK;
+    const char *cache = getenv("WD_TUNE_CACHE");
+    for (const Kind &k : kinds) {
+        if (cache && cache[0]) {
+            TuneCfg cc;
+            double us = 0;
+            if (cache_lookup(cache, cache_key(c, nrhs, sp, lk, k.dag, k.epi), &cc, &us) &&
+                dslash_shape_supported(sp, cc.nr, cc.rl)) {
+                c->tuned[sweep_key(sp, lk, k.dag, k.epi)] = cc;
+                char line[256];
+                snprintf(line, sizeof(line),
+                         "%s;sp=%d;lk=%d;nrhs=%d;block=%d;nr=%d;rl=%d;remap=%d;us=%.2f;GB/s=0.0;candidates=0;rejected=0\n",
+                         k.name, sp, lk, nrhs, cc.block, cc.nr, cc.rl, cc.remap, us);
+                rep += line;
+                continue;
+            }
+        }
+        Sweep sw;
+        sw.sp = sp; sw.lk = lk; sw.xp = xp; sw.dag = k.dag; sw.epi = k.epi; sw.P = k.P;
+        sw.in = t.in; sw.out = t.out; sw.x = t.x; sw.p = t.p; sw.xs = t.xs; sw.r = t.r;
+        sw.coef = t.coef; sw.alpha = t.alpha; sw.active = t.act; sw.nact = nrhs;
+        sw.partial = (k.epi == EPI_PLAIN) ? nullptr : t.partial;
+        sw.pstride = t.pstride;
+        double best = 1e30;
+        TuneCfg bestc = cands[0];
+        int rejected = 0;
+        for (size_t q = 0; q < cands.size(); q++) {
+            const TuneCfg &cf = cands[q];
+            // correctness run on fresh inputs
+            if (k.epi == EPI_CGUPD) {
+                HIPCHK(hipMemcpyAsync(t.r.base, t.r0.base, sb * nrhs, hipMemcpyDeviceToDevice, s));
+                HIPCHK(hipMemcpyAsync(t.xs.base, t.xs0.base, xb * nrhs, hipMemcpyDeviceToDevice, s));
+            }
+            if ((st = run_sweep(c, sw, &cf)) != WD_OK) break;
+            if (q == 0) {
+                HIPCHK(hipMemcpyAsync(t.outref.base, t.out.base, sb * nrhs, hipMemcpyDeviceToDevice, s));
+                HIPCHK(hipMemcpyAsync(t.rref.base, t.r.base, sb * nrhs, hipMemcpyDeviceToDevice, s));
+                HIPCHK(hipMemcpyAsync(t.xsref.base, t.xs.base, xb * nrhs, hipMemcpyDeviceToDevice, s));
+                HIPCHK(hipMemcpyAsync(t.pref, t.partial, sizeof(double) * t.pstride * nrhs, hipMemcpyDeviceToDevice, s));
+            } else {
+                unsigned bad = 0;
+                if (k.epi == EPI_CGUPD) {
+                    WD_TRY(compare(c, t.r.base, t.rref.base, sb * nrhs, dcount, nd));
+                    bad += *nd;
+                    WD_TRY(compare(c, t.xs.base, t.xsref.base, xb * nrhs, dcount, nd));
+                    bad += *nd;
+                } else {
+                    WD_TRY(compare(c, t.out.base, t.outref.base, sb * nrhs, dcount, nd));
+                    bad += *nd;
+                }
+                if (k.epi != EPI_PLAIN) {
+                    WD_TRY(compare(c, (const char *)t.partial, (const char *)t.pref,
+                                   sizeof(double) * t.pstride * nrhs, dcount, nd));
+                    bad += *nd;
+                }
+                if (bad) {
+                    rejected++;
+                    continue;
+                }
+            }
+            // timing: best of 3 batches of 4 launches
+            double tbest = 1e30;
+            for (int rep3 = 0; rep3 < 3; rep3++) {
+                HIPCHK(hipEventRecord(e0, s));
+                for (int it = 0; it < 4; it++)
+                    if ((st = run_sweep(c, sw, &cf)) != WD_OK) break;
+                HIPCHK(hipEventRecord(e1, s));
+                HIPCHK(hipEventSynchronize(e1));
+                float ms = 0;
+                HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+                tbest = std::min(tbest, (double)ms / 4);
+            }
+            if (st != WD_OK) break;
+            if (tbest < best) {
+                best = tbest;
+                bestc = cf;
+            }
+        }
+        if (st != WD_OK) break;
+        c->tuned[sweep_key(sp, lk, k.dag, k.epi)] = bestc;
+        if (cache && cache[0]) cache_store(cache, cache_key(c, nrhs, sp, lk, k.dag, k.epi), bestc, best * 1e3);
+        Sweep swb = sw;
+        const double gbs = sweep_bytes(c, swb) / (best * 1e-3) / 1e9;
+        char line[256];
+        snprintf(line, sizeof(line),
+                 "%s;sp=%d;lk=%d;nrhs=%d;block=%d;nr=%d;rl=%d;remap=%d;us=%.2f;GB/s=%.1f;candidates=%zu;rejected=%d\n",
+                 k.name, sp, lk, nrhs, bestc.block, bestc.nr, bestc.rl, bestc.remap, best * 1e3, gbs,
+                 cands.size(), rejected);
+        rep += line;
+    }
+    c->timing = was_timing;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != WD_OK) return st;
+    if (report && len) {
+        if (rep.size() + 1 > len) return set_error(WD_ERR_ARG, "report needs %zu bytes", rep.size() + 1);
+        memcpy(report, rep.c_str(), rep.size() + 1);
+    }
+    return WD_OK;
+}
+
+extern "C" wd_status wd_bench_dslash(wd_ctx *c, int nrhs, int prec, int epi, int iters, int tuned,
+                                     double *ms, double *bytes)
+{
+    if (!c || !ms) return set_error(WD_ERR_ARG, "NULL argument");
+    if (nrhs < 1 || nrhs > 64 || iters < 1 || epi < EPI_PLAIN || epi > EPI_CGUPD)
+        return set_error(WD_ERR_ARG, "bad arguments");
+    if (!c->have_gauge) return set_error(WD_ERR_STATE, "no gauge field loaded");
+    WD_HIP(hipSetDevice(c->device));
+    int sp, lk, xp;
+    WD_TRY(prec_decode(c, prec, &sp, &lk, &xp));
+    TuneFields t;
+    WD_TRY(tune_fields(c, sp, xp, nrhs, &t));
+    hipStream_t s = c->stream;
+    HIPCHK(hipMemcpyAsync(t.r.base, t.r0.base, (size_t)t.r.rs * nrhs, hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync(t.xs.base, t.xs0.base, (size_t)t.xs.rs * nrhs, hipMemcpyDeviceToDevice, s));
+    Sweep sw;
+    sw.sp = sp; sw.lk = lk; sw.xp = xp; sw.dag = 0; sw.epi = epi; sw.P = (epi == EPI_PLAIN) ? 1 : 0;
+    sw.in = t.in; sw.out = t.out; sw.x = t.x; sw.p = t.p; sw.xs = t.xs; sw.r = t.r;
+    sw.coef = t.coef; sw.alpha = t.alpha; sw.active = t.act; sw.nact = nrhs;
+    sw.partial = (epi == EPI_PLAIN) ? nullptr : t.partial;
+    sw.pstride = t.pstride;
+    const TuneCfg *cfg = tuned ? tuned_cfg(c, sw) : nullptr;
+    WD_TRY(run_sweep(c, sw, cfg));  // warm-up
+    hipEvent_t e0, e1;
+    WD_HIP(hipEventCreate(&e0));
+    WD_HIP(hipEventCreate(&e1));
+    HIPCHK(hipEventRecord(e0, s));
+    for (int it = 0; it < iters; it++) WD_TRY(run_sweep(c, sw, cfg));
+    HIPCHK(hipEventRecord(e1, s));
+    HIPCHK(hipEventSynchronize(e1));
+    float t_ms = 0;
+    HIPCHK(hipEventElapsedTime(&t_ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    *ms = t_ms / iters;
+    if (bytes) *bytes = sweep_bytes(c, sw);
+    return WD_OK;
+}

@@ -3,12 +3,17 @@
 // projections of (1 +- gamma_mu) and the SU(3) matrix-vector products.
 //
 // Internal storage (structure of arrays, one parity "subfield" at a time):
-//   spinor F64: double2 [12][Vh]          (complex component k = 3*spin + colour)
-//   spinor F32: float4  [6][Vh]           (reals 4k..4k+3 of the 24)
-//   spinor F16: half8   [3][Vh] + float [Vh] norm  (reals 8k..8k+7, times norm)
-//   links  L64_18: double2 [9][Vh], L64_12: double2 [6][Vh],
-//          L32_12: float4 [3][Vh],  L16_12: half4 [3][Vh]
+//   spinor F64: double2 [12][cs]          (complex component k = 3*spin + colour)
+//   spinor F32: float4  [6][cs]           (reals 4k..4k+3 of the 24)
+//   spinor F16: half8   [3][cs] + float [cs] norm  (reals 8k..8k+7, times norm)
+//   links  L64_18: double2 [9][cs], L64_12: double2 [6][cs],
+//          L32_12: float4 [3][cs],  L16_12: half4 [3][cs],
+//          L32_18: float4 [4][cs] (+ float2 [cs] in a second region)
 //          per (parity, mu) block, blocks ordered (parity*4 + mu).
+// cs >= Vh is the padded chunk stride (in sites): Vh is often a power of two
+// and unpadded chunk arrays would all start at the same offset modulo large
+// powers of two, so the chunks of one site would compete for the same L2
+// sets and channels.
 // Consecutive threads take consecutive checkerboard sites, so every load
 // and store of a wavefront is one contiguous 1 KiB (16 B per lane) segment.
 #pragma once
@@ -19,16 +24,62 @@
 namespace wd {
 
 enum { SP_F64 = 0, SP_F32 = 1, SP_F16 = 2 };
-enum { LK_F64_18 = 0, LK_F64_12 = 1, LK_F32_12 = 2, LK_F16_12 = 3 };
+enum { LK_F64_18 = 0, LK_F64_12 = 1, LK_F32_12 = 2, LK_F16_12 = 3, LK_F32_18 = 4 };
 
 typedef _Float16 half8_t __attribute__((ext_vector_type(8)));
+
+// All library code is compiled without floating-point contraction; every
+// fused multiply-add is written out with fmaT so that the rounding sequence
+// is fixed by the source and identical in every kernel instantiation.
+__device__ __forceinline__ float fmaT(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmaT(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// Two FP32 values to a packed pair of FP16 (round to nearest even), low half
+// first.  An ALU instruction only (no memory access).
+__device__ __forceinline__ uint32_t cvt_pk_f16(float lo, float hi)
+{
+    uint32_t r;
+    asm("v_cvt_pk_f16_f32 %0, %1, %2" : "=v"(r) : "v"(lo), "v"(hi));
+    return r;
+}
 typedef _Float16 half4_t __attribute__((ext_vector_type(4)));
+
+// Exact division by a runtime constant d for 0 <= n < 2^31 by a multiply and
+// a shift (Granlund & Montgomery, PLDI 1994): with l = ceil(log2 d) and
+// m = ceil(2^(31+l) / d), floor(n/d) = (n * m) >> (31 + l).
+struct FastDiv {
+    unsigned m;
+    int s;
+};
+
+__host__ __device__ __forceinline__ int fdiv(int n, FastDiv d)
+{
+    return (int)(((unsigned long long)(unsigned)n * d.m) >> d.s);
+}
+
+// Chunk stride for Vh sites: rounded up to 64 sites, then offset by an odd
+// multiple of 64 sites (592 = 37 * 16) so that consecutive chunk arrays, the
+// per-site norms and the fields of a batch start at staggered offsets.
+inline int padded_stride(int Vh) { return (Vh + 63) / 64 * 64 + 37 * 16; }
+
+inline FastDiv make_fastdiv(int d)
+{
+    int l = 0;
+    while ((1LL << l) < d) l++;
+    const unsigned long long num = 1ULL << (31 + l);
+    FastDiv f;
+    f.m = (unsigned)((num + (unsigned long long)d - 1) / (unsigned long long)d);
+    f.s = 31 + l;
+    return f;
+}
 
 struct Geom {
     int L[4];
     int Vh;
+    int cs;           // chunk stride of the structure-of-arrays layouts (sites)
     int Lxh;          // Lx / 2
     int sy, sz, st;   // checkerboard strides of y, z, t: Lxh, Lxh*Ly, Lxh*Ly*Lz
+    FastDiv dxh, dy, dz;  // division by Lxh, Ly, Lz
 };
 
 // Coordinates of checkerboard site i of parity P.  Because Lx is even,
@@ -36,12 +87,12 @@ struct Geom {
 // the parity.
 __device__ __forceinline__ void site_coords(const Geom &g, int i, int P, int c[4])
 {
-    int q = i / g.Lxh;
+    int q = fdiv(i, g.dxh);
     int x0 = 2 * (i - q * g.Lxh);
-    int y = q % g.L[1];
-    int zt = q / g.L[1];
-    int z = zt % g.L[2];
-    int t = zt / g.L[2];
+    int zt = fdiv(q, g.dy);
+    int y = q - zt * g.L[1];
+    int t = fdiv(zt, g.dz);
+    int z = zt - t * g.L[2];
     c[0] = x0 + ((P + y + z + t) & 1);
     c[1] = y;
     c[2] = z;
@@ -70,22 +121,22 @@ template <> struct SpinorIO<SP_F64> {
     typedef double real;
     static constexpr size_t site_bytes = 192;
     template <typename T>
-    __device__ static __forceinline__ void load(const char *f, int Vh, int i, T v[24])
+    __device__ static __forceinline__ void load(const char *f, int cs, int i, T v[24])
     {
         const double2 *p = reinterpret_cast<const double2 *>(f);
 #pragma unroll
         for (int k = 0; k < 12; k++) {
-            double2 w = p[(size_t)k * Vh + i];
+            double2 w = p[(size_t)k * cs + i];
             v[2 * k] = (T)w.x;
             v[2 * k + 1] = (T)w.y;
         }
     }
     template <typename T>
-    __device__ static __forceinline__ void store(char *f, int Vh, int i, const T v[24])
+    __device__ static __forceinline__ void store(char *f, int cs, int i, const T v[24])
     {
         double2 *p = reinterpret_cast<double2 *>(f);
 #pragma unroll
-        for (int k = 0; k < 12; k++) p[(size_t)k * Vh + i] = make_double2((double)v[2 * k], (double)v[2 * k + 1]);
+        for (int k = 0; k < 12; k++) p[(size_t)k * cs + i] = make_double2((double)v[2 * k], (double)v[2 * k + 1]);
     }
 };
 
@@ -93,12 +144,12 @@ template <> struct SpinorIO<SP_F32> {
     typedef float real;
     static constexpr size_t site_bytes = 96;
     template <typename T>
-    __device__ static __forceinline__ void load(const char *f, int Vh, int i, T v[24])
+    __device__ static __forceinline__ void load(const char *f, int cs, int i, T v[24])
     {
         const float4 *p = reinterpret_cast<const float4 *>(f);
 #pragma unroll
         for (int k = 0; k < 6; k++) {
-            float4 w = p[(size_t)k * Vh + i];
+            float4 w = p[(size_t)k * cs + i];
             v[4 * k] = (T)w.x;
             v[4 * k + 1] = (T)w.y;
             v[4 * k + 2] = (T)w.z;
@@ -106,12 +157,12 @@ template <> struct SpinorIO<SP_F32> {
         }
     }
     template <typename T>
-    __device__ static __forceinline__ void store(char *f, int Vh, int i, const T v[24])
+    __device__ static __forceinline__ void store(char *f, int cs, int i, const T v[24])
     {
         float4 *p = reinterpret_cast<float4 *>(f);
 #pragma unroll
         for (int k = 0; k < 6; k++)
-            p[(size_t)k * Vh + i] = make_float4((float)v[4 * k], (float)v[4 * k + 1], (float)v[4 * k + 2],
+            p[(size_t)k * cs + i] = make_float4((float)v[4 * k], (float)v[4 * k + 1], (float)v[4 * k + 2],
                                                 (float)v[4 * k + 3]);
     }
 };
@@ -122,33 +173,37 @@ template <> struct SpinorIO<SP_F16> {
     typedef float real;
     static constexpr size_t site_bytes = 52;
     template <typename T>
-    __device__ static __forceinline__ void load(const char *f, int Vh, int i, T v[24])
+    __device__ static __forceinline__ void load(const char *f, int cs, int i, T v[24])
     {
         const half8_t *p = reinterpret_cast<const half8_t *>(f);
-        const float n = reinterpret_cast<const float *>(f + (size_t)48 * Vh)[i];
+        const float n = reinterpret_cast<const float *>(f + (size_t)48 * cs)[i];
 #pragma unroll
         for (int k = 0; k < 3; k++) {
-            half8_t w = p[(size_t)k * Vh + i];
+            half8_t w = p[(size_t)k * cs + i];
 #pragma unroll
             for (int j = 0; j < 8; j++) v[8 * k + j] = (T)((float)w[j] * n);
         }
     }
     template <typename T>
-    __device__ static __forceinline__ void store(char *f, int Vh, int i, const T v[24])
+    __device__ static __forceinline__ void store(char *f, int cs, int i, const T v[24])
     {
+        // The scaled value is rounded to FP32 and then to FP16 (RNE) by an
+        // explicit conversion: left to itself the backend may fuse some of
+        // the multiplies into one-rounding mixed FMAs in some instantiations.
         float m = 0.f;
 #pragma unroll
         for (int j = 0; j < 24; j++) m = fmaxf(m, fabsf((float)v[j]));
         const float inv = (m > 0.f) ? 1.0f / m : 0.f;
-        half8_t *p = reinterpret_cast<half8_t *>(f);
+        uint4 *p = reinterpret_cast<uint4 *>(f);
 #pragma unroll
         for (int k = 0; k < 3; k++) {
-            half8_t w;
+            uint32_t w[4];
 #pragma unroll
-            for (int j = 0; j < 8; j++) w[j] = (_Float16)((float)v[8 * k + j] * inv);
-            p[(size_t)k * Vh + i] = w;
+            for (int j = 0; j < 4; j++)
+                w[j] = cvt_pk_f16((float)v[8 * k + 2 * j] * inv, (float)v[8 * k + 2 * j + 1] * inv);
+            p[(size_t)k * cs + i] = make_uint4(w[0], w[1], w[2], w[3]);
         }
-        reinterpret_cast<float *>(f + (size_t)48 * Vh)[i] = m;
+        reinterpret_cast<float *>(f + (size_t)48 * cs)[i] = m;
     }
 };
 
@@ -170,8 +225,14 @@ __device__ __forceinline__ void reconstruct_row3(T u[18])
     for (int j = 0; j < 3; j++) {
         const int k = (j + 1) % 3, l = (j + 2) % 3;
         // (row1 x row2)_j = u0k u1l - u0l u1k
-        T re = RE(0, k) * RE(1, l) - IM(0, k) * IM(1, l) - (RE(0, l) * RE(1, k) - IM(0, l) * IM(1, k));
-        T im = RE(0, k) * IM(1, l) + IM(0, k) * RE(1, l) - (RE(0, l) * IM(1, k) + IM(0, l) * RE(1, k));
+        T re = RE(0, k) * RE(1, l);
+        re = fmaT(-IM(0, k), IM(1, l), re);
+        re = fmaT(-RE(0, l), RE(1, k), re);
+        re = fmaT(IM(0, l), IM(1, k), re);
+        T im = RE(0, k) * IM(1, l);
+        im = fmaT(IM(0, k), RE(1, l), im);
+        im = fmaT(-RE(0, l), IM(1, k), im);
+        im = fmaT(-IM(0, l), RE(1, k), im);
         RE(2, j) = re;
         IM(2, j) = -im;
     }
@@ -185,12 +246,12 @@ template <> struct LinkIO<LK_F64_18> {
     typedef double real;
     static constexpr int nchunk = 9;
     static constexpr size_t chunk_bytes = 16;
-    __device__ static __forceinline__ void load(const char *U, int Vh, int blk, int i, double u[18])
+    __device__ static __forceinline__ void load(const char *U, int cs, int blk, int i, double u[18])
     {
-        const double2 *p = reinterpret_cast<const double2 *>(U) + (size_t)blk * 9 * Vh;
+        const double2 *p = reinterpret_cast<const double2 *>(U) + (size_t)blk * 9 * cs;
 #pragma unroll
         for (int k = 0; k < 9; k++) {
-            double2 w = p[(size_t)k * Vh + i];
+            double2 w = p[(size_t)k * cs + i];
             u[2 * k] = w.x;
             u[2 * k + 1] = w.y;
         }
@@ -201,12 +262,12 @@ template <> struct LinkIO<LK_F64_12> {
     typedef double real;
     static constexpr int nchunk = 6;
     static constexpr size_t chunk_bytes = 16;
-    __device__ static __forceinline__ void load(const char *U, int Vh, int blk, int i, double u[18])
+    __device__ static __forceinline__ void load(const char *U, int cs, int blk, int i, double u[18])
     {
-        const double2 *p = reinterpret_cast<const double2 *>(U) + (size_t)blk * 6 * Vh;
+        const double2 *p = reinterpret_cast<const double2 *>(U) + (size_t)blk * 6 * cs;
 #pragma unroll
         for (int k = 0; k < 6; k++) {
-            double2 w = p[(size_t)k * Vh + i];
+            double2 w = p[(size_t)k * cs + i];
             u[2 * k] = w.x;
             u[2 * k + 1] = w.y;
         }
@@ -218,12 +279,12 @@ template <> struct LinkIO<LK_F32_12> {
     typedef float real;
     static constexpr int nchunk = 3;
     static constexpr size_t chunk_bytes = 16;
-    __device__ static __forceinline__ void load(const char *U, int Vh, int blk, int i, float u[18])
+    __device__ static __forceinline__ void load(const char *U, int cs, int blk, int i, float u[18])
     {
-        const float4 *p = reinterpret_cast<const float4 *>(U) + (size_t)blk * 3 * Vh;
+        const float4 *p = reinterpret_cast<const float4 *>(U) + (size_t)blk * 3 * cs;
 #pragma unroll
         for (int k = 0; k < 3; k++) {
-            float4 w = p[(size_t)k * Vh + i];
+            float4 w = p[(size_t)k * cs + i];
             u[4 * k] = w.x;
             u[4 * k + 1] = w.y;
             u[4 * k + 2] = w.z;
@@ -237,12 +298,12 @@ template <> struct LinkIO<LK_F16_12> {
     typedef float real;
     static constexpr int nchunk = 3;
     static constexpr size_t chunk_bytes = 8;
-    __device__ static __forceinline__ void load(const char *U, int Vh, int blk, int i, float u[18])
+    __device__ static __forceinline__ void load(const char *U, int cs, int blk, int i, float u[18])
     {
-        const half4_t *p = reinterpret_cast<const half4_t *>(U) + (size_t)blk * 3 * Vh;
+        const half4_t *p = reinterpret_cast<const half4_t *>(U) + (size_t)blk * 3 * cs;
 #pragma unroll
         for (int k = 0; k < 3; k++) {
-            half4_t w = p[(size_t)k * Vh + i];
+            half4_t w = p[(size_t)k * cs + i];
 #pragma unroll
             for (int j = 0; j < 4; j++) u[4 * k + j] = (float)w[j];
         }
@@ -250,9 +311,34 @@ template <> struct LinkIO<LK_F16_12> {
     }
 };
 
+// FP32 with all 18 reals (no reconstruction): reals 0..15 as float4 [4][cs]
+// per (parity, mu) block, then reals 16..17 as float2 [cs] per block in a
+// second region after all eight float4 blocks.
+template <> struct LinkIO<LK_F32_18> {
+    typedef float real;
+    __device__ static __forceinline__ void load(const char *U, int cs, int blk, int i, float u[18])
+    {
+        const float4 *p = reinterpret_cast<const float4 *>(U) + (size_t)blk * 4 * cs;
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            float4 w = p[(size_t)k * cs + i];
+            u[4 * k] = w.x;
+            u[4 * k + 1] = w.y;
+            u[4 * k + 2] = w.z;
+            u[4 * k + 3] = w.w;
+        }
+        const float2 *q = reinterpret_cast<const float2 *>(reinterpret_cast<const float4 *>(U) + (size_t)32 * cs) +
+                          (size_t)blk * cs;
+        float2 w = q[i];
+        u[16] = w.x;
+        u[17] = w.y;
+    }
+};
+
 __host__ __device__ constexpr size_t link_bytes(int lk)
 {
-    return lk == LK_F64_18 ? 144 : (lk == LK_F64_12 ? 96 : (lk == LK_F32_12 ? 48 : 24));
+    return lk == LK_F64_18 ? 144
+                           : (lk == LK_F64_12 ? 96 : (lk == LK_F32_12 ? 48 : (lk == LK_F16_12 ? 24 : 72)));
 }
 
 // ---------------------------------------------------------------------------
@@ -348,8 +434,10 @@ __device__ __forceinline__ void su3_mul_half(const T u[18], const T h[12], T w[1
                 const int idx = ADJ ? 2 * (3 * b + a) : 2 * (3 * a + b);
                 const T ur = u[idx], ui = ADJ ? -u[idx + 1] : u[idx + 1];
                 const T hr = h[6 * r + 2 * b], hi = h[6 * r + 2 * b + 1];
-                re += ur * hr - ui * hi;
-                im += ur * hi + ui * hr;
+                re = fmaT(ur, hr, re);
+                re = fmaT(-ui, hi, re);
+                im = fmaT(ur, hi, im);
+                im = fmaT(ui, hr, im);
             }
             w[6 * r + 2 * a] = re;
             w[6 * r + 2 * a + 1] = im;
@@ -369,12 +457,5 @@ __device__ __forceinline__ int xcd_remap(int b, int nb)
     return x * q + (x < rm ? x : rm) + j;
 }
 
-// Deterministic wavefront sum (fixed butterfly order).
-__device__ __forceinline__ double wave_sum(double v)
-{
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
 
 }  // namespace wd

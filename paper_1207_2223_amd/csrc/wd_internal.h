@@ -40,6 +40,7 @@ struct Field {
     long long ss = 0;
     int sp = SP_F64;
     int nsub = 1;
+    int cs = 0;  // chunk stride (sites) of the structure-of-arrays layout
     char *sub(int rid, int s) const { return base + rid * rs + s * ss; }
 };
 
@@ -64,25 +65,28 @@ struct DslashArgs {
     const double *alpha;   // [rid]
     const int *active;     // RHS ids processed by this launch
     int nact;
-    int G;                 // RHS groups of NR per tile
-    int remap;             // XCD-aware tile order
-    double *partial;       // partial[rid*pstride + pw_off + wave] = sum |out|^2 (or |r|^2)
+    int G;                 // RHS groups of RL*NR per tile
+    int remap;             // tile order: 0 dispatch order, 1 XCD-contiguous, 2 XCD z-slabs
+    int tpp;               // remap 2: tiles per (z, t) plane
+    int nzl;               // remap 2: z planes per XCD
+    double *partial;       // partial[rid*pstride + pw_off + site/16] = sum |out|^2 (or |r|^2)
     int pstride;
     int pw_off;
 };
 
+// Launch shape of one stencil sweep: threads per work-group, RHS per lane
+// (nr), lanes per site (rl), tile order (remap: 0 dispatch order,
+// 1 contiguous tile range per XCD, 2 z-slab per XCD walked z-fastest).
 struct TuneCfg {
     int block = 128;
     int nr = 1;
+    int rl = 1;
     int remap = 1;
 };
 
-hipError_t dslash_launch_f64(const DslashArgs &a, int lk, int nr, int dag, int epi, int block,
-                             int grid, hipStream_t s);
-hipError_t dslash_launch_f32(const DslashArgs &a, int lk, int nr, int dag, int epi, int block,
-                             int grid, hipStream_t s);
-hipError_t dslash_launch_f16(const DslashArgs &a, int lk, int nr, int dag, int epi, int block,
-                             int grid, hipStream_t s);
+hipError_t dslash_launch(const DslashArgs &a, int sp, int lk, int nr, int rl, int dag, int epi,
+                         int block, int grid, hipStream_t s);
+bool dslash_shape_supported(int sp, int nr, int rl);
 
 // BLAS-1 / reductions (blas.hip).  All take an active-RHS list.
 enum { FIN_STORE = 0, FIN_ALPHA = 1, FIN_BETA = 2, FIN_RR = 3 };
@@ -100,10 +104,17 @@ hipError_t blas_add_zero(const Field &xhi, const Field &xs, int Vh, const int *a
 hipError_t blas_resid(const Field &r, const Field &b, const Field &Ap, int Vh, const int *active,
                       int nact, double *partial, int pstride, hipStream_t s);
 hipError_t blas_zero(const Field &a, int Vh, const int *active, int nact, hipStream_t s);
+hipError_t blas_cdot(const Field &a, const Field &b, int Vh, const int *active, int nact,
+                     double *pre, double *pim, int pstride, hipStream_t s);
+hipError_t blas_orth(const Field &p, const Field &r, const double *dre, const double *dim,
+                     const double *rr, int Vh, const int *active, int nact, hipStream_t s);
+hipError_t blas_axpy_const(const Field &p, const Field &r, double a, int Vh, const int *active,
+                           int nact, hipStream_t s);
 hipError_t blas_finalize(const double *partial, int pstride, int nw, const int *active, int nact,
                          int mode, double *rr, double *alpha, double *beta, double *out,
                          hipStream_t s);
-inline int nwaves_of(int nsites) { return (nsites + 63) / 64; }
+// Reductions are formed from partial sums over groups of 16 consecutive sites.
+inline int ngroups_of(int nsites) { return (nsites + 15) / 16; }
 
 // Packing between the canonical complex128 layouts and the internal ones (pack.hip).
 hipError_t pack_gauge(const double *U, char *dst, int lk, const Geom &g, hipStream_t s);
@@ -130,6 +141,7 @@ struct wd_ctx {
     char *links64 = nullptr;
     char *links32 = nullptr;
     char *links16 = nullptr;
+    char *links32r = nullptr;  // FP32 18-real
 
     // named, growable device workspaces
     std::map<std::string, std::pair<void *, size_t>> ws;
@@ -145,8 +157,10 @@ struct wd_ctx {
     double t_ms = 0;
     long long t_launches = 0;
 
-    // launch shapes chosen by the autotuner, keyed by kernel description
+    // launch shapes chosen by the autotuner, keyed by sweep description, and
+    // whether the current call uses them
     std::map<std::string, wd::TuneCfg> tuned;
+    bool use_tuned = false;
 };
 
 namespace wd {
@@ -155,6 +169,9 @@ wd_status ws_get(wd_ctx *c, const std::string &name, size_t bytes, void **ptr);
 wd_status pinned_get(wd_ctx *c, int slot, size_t bytes, void **ptr);
 wd_status alloc_field(wd_ctx *c, const std::string &name, int sp, int nsub, int nrhs, Field *f);
 const char *link_ptr(const wd_ctx *c, int lk);
+// Storage of an operator precision code (wd_prec | WD_LINKS_F16 | WD_LINKS_R18):
+// spinor format, link format and solution-accumulator format.
+wd_status decode_prec(const wd_ctx *c, int prec, int *sp, int *lk, int *xp);
 
 // One stencil sweep over the active RHS (dispatch + optional timing).
 struct Sweep {
@@ -178,6 +195,9 @@ wd_status upload_doubles(wd_ctx *c, const std::string &name, const double *v, in
 wd_status upload_ints(wd_ctx *c, const std::string &name, const int *v, int n, int **dev);
 Field sub_view(const Field &f, int s);
 TuneCfg default_cfg(int sp);
+// Whether the z-slab tile order (remap 2) applies to tiles of spb sites.
+bool slab_order_ok(const Geom &g, int spb);
+const TuneCfg *tuned_cfg(const wd_ctx *c, const Sweep &sw);
 double sweep_bytes(const wd_ctx *c, const Sweep &sw);
 
 }  // namespace wd

@@ -17,6 +17,7 @@ WD_OK, WD_ERR_ARG, WD_ERR_DIMS, WD_ERR_OOM, WD_ERR_HIP, WD_ERR_NOCONV, WD_ERR_NA
     0, -1, -2, -3, -4, -5, -6, -7)
 WD_F64, WD_F32, WD_F16 = 0, 1, 2
 WD_LINKS_F16 = 0x10
+WD_LINKS_R18 = 0x20
 WD_FULL, WD_EVEN, WD_ODD = 0, 1, 2
 WD_RECON_18, WD_RECON_12 = 0, 1
 
@@ -59,6 +60,9 @@ _SIGS = {
     "wd_timing_read": (C.c_int, [_P, C.POINTER(C.c_double), C.POINTER(C.c_int64),
                                  C.POINTER(C.c_double)]),
     "wd_timing_report": (C.c_int, [_P, C.c_char_p, C.c_size_t]),
+    "wd_tune": (C.c_int, [_P, C.c_int, C.c_int, C.c_char_p, C.c_size_t]),
+    "wd_bench_dslash": (C.c_int, [_P, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int,
+                                  C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "wd_last_error": (C.c_char_p, []),
     "wd_version": (C.c_char_p, []),
 }
@@ -226,6 +230,30 @@ def wd_timing_report(ctx):
         name, n, ms, b, u = line.split(";")
         out[name] = (int(n), float(ms), float(b), float(u))
     return out
+
+
+def wd_tune(ctx, nrhs, prec):
+    """Autotune the solver's stencil sweeps; returns the report lines as dicts."""
+    buf = C.create_string_buffer(1 << 14)
+    _check(lib().wd_tune(ctx, int(nrhs), int(prec), buf, len(buf)))
+    rows = []
+    for line in buf.value.decode().splitlines():
+        f = line.split(";")
+        d = {"sweep": f[0]}
+        for kv in f[1:]:
+            k, v = kv.split("=")
+            d[k] = float(v) if "." in v else int(v)
+        rows.append(d)
+    return rows
+
+
+def wd_bench_dslash(ctx, nrhs, prec, epi=0, iters=20, tuned=1):
+    """(ms per sweep, algorithmic bytes per sweep) of the stencil micro-benchmark."""
+    ms = C.c_double()
+    by = C.c_double()
+    _check(lib().wd_bench_dslash(ctx, int(nrhs), int(prec), int(epi), int(iters), int(tuned),
+                                 C.byref(ms), C.byref(by)))
+    return ms.value, by.value
 
 
 def wd_last_error():

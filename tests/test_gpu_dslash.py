@@ -70,11 +70,13 @@ def test_dslash_fp64_full_lattice(wd, oracle, dims):
     lat.close()
 
 
-@pytest.mark.parametrize("prec,tol", [("F32", 2e-6), ("F16", 4e-3), ("F16L", 5e-3), ("F32L", 2e-3)])
+@pytest.mark.parametrize("prec,tol", [("F32", 2e-6), ("F16", 4e-3), ("F16L", 5e-3), ("F32L", 2e-3),
+                                      ("F32R", 2e-6), ("F16R", 4e-3)])
 def test_dslash_sloppy_precisions(wd, oracle, prec, tol):
     dims = (6, 4, 4, 6)
     code = {"F32": wd.WD_F32, "F16": wd.WD_F16, "F16L": wd.WD_F16 | wd.WD_LINKS_F16,
-            "F32L": wd.WD_F32 | wd.WD_LINKS_F16}[prec]
+            "F32L": wd.WD_F32 | wd.WD_LINKS_F16, "F32R": wd.WD_F32 | wd.WD_LINKS_R18,
+            "F16R": wd.WD_F16 | wd.WD_LINKS_R18}[prec]
     V = li.volume(dims)
     U = li.random_su3_field(dims, 0.5, seed=5)
     lat = wd.Lattice(dims)

@@ -1,0 +1,64 @@
+"""Autotuner: every launch shape of every sweep produces bitwise-identical
+vectors and norm partials (the tuner rejects any that does not; none may be
+rejected), and a solve with tuned shapes equals the default-shape solve bit
+for bit."""
+import numpy as np
+import pytest
+
+import lattice_inputs as li
+from gpu_util import dev, empty_like_dev, host, note
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def wd():
+    from paper_1207_2223_amd import wd
+    wd.lib()
+    return wd
+
+
+@pytest.mark.parametrize("prec", ["F64", "F32", "F16", "F16L", "F16R"])
+@pytest.mark.parametrize("dims", [(6, 4, 4, 6), (16, 8, 8, 4)])
+def test_tuner_all_shapes_bitwise_and_tuned_solve_identical(wd, oracle, prec, dims):
+    """(6,4,4,6): Vh = 288, a ragged last tile for every block size;
+    (16,8,8,4): Lz divisible by 8, so the z-slab tile order is a candidate."""
+    code = {"F64": wd.WD_F64, "F32": wd.WD_F32, "F16": wd.WD_F16,
+            "F16L": wd.WD_F16 | wd.WD_LINKS_F16, "F16R": wd.WD_F16 | wd.WD_LINKS_R18}[prec]
+    V = li.volume(dims)
+    U = li.random_su3_field(dims, 0.5, seed=41)
+    lat = wd.Lattice(dims)
+    lat.gauge_load(dev(U), recon=12)
+    nrhs = 5
+    rows = wd.wd_tune(lat.ctx, nrhs, code)
+    for r in rows:
+        note(f"{prec} {r['sweep']}: block {r['block']} nr {r['nr']} rl {r['rl']} remap {r['remap']} "
+             f"{r['candidates']} candidates, {r['rejected']} rejected")
+        assert r["rejected"] == 0 and r["candidates"] > 1
+    if code != wd.WD_F64:
+        wd.wd_tune(lat.ctx, nrhs, wd.WD_F64)
+    B = li.gaussian_spinor(V // 2, seed=42, nrhs=nrhs)
+    kap = [0.15, 0.152, 0.154, 0.156, 0.157]
+    X0 = empty_like_dev(B)
+    X1 = empty_like_dev(B)
+    s0, st0 = lat.cg_solve(X0, dev(B), kap, wd.solver_params(prec=code, tuned=0))
+    s1, st1 = lat.cg_solve(X1, dev(B), kap, wd.solver_params(prec=code, tuned=1))
+    assert s0 == wd.WD_OK and s1 == wd.WD_OK
+    assert [s["iters"] for s in st0] == [s["iters"] for s in st1]
+    assert np.array_equal(host(X0), host(X1))
+    # and the result is a solution by the oracle's operator
+    Xh = host(X1)
+    for j in range(nrhs):
+        r = B[j] - oracle.mhatdag_mhat(dims, U, kap[j], Xh[j])
+        assert np.linalg.norm(r) / np.linalg.norm(B[j]) <= 1.01e-10
+    lat.close()
+
+
+def test_bench_dslash_runs(wd):
+    dims = (8, 8, 8, 8)
+    lat = wd.Lattice(dims)
+    lat.gauge_load(dev(li.unit_field(dims)))
+    for epi in (0, 1, 2):
+        ms, by = wd.wd_bench_dslash(lat.ctx, 3, wd.WD_F16, epi=epi, iters=3, tuned=0)
+        assert ms > 0 and by > 0
+    lat.close()
