@@ -143,6 +143,65 @@ wd_status wd_mdagm(wd_ctx *c, double *out, const double *in, double kappa, int e
 wd_status wd_cg_solve(wd_ctx *c, double *x, const double *phi, int nrhs, const double *kappa,
                       const wd_solver_params *p, wd_solver_stats *st);
 
+/* ---------------------------------------------------------------------- */
+/* Molecular dynamics and HMC (Sec. 2, eq. 5; Sec. 3 kernels 2-4 and the     */
+/* three steps of a trajectory).  Even-odd action                            */
+/*   S = beta sum_{x,mu<nu} (1 - Re tr U_munu / 3)                           */
+/*     + phi_e^dag (Mhat^dag Mhat)^-1 phi_e,   H = S + 1/2 sum tr p^2.       */
+/* ---------------------------------------------------------------------- */
+
+typedef struct {
+    double beta;                   /* gauge coupling of the plaquette action          */
+    double kappa;                  /* hopping parameter                               */
+    double tau;                    /* trajectory length                               */
+    int nsteps;                    /* leapfrog steps (P-Q-P), dtau = tau / nsteps      */
+    uint32_t traj;                 /* trajectory index: Philox counter word           */
+    uint64_t seed;                 /* Philox key                                      */
+    wd_solver_params force_solver; /* solves inside the force (eo must be 1)          */
+    wd_solver_params h_solver;     /* the final-Hamiltonian solve (eo must be 1)      */
+} wd_hmc_params;
+
+typedef struct {
+    double dH;        /* H_new - H_old (FP64 sums)                                   */
+    double exp_mdH;   /* exp(-dH)                                                    */
+    double plaquette; /* average plaquette of the field returned                     */
+    double H_old, H_new;
+    double u;         /* Metropolis uniform; accepted iff u < exp(-dH)              */
+    double seconds;
+    int accepted;
+    int cg_iters;     /* CG iterations of all force solves and the final solve      */
+    int status;       /* wd_status of the trajectory                                */
+} wd_hmc_result;
+
+/* Defaults: beta 5.6, kappa 0.156, tau 1, 50 steps, seed 1, traj 0; force
+ * solves FP16-sloppy to 1e-8, final solve FP64 to 1e-10.  h: host pointer. */
+void wd_hmc_defaults(wd_hmc_params *h);
+
+/* The refresh draws of a trajectory: momenta P [V][4][3][3] (Hermitian
+ * traceless, p = sum_a xi_a lambda_a / sqrt 2, xi ~ N(0,1)) and the even-site
+ * Gaussian chi [Vh][4][3] (Re, Im ~ N(0, 1/2)), from Philox4x32-10 keyed by
+ * seed with counter (link or site, traj, stream tag, j).  Device pointers. */
+wd_status wd_hmc_draw(wd_ctx *c, double *P, double *chi, uint64_t seed, uint32_t traj);
+
+/* MD force (Sec. 3 kernels 2 and 3) of the even-odd action at gauge field U
+ * ([V][4][3][3], device) and pseudofermion phi ([Vh][4][3] even sites,
+ * device): F = F_g + F_f written to F ([V][4][3][3] Hermitian traceless,
+ * device), defined by dS/dt = sum tr(X F) for U -> exp(i t X) U, so that
+ * dp/dt = -F.  The solve X_e = (Mhat^dag Mhat)^-1 phi_e uses p (eo = 1;
+ * NULL = defaults); *cg_iters (host, may be NULL) receives its iterations.
+ * Loads U as the context's gauge field. */
+wd_status wd_md_force(wd_ctx *c, double *F, const double *U, const double *phi, double kappa,
+                      double beta, const wd_solver_params *p, int *cg_iters);
+
+/* One HMC trajectory (Sec. 3 steps 1-3): draw p and chi (wd_hmc_draw),
+ * phi_e = Mhat^dag chi_e, H_old = 1/2 sum tr p^2 + S_g + chi^dag chi,
+ * leapfrog P-Q-P with U <- exp(i dtau p) U and p <- p - dtau F, H_new with a
+ * final solve, Metropolis with u from Philox (0, traj, 'M', 0).  U
+ * ([V][4][3][3], device) is replaced by the proposal when accepted and left
+ * unchanged otherwise; the context's packed links follow U either way.
+ * h, r: host pointers.  A failed solve rejects and returns its status. */
+wd_status hmc_trajectory(wd_ctx *c, double *U, const wd_hmc_params *h, wd_hmc_result *r);
+
 /* Index tables computed on the HOST from the definition above: nb [V][8]
  * (x+mu, x-mu for mu = 0..3), cb [V], par [V].  HOST pointers. */
 wd_status wd_index_tables(const int32_t dims[4], int32_t *nb, int32_t *cb, uint8_t *par);

@@ -41,6 +41,19 @@ class wd_solver_stats(C.Structure):
                 ("seconds", C.c_double), ("status", C.c_int)]
 
 
+class wd_hmc_params(C.Structure):
+    _fields_ = [("beta", C.c_double), ("kappa", C.c_double), ("tau", C.c_double),
+                ("nsteps", C.c_int), ("traj", C.c_uint32), ("seed", C.c_uint64),
+                ("force_solver", wd_solver_params), ("h_solver", wd_solver_params)]
+
+
+class wd_hmc_result(C.Structure):
+    _fields_ = [("dH", C.c_double), ("exp_mdH", C.c_double), ("plaquette", C.c_double),
+                ("H_old", C.c_double), ("H_new", C.c_double), ("u", C.c_double),
+                ("seconds", C.c_double), ("accepted", C.c_int), ("cg_iters", C.c_int),
+                ("status", C.c_int)]
+
+
 _P = C.c_void_p
 _I32x4 = C.c_int32 * 4
 _SIGS = {
@@ -63,6 +76,11 @@ _SIGS = {
     "wd_tune": (C.c_int, [_P, C.c_int, C.c_int, C.c_char_p, C.c_size_t]),
     "wd_bench_dslash": (C.c_int, [_P, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int,
                                   C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "wd_hmc_defaults": (None, [C.POINTER(wd_hmc_params)]),
+    "wd_hmc_draw": (C.c_int, [_P, _P, _P, C.c_uint64, C.c_uint32]),
+    "wd_md_force": (C.c_int, [_P, _P, _P, _P, C.c_double, C.c_double, C.POINTER(wd_solver_params),
+                              C.POINTER(C.c_int)]),
+    "hmc_trajectory": (C.c_int, [_P, _P, C.POINTER(wd_hmc_params), C.POINTER(wd_hmc_result)]),
     "wd_last_error": (C.c_char_p, []),
     "wd_version": (C.c_char_p, []),
 }
@@ -254,6 +272,51 @@ def wd_bench_dslash(ctx, nrhs, prec, epi=0, iters=20, tuned=1):
     _check(lib().wd_bench_dslash(ctx, int(nrhs), int(prec), int(epi), int(iters), int(tuned),
                                  C.byref(ms), C.byref(by)))
     return ms.value, by.value
+
+
+def wd_hmc_defaults():
+    h = wd_hmc_params()
+    lib().wd_hmc_defaults(C.byref(h))
+    return h
+
+
+def wd_hmc_draw(ctx, P, chi, seed, traj):
+    _c128(P, (4, 3, 3), "P")
+    _c128(chi, (4, 3), "chi")
+    _check(lib().wd_hmc_draw(ctx, _ptr(P), _ptr(chi), int(seed), int(traj)))
+
+
+def wd_md_force(ctx, F, U, phi, kappa, beta, params=None):
+    """F = F_g + F_f (even-odd action); returns the solve's iteration count."""
+    _c128(F, (4, 3, 3), "F")
+    _c128(U, (4, 3, 3), "U")
+    _c128(phi, (4, 3), "phi")
+    it = C.c_int(0)
+    p = params if params is not None else wd_solver_defaults()
+    _check(lib().wd_md_force(ctx, _ptr(F), _ptr(U), _ptr(phi), float(kappa), float(beta),
+                             C.byref(p), C.byref(it)))
+    return it.value
+
+
+def hmc_trajectory(ctx, U, params, check=True):
+    """One trajectory; U is updated in place when accepted.  Returns a dict."""
+    _c128(U, (4, 3, 3), "U")
+    r = wd_hmc_result()
+    st = lib().hmc_trajectory(ctx, _ptr(U), C.byref(params), C.byref(r))
+    if check and st not in (WD_OK, WD_ERR_NOCONV, WD_ERR_NAN):
+        _check(st)
+    return {k: getattr(r, k) for k, _ in wd_hmc_result._fields_}
+
+
+def hmc_params(beta=5.6, kappa=0.156, tau=1.0, nsteps=50, seed=1, traj=0, force=None, h=None):
+    p = wd_hmc_defaults()
+    p.beta, p.kappa, p.tau, p.nsteps, p.seed, p.traj = (float(beta), float(kappa), float(tau),
+                                                        int(nsteps), int(seed), int(traj))
+    if force is not None:
+        p.force_solver = force
+    if h is not None:
+        p.h_solver = h
+    return p
 
 
 def wd_last_error():

@@ -1,0 +1,115 @@
+"""GPU parity of the MD force and the HMC trajectory (Sec. 2 eq. 5; Sec. 3
+kernels 2-4 and the three steps of a trajectory) against the oracle on the
+same Philox draws."""
+import numpy as np
+import pytest
+
+import lattice_inputs as li
+from gpu_util import dev, host, note
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def wd():
+    from paper_1207_2223_amd import wd
+    wd.lib()
+    return wd
+
+
+def test_draws_match_oracle(wd, oracle):
+    import torch
+    dims = (4, 4, 2, 6)
+    V = li.volume(dims)
+    lat = wd.Lattice(dims)
+    P = torch.empty((V, 4, 3, 3), dtype=torch.complex128, device="cuda")
+    chi = torch.empty((V // 2, 4, 3), dtype=torch.complex128, device="cuda")
+    for seed, traj in [(77, 3), (2 ** 40 + 5, 0)]:
+        wd.wd_hmc_draw(lat.ctx, P, chi, seed, traj)
+        Po = oracle.draw_momenta(dims, seed, traj)
+        co = oracle.draw_chi(V // 2, seed, traj)
+        assert np.allclose(host(P), Po, rtol=0, atol=1e-13)
+        assert np.allclose(host(chi), co, rtol=0, atol=1e-13)
+    lat.close()
+
+
+@pytest.mark.parametrize("dims", [(4, 4, 4, 4), (6, 4, 4, 6)])
+def test_md_force_matches_oracle(wd, oracle, dims):
+    import torch
+    V = li.volume(dims)
+    U = li.random_su3_field(dims, 0.5, seed=5)
+    phi = li.gaussian_spinor(V // 2, seed=6)
+    kappa, beta = 0.15, 5.6
+    lat = wd.Lattice(dims)
+    F = torch.empty((V, 4, 3, 3), dtype=torch.complex128, device="cuda")
+    it = wd.wd_md_force(lat.ctx, F, dev(U), dev(phi), kappa, beta, wd.solver_params(tol=1e-13))
+    Fo, ito = oracle.md_force(dims, U, beta, kappa, phi, eo=True, tol=1e-13)
+    Fg = host(F)
+    err = np.abs(Fg - Fo).max() / np.abs(Fo).max()
+    note(f"force {dims}: {it} iters, max rel err {err:.2e}")
+    assert err <= 1e-9
+    lat.close()
+
+
+def test_trajectory_matches_oracle(wd, oracle):
+    dims = (4, 4, 4, 4)
+    U0 = li.random_su3_field(dims, 0.5, seed=50)
+    beta, kappa, tau, n = 5.6, 0.12, 0.5, 10
+    tight = wd.solver_params(tol=1e-13)
+    lat = wd.Lattice(dims)
+    Ud = dev(U0)
+    hp = wd.hmc_params(beta, kappa, tau, n, seed=51, traj=0, force=tight, h=tight)
+    r = wd.hmc_trajectory(lat.ctx, Ud, hp)
+    Uo, ro = oracle.hmc_trajectory(dims, U0, beta, kappa, tau, n, seed=51, traj=0, eo=True,
+                                   tol_force=1e-13, tol_h=1e-13)
+    note(f"gpu dH {r['dH']:.10f} oracle {ro['dH']:.10f}; accepted {r['accepted']} / {ro['accepted']}")
+    assert r["status"] == wd.WD_OK
+    assert abs(r["H_old"] - ro["H_old"]) <= 1e-9 * abs(ro["H_old"])
+    assert abs(r["dH"] - ro["dH"]) <= 1e-6
+    assert r["u"] == ro["u"]
+    assert bool(r["accepted"]) == ro["accepted"]
+    assert np.abs(host(Ud) - Uo).max() <= 1e-10
+    assert abs(r["plaquette"] - ro["plaquette"]) <= 1e-12
+    lat.close()
+
+
+def test_mixed_precision_force_solver(wd, oracle):
+    dims = (4, 4, 4, 4)
+    U0 = li.random_su3_field(dims, 0.5, seed=60)
+    lat = wd.Lattice(dims)
+    Ud = dev(U0)
+    hp = wd.hmc_params(5.6, 0.12, 0.5, 10, seed=61, traj=2,
+                       force=wd.solver_params(tol=1e-9, prec=wd.WD_F16),
+                       h=wd.solver_params(tol=1e-12))
+    r = wd.hmc_trajectory(lat.ctx, Ud, hp)
+    _, ro = oracle.hmc_trajectory(dims, U0, 5.6, 0.12, 0.5, 10, seed=61, traj=2, eo=True,
+                                  tol_force=1e-12, tol_h=1e-12)
+    note(f"mixed-force dH {r['dH']:.8f} vs oracle {ro['dH']:.8f}")
+    assert r["status"] == wd.WD_OK
+    assert abs(r["dH"] - ro["dH"]) <= 1e-4 * max(1.0, abs(ro["dH"]))
+    lat.close()
+
+
+def test_reject_leaves_field_and_context_unchanged(wd):
+    import torch
+    dims = (4, 4, 4, 4)
+    V = li.volume(dims)
+    U0 = li.random_su3_field(dims, 0.5, seed=70)
+    lat = wd.Lattice(dims)
+    Ud = dev(U0)
+    hp = wd.hmc_params(5.6, 0.12, 6.0, 2, seed=71, traj=0,
+                       force=wd.solver_params(tol=1e-10), h=wd.solver_params(tol=1e-10))
+    r = wd.hmc_trajectory(lat.ctx, Ud, hp)
+    assert not r["accepted"]
+    assert np.array_equal(host(Ud), U0)
+    # the context's packed links still hold U0
+    psi = li.gaussian_spinor(V // 2, seed=72)
+    out = torch.empty((V // 2, 4, 3), dtype=torch.complex128, device="cuda")
+    lat.dslash(out, dev(psi), wd.WD_EVEN, 0, wd.WD_F64)
+    lat2 = wd.Lattice(dims)
+    lat2.gauge_load(dev(U0))
+    out2 = torch.empty_like(out)
+    lat2.dslash(out2, dev(psi), wd.WD_EVEN, 0, wd.WD_F64)
+    assert torch.equal(out, out2)
+    lat.close()
+    lat2.close()
