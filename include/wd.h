@@ -92,6 +92,9 @@ typedef struct {
     double true_resid;    /* final |b - A x| / |b| in FP64                          */
     double seconds;       /* wall time of the whole batched call                   */
     int status;           /* wd_status of this RHS                                 */
+    int iters_fp64;       /* of iters, those run in FP64: all of them for an FP64  */
+                          /* solve; in a mixed solve, those after the RHS left the */
+                          /* sloppy precision because its true residual stalled    */
 } wd_solver_stats;
 
 /* Fill p with the defaults: tol 1e-10, maxiter 20000, FP64, eo 1, delta 0.1,
@@ -142,6 +145,50 @@ wd_status wd_mdagm(wd_ctx *c, double *out, const double *in, double kappa, int e
  * RHS are still solved); x holds the best iterate of every RHS. */
 wd_status wd_cg_solve(wd_ctx *c, double *x, const double *phi, int nrhs, const double *kappa,
                       const wd_solver_params *p, wd_solver_stats *st);
+
+/* ---------------------------------------------------------------------- */
+/* Solver sessions: persistent batched CG state for continuous batching.     */
+/* A session owns the device state of max_rhs slots on one context (one    */
+/* lattice and gauge field).  Right-hand sides join between steps; every    */
+/* running slot advances k iterations per step; reliable updates and        */
+/* convergence are decided from each slot's own history at multiples of k   */
+/* of its own iteration count, so a slot's result is bitwise the same alone */
+/* or batched with others (for equal k and parameters).  Calls on one       */
+/* session (and context) must not overlap; different contexts may run on    */
+/* different streams concurrently.                                          */
+/* ---------------------------------------------------------------------- */
+
+typedef struct wd_session wd_session;
+
+/* Create a session of max_rhs slots (1..1024) solving with parameters p
+ * (NULL = defaults; p->maxiter bounds each slot, p->poll is unused).
+ * Allocates the whole state up front (WD_ERR_OOM if it does not fit). */
+wd_status wd_session_create(wd_ctx *c, int max_rhs, const wd_solver_params *p, wd_session **s);
+
+/* Free the session and its device state.  NULL is accepted. */
+wd_status wd_session_destroy(wd_session *s);
+
+/* Add nrhs right-hand sides phi ([nrhs][sites][4][3] device, sites = Vh for
+ * eo, V otherwise) with hopping parameters kappa (HOST [nrhs]); slots (HOST
+ * [nrhs], may be NULL) receives the slots used.  WD_ERR_OOM if fewer than
+ * nrhs slots are free (nothing is added then).  phi may be freed after the
+ * call returns. */
+wd_status wd_session_add(wd_session *s, const double *phi, int nrhs, const double *kappa, int32_t *slots);
+
+/* Run k_iters iterations of every running slot, then the residual checks
+ * (synchronises the context's stream). */
+wd_status wd_session_step(wd_session *s, int k_iters);
+
+/* Slot states (HOST [max_rhs], 0 free, 1 running, 2 done; may be NULL) and
+ * stats (HOST [max_rhs], may be NULL; seconds = time since creation). */
+wd_status wd_session_poll(wd_session *s, int32_t *state, wd_solver_stats *st);
+
+/* Copy the solution of a done slot to x ([sites][4][3] device) and free the
+ * slot.  WD_ERR_STATE if the slot is not done. */
+wd_status wd_session_take(wd_session *s, int slot, double *x);
+
+/* Device bytes of a session of max_rhs slots (without the gauge field). */
+size_t wd_session_bytes(const int32_t dims[4], int max_rhs, const wd_solver_params *p);
 
 /* ---------------------------------------------------------------------- */
 /* Molecular dynamics and HMC (Sec. 2, eq. 5; Sec. 3 kernels 2-4 and the     */

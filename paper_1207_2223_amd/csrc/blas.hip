@@ -245,6 +245,26 @@ __global__ void __launch_bounds__(kBlock) k_axpy_const(FArg p, FArg r, double a,
     SpinorIO<SP>::store(site_base(p, rid, sub), p.cs, i, pv);
 }
 
+// p = r + (num[rid] / den[rid]) p
+template <int SP>
+__global__ void __launch_bounds__(kBlock) k_xpay_ratio(FArg p, FArg r, const double *num, const double *den,
+                                                        int Vh, int nsub, const int *active)
+{
+    typedef typename SpinorIO<SP>::real real;
+    const int rid = active[blockIdx.y];
+    const int s = blockIdx.x * kBlock + threadIdx.x;
+    if (s >= nsub * Vh) return;
+    const int sub = s / Vh, i = s - sub * Vh;
+    const double d = den[rid];
+    const real b = (real)(d > 0.0 ? num[rid] / d : 0.0);
+    real pv[24], rv[24];
+    SpinorIO<SP>::load(site_base(p, rid, sub), p.cs, i, pv);
+    SpinorIO<SP>::load(site_base(r, rid, sub), r.cs, i, rv);
+#pragma unroll
+    for (int k = 0; k < 24; k++) pv[k] = fmaT(b, pv[k], rv[k]);
+    SpinorIO<SP>::store(site_base(p, rid, sub), p.cs, i, pv);
+}
+
 // One work-group per active RHS: fixed-order sum of its partials, then the
 // CG scalar update selected by mode.
 __global__ void __launch_bounds__(kFinBlock) k_finalize(const double *partial, int pstride, int nw,
@@ -410,6 +430,17 @@ hipError_t blas_axpy_const(const Field &p, const Field &r, double a, int Vh, con
     if (nact == 0) return hipSuccess;
     if (p.sp != r.sp) return hipErrorInvalidValue;
 #define F(SP) hipLaunchKernelGGL(k_axpy_const<SP>, grid_of(Vh, p.nsub, nact), dim3(kBlock), 0, s, fa(p), fa(r), a, Vh, p.nsub, active)
+    SP_SWITCH(p.sp, F)
+#undef F
+    return hipGetLastError();
+}
+
+hipError_t blas_xpay_ratio(const Field &p, const Field &r, const double *num, const double *den, int Vh,
+                           const int *active, int nact, hipStream_t s)
+{
+    if (nact == 0) return hipSuccess;
+    if (p.sp != r.sp) return hipErrorInvalidValue;
+#define F(SP) hipLaunchKernelGGL(k_xpay_ratio<SP>, grid_of(Vh, p.nsub, nact), dim3(kBlock), 0, s, fa(p), fa(r), num, den, Vh, p.nsub, active)
     SP_SWITCH(p.sp, F)
 #undef F
     return hipGetLastError();

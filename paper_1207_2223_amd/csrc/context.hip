@@ -578,12 +578,13 @@ size_t wd_bytes_required(const int32_t dims[4], int nrhs, const wd_solver_params
     wd_solver_params d;
     wd_solver_defaults(&d);
     if (!p) p = &d;
-    const size_t Vh = (size_t)V / 2;
+    // fields are allocated with the padded per-parity stride
+    const size_t Vh = (size_t)padded_stride((int)(V / 2));
     size_t links = (144 + 48 + 24 + 72) * 4 * (size_t)V;
     const int sp = p->prec_sloppy & 0xf;
     const size_t nsub = p->eo ? 1 : 2;
-    // FP64: b, x, r, two temporaries and Ap
-    size_t f64 = 6 * 192 * Vh * nsub;
+    // FP64: b, x, r, p, Ap, a full-size temporary and a one-parity temporary
+    size_t f64 = (6 * nsub + 1) * 192 * Vh;
     size_t sl = 0;
     if (sp != WD_F64) sl = 4 * spinor_site_bytes(sp == WD_F32 ? SP_F32 : SP_F16) * Vh * nsub + 96 * Vh * nsub;
     return links + (size_t)nrhs * (f64 + sl) + (size_t)nrhs * 4096;

@@ -1,6 +1,7 @@
 // solver.hip -- conjugate gradient on M^dag M (eq. 3-4: the inverse of the
 // two-flavour fermion matrix applied to the pseudofermion), batched over
-// right-hand sides, in FP64 or mixed precision with FP64 reliable updates.
+// right-hand sides, in FP64 or mixed precision with FP64 reliable updates,
+// and persistent solver sessions for continuous batching.
 //
 // Even-odd iteration (A = Mhat^dag Mhat, Mhat = 1 - kappa^2 D_eo D_oe), per
 // active RHS, four stencil sweeps and one vector kernel:
@@ -13,18 +14,27 @@
 //   beta = rr' / rr                                  (finalize, on device)
 //   p    = r + beta p
 // alpha and beta never leave the device; the host reads the residual norms
-// every `poll` iterations.  In mixed precision p, r and the intermediates are
-// FP32 or FP16 (per-site norm) and the solution increment accumulates in
-// FP32; when |r| falls below delta * (its maximum since the last update), or
-// the sloppy residual claims convergence, the FP64 solution is advanced and
-// the residual is recomputed as b - A x in FP64 (reliable update).
-// Convergence is declared only on that FP64 true residual.
+// after every step of k iterations.  In mixed precision p, r and the
+// intermediates are FP32 or FP16 (per-site norm) and the solution increment
+// accumulates in FP32; when |r| falls below delta * (its maximum since the
+// last update), or the sloppy residual claims convergence, the FP64 solution
+// is advanced and the residual is recomputed as b - A x in FP64 (reliable
+// update).  Convergence is declared only on that FP64 true residual.
+//
+// Every decision for a right-hand side depends only on its own residual
+// history at multiples of k of its own iteration count, and the kernels treat
+// every RHS independently (fixed reduction trees), so a RHS gives the same
+// bits whether it is solved alone or batched with others joining at step
+// boundaries.
 #include <stdio.h>
 #include <stdlib.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
+#include <cstring>
+#include <string>
 #include <vector>
 
 #include "wd_internal.h"
@@ -33,67 +43,6 @@ namespace wd {
 
 namespace {
 
-struct Scalars {
-    double *bb, *rr, *alpha, *beta, *coef1, *coef2, *partial;
-    int pstride;
-};
-
-struct Ops {
-    wd_ctx *c;
-    int eo;
-    Scalars s;
-    const TuneCfg *cfg;
-};
-
-// out = A in for the active RHS in precision (sp, lk), using t_o / t_e as
-// temporaries (eo) or T (full).  When pAp != nullptr the first half's norm
-// partials go to the scalar partial buffer (pAp = |M in|^2).
-wd_status apply_A(const Ops &o, int sp, int lk, const Field &in, const Field &out,
-                  const Field &t_o, const Field &t_e, const int *act, int nact, bool norm)
-{
-    wd_ctx *c = o.c;
-    Sweep sw;
-    sw.sp = sp;
-    sw.lk = lk;
-    sw.xp = sp;
-    sw.active = act;
-    sw.nact = nact;
-    if (o.eo) {
-        sw.coef = o.s.coef2;
-        sw.P = 1; sw.dag = 0; sw.epi = EPI_PLAIN; sw.in = in; sw.out = t_o;
-        WD_TRY(run_sweep(c, sw, o.cfg));
-        sw.P = 0; sw.epi = EPI_XPAY; sw.in = t_o; sw.x = in; sw.out = t_e;
-        sw.partial = norm ? o.s.partial : nullptr; sw.pstride = o.s.pstride; sw.pw_off = 0;
-        WD_TRY(run_sweep(c, sw, o.cfg));
-        sw.partial = nullptr;
-        sw.P = 1; sw.dag = 1; sw.epi = EPI_PLAIN; sw.in = t_e; sw.out = t_o;
-        WD_TRY(run_sweep(c, sw, o.cfg));
-        sw.P = 0; sw.epi = EPI_XPAY; sw.in = t_o; sw.x = t_e; sw.out = out;
-        WD_TRY(run_sweep(c, sw, o.cfg));
-    } else {
-        // T = M in (both parities), out = M^dag T
-        const Field &T = t_e;
-        sw.coef = o.s.coef1;
-        sw.epi = EPI_XPAY;
-        for (int pass = 0; pass < 2; pass++) {
-            const Field &src = pass ? T : in;
-            const Field &dst = pass ? out : T;
-            sw.dag = pass;
-            for (int P = 0; P < 2; P++) {
-                sw.P = P;
-                sw.in = sub_view(src, 1 - P);
-                sw.x = sub_view(src, P);
-                sw.out = sub_view(dst, P);
-                sw.partial = (norm && pass == 0) ? o.s.partial : nullptr;
-                sw.pstride = o.s.pstride;
-                sw.pw_off = P * ngroups_of((int)c->Vh);
-                WD_TRY(run_sweep(c, sw, o.cfg));
-            }
-        }
-    }
-    return WD_OK;
-}
-
 #define HIPCHK(expr)                                                                               \
     do {                                                                                          \
         hipError_t e__ = (expr);                                                                  \
@@ -101,11 +50,488 @@ wd_status apply_A(const Ops &o, int sp, int lk, const Field &in, const Field &ou
             return set_error(WD_ERR_HIP, "%s: %s (%s:%d)", #expr, hipGetErrorString(e__), __FILE__, __LINE__); \
     } while (0)
 
+enum { SLOT_FREE = 0, SLOT_RUNNING = 1, SLOT_DONE = 2 };
+
 }  // namespace
+
+struct BatchSolver {
+    // one set of iterated fields: the sloppy lane (prec_sloppy), or the FP64
+    // lane that finishes right-hand sides escalated out of the sloppy one
+    struct Lane {
+        int sp, lk, xp;
+        Field P, R, T2, TO, X;
+        bool sloppy;  // X is an increment added to x64 at reliable updates
+    };
+
+    // a slot whose FP64 true residual has not reached a new minimum over this
+    // many consecutive reliable updates leaves the sloppy lane for FP64
+    static constexpr int kStallUpdates = 3;
+    // a sloppy slot gets a reliable update at least this often (iterations)
+    static constexpr int kMaxItersPerUpdate = 256;
+    // restart p = r when the true residual exceeds the recursive one by more
+    // than this factor (in |r|^2): the recursion has lost its accuracy
+    static constexpr double kDriftRestart = 4.0;
+
+    wd_ctx *c = nullptr;
+    wd_solver_params p{};
+    std::string pre;  // workspace name prefix
+    int cap = 0, sp = 0, lk = 0, xp = 0, nsub = 1, Vh = 0;
+    bool mixed = false;
+    int pstride = 0, nw1 = 0, nwF = 0, nwD = 0;
+    Field b64, x64, r64, to64, te64, Ap64, p64, ps, rs, t2s, tos, xs;
+    Lane lane_s{}, lane_d{};
+    double *bb = nullptr, *rr = nullptr, *alpha = nullptr, *beta = nullptr, *dre = nullptr, *dim = nullptr;
+    double *coef1 = nullptr, *coef2 = nullptr, *partial = nullptr, *partial2 = nullptr;
+    double *rr_s = nullptr;  // recursive |r|^2 saved at a reliable update
+    double *hbuf = nullptr;  // pinned, cap doubles
+    int *act = nullptr, *act64 = nullptr, *lst = nullptr;  // device id lists
+    std::vector<int> state, iters, iters64, rus, status, last_ru, stall, active, active64;
+    std::vector<double> bbh, maxrr, best, tres, kap;
+    bool trace = false;
+
+    std::string nm(const char *s) const { return pre + s; }
+
+    wd_status init(wd_ctx *ctx, int capacity, const wd_solver_params &prm, const std::string &prefix)
+    {
+        c = ctx;
+        p = prm;
+        pre = prefix;
+        cap = capacity;
+        WD_TRY(decode_prec(c, p.prec_sloppy, &sp, &lk, &xp));
+        if (!p.eo && sp != SP_F64) return set_error(WD_ERR_ARG, "the full-lattice solver runs in FP64 only");
+        mixed = sp != SP_F64;
+        nsub = p.eo ? 1 : 2;
+        Vh = (int)c->Vh;
+        nw1 = ngroups_of(Vh);
+        pstride = 2 * nw1 + 1;
+        nwF = p.eo ? nw1 : ngroups_of(2 * Vh);
+        nwD = p.eo ? nw1 : 2 * nw1;
+        void *vp;
+        WD_TRY(ws_get(c, nm("scal"), sizeof(double) * 9 * cap, &vp));
+        bb = (double *)vp;
+        rr = bb + cap;
+        alpha = rr + cap;
+        beta = alpha + cap;
+        dre = beta + cap;
+        dim = dre + cap;
+        coef1 = dim + cap;
+        coef2 = coef1 + cap;
+        rr_s = coef2 + cap;
+        WD_TRY(ws_get(c, nm("partial"), sizeof(double) * pstride * cap * 2, &vp));
+        partial = (double *)vp;
+        partial2 = partial + (size_t)pstride * cap;
+        WD_TRY(ws_get(c, nm("ids"), sizeof(int) * 3 * cap, &vp));
+        act = (int *)vp;
+        act64 = act + cap;
+        lst = act64 + cap;
+        WD_TRY(alloc_field(c, nm("b"), SP_F64, nsub, cap, &b64));
+        WD_TRY(alloc_field(c, nm("x"), SP_F64, nsub, cap, &x64));
+        WD_TRY(alloc_field(c, nm("r"), SP_F64, nsub, cap, &r64));
+        WD_TRY(alloc_field(c, nm("to"), SP_F64, 1, cap, &to64));
+        WD_TRY(alloc_field(c, nm("te"), SP_F64, nsub, cap, &te64));
+        WD_TRY(alloc_field(c, nm("ap"), SP_F64, nsub, cap, &Ap64));
+        WD_TRY(alloc_field(c, nm("p"), SP_F64, nsub, cap, &p64));
+        lane_d = Lane{SP_F64, c->lk64, SP_F64, p64, r64, te64, to64, x64, false};
+        if (mixed) {
+            WD_TRY(alloc_field(c, nm("ps"), sp, 1, cap, &ps));
+            WD_TRY(alloc_field(c, nm("rs"), sp, 1, cap, &rs));
+            WD_TRY(alloc_field(c, nm("t2s"), sp, 1, cap, &t2s));
+            WD_TRY(alloc_field(c, nm("tos"), sp, 1, cap, &tos));
+            WD_TRY(alloc_field(c, nm("xs"), xp, 1, cap, &xs));
+            lane_s = Lane{sp, lk, xp, ps, rs, t2s, tos, xs, true};
+        } else {
+            lane_s = lane_d;
+        }
+        WD_HIP(hipHostMalloc((void **)&hbuf, sizeof(double) * cap, hipHostMallocDefault));
+        state.assign(cap, SLOT_FREE);
+        iters.assign(cap, 0);
+        iters64.assign(cap, 0);
+        rus.assign(cap, 0);
+        status.assign(cap, WD_OK);
+        last_ru.assign(cap, 0);
+        stall.assign(cap, 0);
+        bbh.assign(cap, 0.0);
+        maxrr.assign(cap, 0.0);
+        best.assign(cap, 0.0);
+        tres.assign(cap, 0.0);
+        kap.assign(cap, 0.0);
+        active.clear();
+        active64.clear();
+        const char *te = getenv("WD_SOLVER_TRACE");
+        trace = te && te[0] == '1';
+        return WD_OK;
+    }
+
+    void release()
+    {
+        if (hbuf) (void)hipHostFree(hbuf);
+        hbuf = nullptr;
+        for (auto it = c->ws.begin(); it != c->ws.end();) {
+            if (it->first.compare(0, pre.size(), pre) == 0) {
+                (void)hipFree(it->second.first);
+                it = c->ws.erase(it);
+            } else {
+                ++it;
+            }
+        }
+    }
+
+    wd_status upload_list(const std::vector<int> &v, int *dev)
+    {
+        if (v.empty()) return WD_OK;
+        void *h;
+        WD_HIP(hipStreamSynchronize(c->stream));
+        WD_TRY(pinned_get(c, 0, sizeof(int) * v.size(), &h));
+        std::memcpy(h, v.data(), sizeof(int) * v.size());
+        WD_HIP(hipMemcpyAsync(dev, h, sizeof(int) * v.size(), hipMemcpyHostToDevice, c->stream));
+        WD_HIP(hipStreamSynchronize(c->stream));
+        return WD_OK;
+    }
+
+    wd_status upload_coefs()
+    {
+        std::vector<double> h(2 * cap);
+        for (int j = 0; j < cap; j++) {
+            h[j] = -kap[j];
+            h[cap + j] = -kap[j] * kap[j];
+        }
+        void *hp;
+        WD_HIP(hipStreamSynchronize(c->stream));
+        WD_TRY(pinned_get(c, 0, sizeof(double) * 2 * cap, &hp));
+        std::memcpy(hp, h.data(), sizeof(double) * 2 * cap);
+        WD_HIP(hipMemcpyAsync(coef1, hp, sizeof(double) * 2 * cap, hipMemcpyHostToDevice, c->stream));
+        WD_HIP(hipStreamSynchronize(c->stream));
+        return WD_OK;
+    }
+
+    // out = A in (FP64 or sloppy) for the listed RHS, temporaries to64, te64
+    wd_status apply_A(int spp, int lkk, const Field &in, const Field &out, const int *ids, int n, bool norm)
+    {
+        Sweep sw;
+        sw.sp = spp;
+        sw.lk = lkk;
+        sw.xp = spp;
+        sw.active = ids;
+        sw.nact = n;
+        if (p.eo) {
+            sw.coef = coef2;
+            sw.P = 1; sw.dag = 0; sw.epi = EPI_PLAIN; sw.in = in; sw.out = to64;
+            WD_TRY(run_sweep(c, sw, nullptr));
+            sw.P = 0; sw.epi = EPI_XPAY; sw.in = to64; sw.x = in; sw.out = te64;
+            sw.partial = norm ? partial : nullptr; sw.pstride = pstride; sw.pw_off = 0;
+            WD_TRY(run_sweep(c, sw, nullptr));
+            sw.partial = nullptr;
+            sw.P = 1; sw.dag = 1; sw.epi = EPI_PLAIN; sw.in = te64; sw.out = to64;
+            WD_TRY(run_sweep(c, sw, nullptr));
+            sw.P = 0; sw.epi = EPI_XPAY; sw.in = to64; sw.x = te64; sw.out = out;
+            WD_TRY(run_sweep(c, sw, nullptr));
+        } else {
+            const Field &T = te64;
+            sw.coef = coef1;
+            sw.epi = EPI_XPAY;
+            for (int pass = 0; pass < 2; pass++) {
+                const Field &src = pass ? T : in;
+                const Field &dst = pass ? out : T;
+                sw.dag = pass;
+                for (int P = 0; P < 2; P++) {
+                    sw.P = P;
+                    sw.in = sub_view(src, 1 - P);
+                    sw.x = sub_view(src, P);
+                    sw.out = sub_view(dst, P);
+                    sw.partial = (norm && pass == 0) ? partial : nullptr;
+                    sw.pstride = pstride;
+                    sw.pw_off = P * nw1;
+                    WD_TRY(run_sweep(c, sw, nullptr));
+                }
+            }
+        }
+        return WD_OK;
+    }
+
+    // One CG iteration of the listed RHS of a lane (see the file header).
+    wd_status iterate(const Lane &L, const int *ids, int n)
+    {
+        const hipStream_t s = c->stream;
+        if (p.eo) {
+            Sweep sw;
+            sw.sp = L.sp; sw.lk = L.lk; sw.xp = L.xp; sw.active = ids; sw.nact = n;
+            sw.coef = coef2;
+            sw.P = 1; sw.dag = 0; sw.epi = EPI_PLAIN; sw.in = L.P; sw.out = L.TO;
+            WD_TRY(run_sweep(c, sw, nullptr));
+            sw.P = 0; sw.epi = EPI_XPAY; sw.in = L.TO; sw.x = L.P; sw.out = L.T2;
+            sw.partial = partial; sw.pstride = pstride; sw.pw_off = 0;
+            WD_TRY(run_sweep(c, sw, nullptr));
+            HIPCHK(blas_finalize(partial, pstride, nwD, ids, n, FIN_ALPHA, rr, alpha, beta, nullptr, s));
+            sw.partial = nullptr;
+            sw.P = 1; sw.dag = 1; sw.epi = EPI_PLAIN; sw.in = L.T2; sw.out = L.TO;
+            WD_TRY(run_sweep(c, sw, nullptr));
+            sw.P = 0; sw.epi = EPI_CGUPD; sw.in = L.TO; sw.x = L.T2; sw.p = L.P; sw.xs = L.X; sw.r = L.R;
+            sw.alpha = alpha; sw.partial = partial;
+            WD_TRY(run_sweep(c, sw, nullptr));
+            HIPCHK(blas_finalize(partial, pstride, nw1, ids, n, FIN_BETA, rr, alpha, beta, nullptr, s));
+        } else {
+            WD_TRY(apply_A(L.sp, L.lk, L.P, Ap64, ids, n, true));
+            HIPCHK(blas_finalize(partial, pstride, nwD, ids, n, FIN_ALPHA, rr, alpha, beta, nullptr, s));
+            HIPCHK(blas_cg_update(L.X, L.P, L.R, Ap64, alpha, Vh, ids, n, partial, pstride, s));
+            HIPCHK(blas_finalize(partial, pstride, nwF, ids, n, FIN_BETA, rr, alpha, beta, nullptr, s));
+        }
+        HIPCHK(blas_p_update(L.P, L.R, beta, Vh, ids, n, s));
+        return WD_OK;
+    }
+
+    // Pack n right-hand sides (phi: [n][sites][4][3], device) into free slots
+    // and initialise their CG state.  slots_out (host) receives the slots.
+    wd_status add(const double *phi, int n, const double *kappa, int *slots_out)
+    {
+        std::vector<int> slots;
+        for (int j = 0; j < cap && (int)slots.size() < n; j++)
+            if (state[j] == SLOT_FREE) slots.push_back(j);
+        if ((int)slots.size() < n) return set_error(WD_ERR_OOM, "%d free slots, %d requested", (int)slots.size(), n);
+        const hipStream_t s = c->stream;
+        const long long site_doubles = (long long)24 * Vh * nsub;
+        for (int q = 0; q < n; q++) {
+            Field v = b64;
+            v.base = b64.base + slots[q] * b64.rs;
+            HIPCHK(pack_spinor(phi + q * site_doubles, v, 1, p.eo ? 0 : 1, c->g, s));
+            kap[slots[q]] = kappa[q];
+        }
+        WD_TRY(upload_coefs());
+        WD_TRY(upload_list(slots, lst));
+        HIPCHK(blas_norm(b64, Vh, lst, n, partial, pstride, s));
+        HIPCHK(blas_finalize(partial, pstride, nwF, lst, n, FIN_STORE, rr, alpha, beta, bb, s));
+        HIPCHK(blas_finalize(partial, pstride, nwF, lst, n, FIN_RR, rr, alpha, beta, nullptr, s));
+        HIPCHK(blas_zero(x64, Vh, lst, n, s));
+        HIPCHK(blas_copy(r64, b64, Vh, lst, n, s));
+        if (mixed) {
+            HIPCHK(blas_copy(rs, b64, Vh, lst, n, s));
+            HIPCHK(blas_zero(xs, Vh, lst, n, s));
+        }
+        HIPCHK(blas_copy(lane_s.P, lane_s.R, Vh, lst, n, s));
+        HIPCHK(hipMemcpyAsync(hbuf, bb, sizeof(double) * cap, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        for (int q = 0; q < n; q++) {
+            const int j = slots[q];
+            bbh[j] = hbuf[j];
+            iters[j] = iters64[j] = 0;
+            rus[j] = 0;
+            last_ru[j] = 0;
+            stall[j] = 0;
+            tres[j] = 0.0;
+            maxrr[j] = best[j] = bbh[j];
+            if (!std::isfinite(bbh[j])) {
+                state[j] = SLOT_DONE;
+                status[j] = WD_ERR_NAN;
+                tres[j] = NAN;
+            } else if (bbh[j] == 0.0) {
+                state[j] = SLOT_DONE;
+                status[j] = WD_OK;
+            } else {
+                state[j] = SLOT_RUNNING;
+                status[j] = WD_ERR_NOCONV;
+                active.push_back(j);
+            }
+            if (slots_out) slots_out[q] = j;
+        }
+        std::sort(active.begin(), active.end());
+        WD_TRY(upload_list(active, act));
+        return WD_OK;
+    }
+
+    // Reliable update of the listed RHS of a lane: (sloppy lane) x64 += X,
+    // X = 0; r64 = b - A x64 in FP64, rr = |r64|^2, R = r64.  The search
+    // direction P = R_old + beta_old p_prev was built from the replaced
+    // recursive residual R_old, beta_old = |R_old|^2 / |r_prev|^2; it is
+    // rebuilt with the true residual: q = P - R_old is made orthogonal to r64
+    // and P = r64 + (|r64|^2 / |R_old|^2) q, which is beta = |r64|^2 /
+    // |r_prev|^2 (as in reliable-update CG, Clark et al. 2010).  rrh[j]
+    // receives the new |r|^2.
+    wd_status reliable(const Lane &L, const std::vector<int> &ids, std::vector<double> &rrh)
+    {
+        if (ids.empty()) return WD_OK;
+        const hipStream_t s = c->stream;
+        WD_TRY(upload_list(ids, lst));
+        const int n = (int)ids.size();
+        HIPCHK(hipMemcpyAsync(rr_s, rr, sizeof(double) * cap, hipMemcpyDeviceToDevice, s));
+        HIPCHK(blas_axpy_const(L.P, L.R, -1.0, Vh, lst, n, s));
+        if (L.sloppy) HIPCHK(blas_add_zero(x64, L.X, Vh, lst, n, s));
+        WD_TRY(apply_A(SP_F64, c->lk64, x64, Ap64, lst, n, false));
+        HIPCHK(blas_resid(r64, b64, Ap64, Vh, lst, n, partial, pstride, s));
+        HIPCHK(blas_finalize(partial, pstride, nwF, lst, n, FIN_RR, rr, alpha, beta, nullptr, s));
+        if (L.sloppy) HIPCHK(blas_copy(L.R, r64, Vh, lst, n, s));
+        HIPCHK(blas_cdot(L.R, L.P, Vh, lst, n, partial, partial2, pstride, s));
+        HIPCHK(blas_finalize(partial, pstride, nwF, lst, n, FIN_STORE, rr, alpha, beta, dre, s));
+        HIPCHK(blas_finalize(partial2, pstride, nwF, lst, n, FIN_STORE, rr, alpha, beta, dim, s));
+        HIPCHK(blas_orth(L.P, L.R, dre, dim, rr, Vh, lst, n, s));
+        HIPCHK(blas_xpay_ratio(L.P, L.R, rr, rr_s, Vh, lst, n, s));
+        HIPCHK(hipMemcpyAsync(hbuf, rr, sizeof(double) * cap, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        for (int j : ids) rrh[j] = hbuf[j];
+        return WD_OK;
+    }
+
+    // k iterations of every running RHS, then the residual checks.
+    wd_status step(int k)
+    {
+        if ((active.empty() && active64.empty()) || k < 1) return WD_OK;
+        const hipStream_t s = c->stream;
+        const int nact = (int)active.size(), nact64 = (int)active64.size();
+        for (int kk = 0; kk < k; kk++) {
+            if (nact) WD_TRY(iterate(lane_s, act, nact));
+            if (nact64) WD_TRY(iterate(lane_d, act64, nact64));
+        }
+        for (int j : active) iters[j] += k;
+        for (int j : active64) {
+            iters[j] += k;
+            iters64[j] += k;
+        }
+        HIPCHK(hipMemcpyAsync(hbuf, rr, sizeof(double) * cap, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        const double tol2 = p.tol * p.tol, d2 = p.delta * p.delta;
+        std::vector<double> rrh(cap, 0.0), r2s(cap, 0.0);
+        std::vector<int> ru[2], keep[2];
+        for (int l = 0; l < 2; l++) {
+            const bool sl = l == 0 && mixed;  // a sloppy lane with FP64 updates
+            for (int j : (l == 0 ? active : active64)) {
+                const double r2 = hbuf[j];
+                r2s[j] = r2;
+                if (trace) fprintf(stderr, "[wd cg] it %d rhs %d %s |r|/|b| %.3e\n", iters[j], j,
+                                   l ? "fp64" : "sloppy", std::sqrt(r2 / bbh[j]));
+                if (!std::isfinite(r2)) {
+                    status[j] = WD_ERR_NAN;
+                    tres[j] = NAN;
+                    state[j] = SLOT_DONE;
+                    continue;
+                }
+                const bool at_cap = iters[j] >= p.maxiter;
+                if (r2 <= tol2 * bbh[j] || at_cap ||
+                    (sl && (r2 < d2 * maxrr[j] || iters[j] - last_ru[j] >= kMaxItersPerUpdate)))
+                    ru[l].push_back(j);
+                if (r2 > maxrr[j]) maxrr[j] = r2;
+                keep[l].push_back(j);
+            }
+        }
+        WD_TRY(reliable(lane_s, ru[0], rrh));
+        WD_TRY(reliable(lane_d, ru[1], rrh));
+        std::vector<int> restart[2], escalate;
+        for (int l = 0; l < 2; l++) {
+            std::vector<int> keep2;
+            for (int j : keep[l]) {
+                bool done = false, moved = false;
+                if (std::find(ru[l].begin(), ru[l].end(), j) != ru[l].end()) {
+                    rus[j]++;
+                    last_ru[j] = iters[j];
+                    if (trace)
+                        fprintf(stderr, "[wd cg] it %d rhs %d reliable update: true |r|/|b| %.3e\n", iters[j], j,
+                                std::sqrt(rrh[j] / bbh[j]));
+                    if (!std::isfinite(rrh[j])) {
+                        status[j] = WD_ERR_NAN;
+                        tres[j] = NAN;
+                        done = true;
+                    } else if (rrh[j] <= tol2 * bbh[j]) {
+                        status[j] = WD_OK;
+                        tres[j] = std::sqrt(rrh[j] / bbh[j]);
+                        done = true;
+                    } else if (iters[j] >= p.maxiter) {
+                        status[j] = WD_ERR_NOCONV;
+                        tres[j] = std::sqrt(rrh[j] / bbh[j]);
+                        done = true;
+                    } else {
+                        maxrr[j] = rrh[j];
+                        if (rrh[j] < best[j]) {
+                            best[j] = rrh[j];
+                            stall[j] = 0;
+                        } else {
+                            stall[j]++;
+                        }
+                        if (l == 0 && mixed && stall[j] >= kStallUpdates) {
+                            escalate.push_back(j);
+                            moved = true;
+                        } else if (rrh[j] > kDriftRestart * r2s[j]) {
+                            restart[l].push_back(j);
+                        }
+                    }
+                }
+                if (done)
+                    state[j] = SLOT_DONE;
+                else if (!moved)
+                    keep2.push_back(j);
+            }
+            keep[l].swap(keep2);
+        }
+        // restarts p = r; escalated slots start FP64 CG from p64 = r64 (the
+        // true residual of their current x64)
+        if (!restart[0].empty()) {
+            WD_TRY(upload_list(restart[0], lst));
+            HIPCHK(blas_copy(lane_s.P, lane_s.R, Vh, lst, (int)restart[0].size(), s));
+        }
+        for (int j : escalate) restart[1].push_back(j);
+        if (!restart[1].empty()) {
+            WD_TRY(upload_list(restart[1], lst));
+            HIPCHK(blas_copy(p64, r64, Vh, lst, (int)restart[1].size(), s));
+        }
+        if (trace) {
+            for (int l = 0; l < 2; l++)
+                for (int j : restart[l]) fprintf(stderr, "[wd cg] it %d rhs %d restart p = r\n", iters[j], j);
+            for (int j : escalate) fprintf(stderr, "[wd cg] it %d rhs %d continues in FP64\n", iters[j], j);
+        }
+        for (int j : escalate) keep[1].push_back(j);
+        std::sort(keep[1].begin(), keep[1].end());
+        if (keep[0] != active) {
+            active.swap(keep[0]);
+            WD_TRY(upload_list(active, act));
+        }
+        if (keep[1] != active64) {
+            active64.swap(keep[1]);
+            WD_TRY(upload_list(active64, act64));
+        }
+        return WD_OK;
+    }
+
+    bool running() const { return !active.empty() || !active64.empty(); }
+
+    wd_status unpack(int slot, double *x)
+    {
+        Field v = x64;
+        v.base = x64.base + slot * x64.rs;
+        HIPCHK(unpack_spinor(v, x, 1, p.eo ? 0 : 1, c->g, c->stream));
+        return WD_OK;
+    }
+
+    void fill_stats(int j, double secs, wd_solver_stats *st) const
+    {
+        st->iters = iters[j];
+        st->reliable_updates = rus[j];
+        st->true_resid = tres[j];
+        st->seconds = secs;
+        st->status = status[j];
+        st->iters_fp64 = mixed ? iters64[j] : iters[j];
+    }
+};
+
+static wd_status check_params(const wd_solver_params &p)
+{
+    if (!(p.tol > 0) || p.maxiter < 0 || p.poll < 1 || !(p.delta > 0 && p.delta < 1))
+        return set_error(WD_ERR_ARG, "bad solver parameters (tol %g maxiter %d poll %d delta %g)", p.tol,
+                         p.maxiter, p.poll, p.delta);
+    return WD_OK;
+}
 
 }  // namespace wd
 
 using namespace wd;
+
+struct wd_session {
+    BatchSolver bs;
+    std::chrono::steady_clock::time_point t0;
+};
+
+namespace {
+struct TunedScope {
+    wd_ctx *c;
+    bool old;
+    ~TunedScope() { c->use_tuned = old; }
+};
+}  // namespace
 
 extern "C" wd_status wd_cg_solve(wd_ctx *c, double *x, const double *phi, int nrhs,
                                  const double *kappa, const wd_solver_params *pin,
@@ -118,268 +544,135 @@ extern "C" wd_status wd_cg_solve(wd_ctx *c, double *x, const double *phi, int nr
     wd_solver_params p;
     wd_solver_defaults(&p);
     if (pin) p = *pin;
-    if (!(p.tol > 0) || p.maxiter < 0 || p.poll < 1 || !(p.delta > 0 && p.delta < 1))
-        return set_error(WD_ERR_ARG, "bad solver parameters (tol %g maxiter %d poll %d delta %g)",
-                         p.tol, p.maxiter, p.poll, p.delta);
-    int sp, lk, xp;
-    WD_TRY(decode_prec(c, p.prec_sloppy, &sp, &lk, &xp));
-    if (!p.eo && sp != SP_F64)
-        return set_error(WD_ERR_ARG, "the full-lattice solver runs in FP64 only");
+    WD_TRY(check_params(p));
     for (int j = 0; j < nrhs; j++)
         if (!std::isfinite(kappa[j])) return set_error(WD_ERR_ARG, "kappa[%d] not finite", j);
     WD_HIP(hipSetDevice(c->device));
-
-    const bool mixed = sp != SP_F64;
-    const int nsub = p.eo ? 1 : 2;
-    const int Vh = (int)c->Vh;
-    const hipStream_t s = c->stream;
-
-    // scalars: bb, rr, alpha, beta, coef1, coef2 (nrhs each) + partials
-    const int nw1 = ngroups_of(Vh);
-    const int pstride = 2 * nw1 + 1;
-    std::vector<double> hc1(nrhs), hc2(nrhs);
-    for (int j = 0; j < nrhs; j++) {
-        hc1[j] = -kappa[j];
-        hc2[j] = -kappa[j] * kappa[j];
-    }
-    Scalars sc;
-    void *vp;
-    WD_TRY(ws_get(c, "cg_scal", sizeof(double) * 6 * nrhs, &vp));
-    sc.bb = (double *)vp;
-    sc.rr = sc.bb + nrhs;
-    sc.alpha = sc.rr + nrhs;
-    sc.beta = sc.alpha + nrhs;
-    double *dre = sc.beta + nrhs, *dim = dre + nrhs;  // <r, p> after a reliable update
-    WD_TRY(upload_doubles(c, "cg_coef1", hc1.data(), nrhs, &sc.coef1));
-    WD_TRY(upload_doubles(c, "cg_coef2", hc2.data(), nrhs, &sc.coef2));
-    WD_TRY(ws_get(c, "cg_partial", sizeof(double) * pstride * nrhs * 2, &vp));
-    sc.partial = (double *)vp;
-    double *partial2 = sc.partial + (size_t)pstride * nrhs;
-    sc.pstride = pstride;
-    const TuneCfg *cfg = nullptr;  // per-sweep shapes come from the tuner when p.tuned
-    Ops o{c, p.eo, sc, cfg};
-    struct TunedScope {
-        wd_ctx *c;
-        bool old;
-        ~TunedScope() { c->use_tuned = old; }
-    } tscope{c, c->use_tuned};
+    TunedScope tscope{c, c->use_tuned};
     c->use_tuned = p.tuned != 0;
 
-    // fields
-    Field b64, x64, r64, to64, te64, Ap64;
-    WD_TRY(alloc_field(c, "cg_b", SP_F64, nsub, nrhs, &b64));
-    WD_TRY(alloc_field(c, "cg_x", SP_F64, nsub, nrhs, &x64));
-    WD_TRY(alloc_field(c, "cg_r", SP_F64, nsub, nrhs, &r64));
-    WD_TRY(alloc_field(c, "cg_to", SP_F64, 1, nrhs, &to64));
-    WD_TRY(alloc_field(c, "cg_te", SP_F64, nsub, nrhs, &te64));
-    WD_TRY(alloc_field(c, "cg_ap", SP_F64, nsub, nrhs, &Ap64));
-    Field ps, rs, t2s, tos, xs;
-    if (mixed) {
-        WD_TRY(alloc_field(c, "cg_ps", sp, 1, nrhs, &ps));
-        WD_TRY(alloc_field(c, "cg_rs", sp, 1, nrhs, &rs));
-        WD_TRY(alloc_field(c, "cg_t2s", sp, 1, nrhs, &t2s));
-        WD_TRY(alloc_field(c, "cg_tos", sp, 1, nrhs, &tos));
-        WD_TRY(alloc_field(c, "cg_xs", xp, 1, nrhs, &xs));
-    } else {
-        WD_TRY(alloc_field(c, "cg_p", SP_F64, nsub, nrhs, &ps));
-        rs = r64;
-        t2s = te64;
-        tos = to64;
-        xs = x64;
-    }
-
-    // all RHS ids
-    std::vector<int> all(nrhs);
-    for (int j = 0; j < nrhs; j++) all[j] = j;
-    int *act_all, *act, *act_ru;
-    WD_TRY(upload_ints(c, "cg_act_all", all.data(), nrhs, &act_all));
-
-    hipError_t e;
-    if ((e = pack_spinor(phi, b64, nrhs, p.eo ? 0 : 1, c->g, s)) != hipSuccess)
-        return set_error(WD_ERR_HIP, "pack: %s", hipGetErrorString(e));
-    const int nwF = p.eo ? nw1 : ngroups_of(2 * Vh);  // BLAS partial count
-    const int nwD = p.eo ? nw1 : 2 * nw1;            // stencil partial count
-    HIPCHK(blas_norm(b64, Vh, act_all, nrhs, sc.partial, pstride, s));
-    HIPCHK(blas_finalize(sc.partial, pstride, nwF, act_all, nrhs, FIN_STORE, sc.rr, sc.alpha, sc.beta, sc.bb, s));
-    HIPCHK(hipMemcpyAsync(sc.rr, sc.bb, sizeof(double) * nrhs, hipMemcpyDeviceToDevice, s));
-    HIPCHK(blas_zero(x64, Vh, act_all, nrhs, s));
-    HIPCHK(blas_copy(r64, b64, Vh, act_all, nrhs, s));
-    if (mixed) {
-        HIPCHK(blas_copy(rs, b64, Vh, act_all, nrhs, s));
-        HIPCHK(blas_zero(xs, Vh, act_all, nrhs, s));
-    }
-    HIPCHK(blas_copy(ps, rs, Vh, act_all, nrhs, s));
-
-    double *hbuf;
-    WD_TRY(pinned_get(c, 1, sizeof(double) * nrhs, &vp));
-    hbuf = (double *)vp;
-    HIPCHK(hipMemcpyAsync(hbuf, sc.bb, sizeof(double) * nrhs, hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    std::vector<double> bb(hbuf, hbuf + nrhs), maxrr(nrhs), rrh(nrhs), prevtrue(hbuf, hbuf + nrhs);
-    std::vector<int> restart;
-    std::vector<int> iters(nrhs, 0), rus(nrhs, 0), status(nrhs, WD_ERR_NOCONV);
-    std::vector<double> tres(nrhs, 0.0);
-    std::vector<int> active;
-    for (int j = 0; j < nrhs; j++) {
-        if (!std::isfinite(bb[j])) {
-            status[j] = WD_ERR_NAN;
-            tres[j] = NAN;
-        } else if (bb[j] == 0.0) {
-            status[j] = WD_OK;
-        } else {
-            active.push_back(j);
-            maxrr[j] = bb[j];
+    // the one-shot solver keeps its state in the context's "cg_" workspaces,
+    // reused across calls; only its pinned buffer is released here
+    BatchSolver bs;
+    struct PinnedScope {
+        BatchSolver &b;
+        ~PinnedScope()
+        {
+            if (b.hbuf) (void)hipHostFree(b.hbuf);
         }
-    }
-    const double tol2 = p.tol * p.tol, d2 = p.delta * p.delta;
-    // WD_SOLVER_TRACE=1 prints the residual history to stderr (diagnostics)
-    const char *trace_env = getenv("WD_SOLVER_TRACE");
-    const bool trace = trace_env && trace_env[0] == '1';
-
-    auto upload_active = [&](const std::vector<int> &v, const char *name, int **dev) -> wd_status {
-        return upload_ints(c, name, v.data(), (int)v.size(), dev);
-    };
-    WD_TRY(upload_active(active, "cg_act", &act));
-
-    // reliable update of the listed RHS: x64 += xs, r64 = b - A x64 (FP64),
-    // rr = |r64|^2, rs = r64.  The search direction p = r + beta p_old was
-    // built from the replaced residual; it is rebuilt as r_new + q with
-    // q = p - r_old = beta p_old made orthogonal to r_new
-    // (q -= <r_new, q> / <r_new, r_new> r_new).  Returns the new rr in rrh.
-    auto reliable = [&](const std::vector<int> &ids) -> wd_status {
-        if (ids.empty()) return WD_OK;
-        WD_TRY(upload_active(ids, "cg_act_ru", &act_ru));
-        const int n = (int)ids.size();
-        HIPCHK(blas_axpy_const(ps, rs, -1.0, Vh, act_ru, n, s));
-        if (mixed) HIPCHK(blas_add_zero(x64, xs, Vh, act_ru, n, s));
-        WD_TRY(apply_A(o, SP_F64, c->lk64, x64, Ap64, to64, te64, act_ru, n, false));
-        HIPCHK(blas_resid(r64, b64, Ap64, Vh, act_ru, n, sc.partial, pstride, s));
-        HIPCHK(blas_finalize(sc.partial, pstride, nwF, act_ru, n, FIN_RR, sc.rr, sc.alpha, sc.beta, nullptr, s));
-        if (mixed) HIPCHK(blas_copy(rs, r64, Vh, act_ru, n, s));
-        HIPCHK(blas_cdot(rs, ps, Vh, act_ru, n, sc.partial, partial2, pstride, s));
-        HIPCHK(blas_finalize(sc.partial, pstride, nwF, act_ru, n, FIN_STORE, sc.rr, sc.alpha, sc.beta, dre, s));
-        HIPCHK(blas_finalize(partial2, pstride, nwF, act_ru, n, FIN_STORE, sc.rr, sc.alpha, sc.beta, dim, s));
-        HIPCHK(blas_orth(ps, rs, dre, dim, sc.rr, Vh, act_ru, n, s));
-        HIPCHK(blas_axpy_const(ps, rs, 1.0, Vh, act_ru, n, s));
-        HIPCHK(hipMemcpyAsync(hbuf, sc.rr, sizeof(double) * nrhs, hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
-        for (int j : ids) rrh[j] = hbuf[j];
-        return WD_OK;
-    };
-
+    } pscope{bs};
+    WD_TRY(bs.init(c, nrhs, p, "cg_"));
+    WD_TRY(bs.add(phi, nrhs, kappa, nullptr));
     int it = 0;
-    while (!active.empty() && it < p.maxiter) {
-        const int nact = (int)active.size();
+    while (bs.running() && it < p.maxiter) {
         const int k = std::min(p.poll, p.maxiter - it);
-        for (int kk = 0; kk < k; kk++) {
-            Sweep sw;
-            sw.sp = sp; sw.lk = lk; sw.xp = xp; sw.active = act; sw.nact = nact;
-            if (p.eo) {
-                sw.coef = sc.coef2;
-                sw.P = 1; sw.dag = 0; sw.epi = EPI_PLAIN; sw.in = ps; sw.out = tos;
-                WD_TRY(run_sweep(c, sw, cfg));
-                sw.P = 0; sw.epi = EPI_XPAY; sw.in = tos; sw.x = ps; sw.out = t2s;
-                sw.partial = sc.partial; sw.pstride = pstride; sw.pw_off = 0;
-                WD_TRY(run_sweep(c, sw, cfg));
-                HIPCHK(blas_finalize(sc.partial, pstride, nwD, act, nact, FIN_ALPHA, sc.rr, sc.alpha, sc.beta, nullptr, s));
-                sw.partial = nullptr;
-                sw.P = 1; sw.dag = 1; sw.epi = EPI_PLAIN; sw.in = t2s; sw.out = tos;
-                WD_TRY(run_sweep(c, sw, cfg));
-                sw.P = 0; sw.epi = EPI_CGUPD; sw.in = tos; sw.x = t2s; sw.p = ps; sw.xs = xs; sw.r = rs;
-                sw.alpha = sc.alpha; sw.partial = sc.partial;
-                WD_TRY(run_sweep(c, sw, cfg));
-                HIPCHK(blas_finalize(sc.partial, pstride, nw1, act, nact, FIN_BETA, sc.rr, sc.alpha, sc.beta, nullptr, s));
-            } else {
-                WD_TRY(apply_A(o, sp, lk, ps, Ap64, to64, te64, act, nact, true));
-                HIPCHK(blas_finalize(sc.partial, pstride, nwD, act, nact, FIN_ALPHA, sc.rr, sc.alpha, sc.beta, nullptr, s));
-                HIPCHK(blas_cg_update(xs, ps, rs, Ap64, sc.alpha, Vh, act, nact, sc.partial, pstride, s));
-                HIPCHK(blas_finalize(sc.partial, pstride, nwF, act, nact, FIN_BETA, sc.rr, sc.alpha, sc.beta, nullptr, s));
-            }
-            HIPCHK(blas_p_update(ps, rs, sc.beta, Vh, act, nact, s));
-        }
+        WD_TRY(bs.step(k));
         it += k;
-        for (int j : active) iters[j] = it;
-        HIPCHK(hipMemcpyAsync(hbuf, sc.rr, sizeof(double) * nrhs, hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
-        std::vector<int> ru, keep;
-        if (trace)
-            for (int j : active) fprintf(stderr, "[wd cg] it %d rhs %d sloppy |r|/|b| %.3e\n", it, j, std::sqrt(hbuf[j] / bb[j]));
-        for (int j : active) {
-            const double r2 = hbuf[j];
-            if (!std::isfinite(r2)) {
-                status[j] = WD_ERR_NAN;
-                continue;
-            }
-            if (r2 <= tol2 * bb[j] || (mixed && r2 < d2 * maxrr[j])) ru.push_back(j);
-            if (r2 > maxrr[j]) maxrr[j] = r2;
-            keep.push_back(j);
-        }
-        if (!ru.empty()) {
-            WD_TRY(reliable(ru));
-            std::vector<int> keep2;
-            for (int j : keep) {
-                bool done = false;
-                for (int q : ru)
-                    if (q == j) {
-                        rus[j]++;
-                        if (trace) fprintf(stderr, "[wd cg] it %d rhs %d reliable update: true |r|/|b| %.3e\n", it, j, std::sqrt(rrh[j] / bb[j]));
-                        if (!std::isfinite(rrh[j])) {
-                            status[j] = WD_ERR_NAN;
-                            done = true;
-                        } else if (rrh[j] <= tol2 * bb[j]) {
-                            status[j] = WD_OK;
-                            tres[j] = std::sqrt(rrh[j] / bb[j]);
-                            done = true;
-                        } else {
-                            maxrr[j] = rrh[j];
-                            // a replacement that did not halve the true residual
-                            // means the sloppy iteration has stalled: restart
-                            if (rrh[j] > 0.25 * prevtrue[j]) restart.push_back(j);
-                            prevtrue[j] = rrh[j];
-                        }
-                    }
-                if (!done) keep2.push_back(j);
-            }
-            keep.swap(keep2);
-            if (!restart.empty()) {
-                int *act_rs;
-                WD_TRY(upload_active(restart, "cg_act_rs", &act_rs));
-                HIPCHK(blas_copy(ps, rs, Vh, act_rs, (int)restart.size(), s));
-                if (trace)
-                    for (int j : restart) fprintf(stderr, "[wd cg] it %d rhs %d restart p = r\n", it, j);
-                restart.clear();
-            }
-        }
-        if (keep.size() != active.size()) {
-            active.swap(keep);
-            WD_TRY(upload_active(active, "cg_act", &act));
-        }
     }
-    // unconverged RHS: fold in the sloppy increment and report the true residual
-    if (!active.empty()) {
-        WD_TRY(reliable(active));
-        for (int j : active) {
-            rus[j]++;
-            tres[j] = std::sqrt(rrh[j] / bb[j]);
-            status[j] = std::isfinite(rrh[j]) ? WD_ERR_NOCONV : WD_ERR_NAN;
+    for (int j = 0; j < nrhs; j++)  // only when maxiter = 0
+        if (bs.state[j] == SLOT_RUNNING) {
+            bs.status[j] = WD_ERR_NOCONV;
+            bs.state[j] = SLOT_DONE;
         }
-    }
-    if ((e = unpack_spinor(x64, x, nrhs, p.eo ? 0 : 1, c->g, s)) != hipSuccess)
-        return set_error(WD_ERR_HIP, "unpack: %s", hipGetErrorString(e));
-    HIPCHK(hipStreamSynchronize(s));
+    for (int j = 0; j < nrhs; j++) WD_TRY(bs.unpack(j, x + (size_t)j * 24 * c->Vh * bs.nsub));
+    WD_HIP(hipStreamSynchronize(c->stream));
     const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     wd_status ret = WD_OK;
     for (int j = 0; j < nrhs; j++) {
-        if (st) {
-            st[j].iters = iters[j];
-            st[j].reliable_updates = rus[j];
-            st[j].true_resid = tres[j];
-            st[j].seconds = secs;
-            st[j].status = status[j];
-        }
-        if (status[j] == WD_ERR_NAN) ret = WD_ERR_NAN;
-        else if (status[j] != WD_OK && ret == WD_OK) ret = (wd_status)status[j];
+        if (st) bs.fill_stats(j, secs, &st[j]);
+        if (bs.status[j] == WD_ERR_NAN) ret = WD_ERR_NAN;
+        else if (bs.status[j] != WD_OK && ret == WD_OK) ret = (wd_status)bs.status[j];
     }
     if (ret != WD_OK) set_error(ret, "%s", ret == WD_ERR_NAN ? "non-finite residual" : "not converged");
     return ret;
+}
+
+static std::atomic<unsigned> g_session_id{0};
+
+extern "C" wd_status wd_session_create(wd_ctx *c, int max_rhs, const wd_solver_params *pin, wd_session **out)
+{
+    if (!c || !out) return set_error(WD_ERR_ARG, "NULL argument");
+    if (max_rhs < 1 || max_rhs > 1024) return set_error(WD_ERR_ARG, "max_rhs %d out of range", max_rhs);
+    if (!c->have_gauge) return set_error(WD_ERR_STATE, "no gauge field loaded");
+    wd_solver_params p;
+    wd_solver_defaults(&p);
+    if (pin) p = *pin;
+    WD_TRY(check_params(p));
+    WD_HIP(hipSetDevice(c->device));
+    wd_session *s = new wd_session();
+    char pre[32];
+    snprintf(pre, sizeof(pre), "ses%u_", g_session_id.fetch_add(1));
+    wd_status st = s->bs.init(c, max_rhs, p, pre);
+    if (st != WD_OK) {
+        s->bs.release();
+        delete s;
+        return st;
+    }
+    s->t0 = std::chrono::steady_clock::now();
+    *out = s;
+    return WD_OK;
+}
+
+extern "C" wd_status wd_session_destroy(wd_session *s)
+{
+    if (!s) return WD_OK;
+    (void)hipSetDevice(s->bs.c->device);
+    (void)hipStreamSynchronize(s->bs.c->stream);
+    s->bs.release();
+    delete s;
+    return WD_OK;
+}
+
+extern "C" wd_status wd_session_add(wd_session *s, const double *phi, int nrhs, const double *kappa,
+                                    int32_t *slots)
+{
+    if (!s || !phi || !kappa || nrhs < 1) return set_error(WD_ERR_ARG, "bad argument");
+    for (int j = 0; j < nrhs; j++)
+        if (!std::isfinite(kappa[j])) return set_error(WD_ERR_ARG, "kappa[%d] not finite", j);
+    WD_HIP(hipSetDevice(s->bs.c->device));
+    std::vector<int> sl(nrhs);
+    WD_TRY(s->bs.add(phi, nrhs, kappa, sl.data()));
+    if (slots)
+        for (int j = 0; j < nrhs; j++) slots[j] = sl[j];
+    return WD_OK;
+}
+
+extern "C" wd_status wd_session_step(wd_session *s, int k_iters)
+{
+    if (!s || k_iters < 1) return set_error(WD_ERR_ARG, "bad argument");
+    wd_ctx *c = s->bs.c;
+    WD_HIP(hipSetDevice(c->device));
+    TunedScope tscope{c, c->use_tuned};
+    c->use_tuned = s->bs.p.tuned != 0;
+    return s->bs.step(k_iters);
+}
+
+extern "C" wd_status wd_session_poll(wd_session *s, int32_t *state, wd_solver_stats *st)
+{
+    if (!s) return set_error(WD_ERR_ARG, "NULL session");
+    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - s->t0).count();
+    for (int j = 0; j < s->bs.cap; j++) {
+        if (state) state[j] = s->bs.state[j];
+        if (st) s->bs.fill_stats(j, secs, &st[j]);
+    }
+    return WD_OK;
+}
+
+extern "C" wd_status wd_session_take(wd_session *s, int slot, double *x)
+{
+    if (!s || !x) return set_error(WD_ERR_ARG, "NULL argument");
+    if (slot < 0 || slot >= s->bs.cap) return set_error(WD_ERR_ARG, "slot %d out of range", slot);
+    if (s->bs.state[slot] != SLOT_DONE) return set_error(WD_ERR_STATE, "slot %d is not done", slot);
+    WD_HIP(hipSetDevice(s->bs.c->device));
+    WD_TRY(s->bs.unpack(slot, x));
+    WD_HIP(hipStreamSynchronize(s->bs.c->stream));
+    s->bs.state[slot] = SLOT_FREE;
+    return WD_OK;
+}
+
+extern "C" size_t wd_session_bytes(const int32_t dims[4], int max_rhs, const wd_solver_params *p)
+{
+    // the solver state of max_rhs slots, without the gauge field
+    const size_t all = wd_bytes_required(dims, max_rhs, p), gauge = wd_bytes_required(dims, 0, p);
+    return all > gauge ? all - gauge : 0;
 }

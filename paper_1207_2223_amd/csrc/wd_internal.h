@@ -110,6 +110,8 @@ hipError_t blas_orth(const Field &p, const Field &r, const double *dre, const do
                      const double *rr, int Vh, const int *active, int nact, hipStream_t s);
 hipError_t blas_axpy_const(const Field &p, const Field &r, double a, int Vh, const int *active,
                            int nact, hipStream_t s);
+hipError_t blas_xpay_ratio(const Field &p, const Field &r, const double *num, const double *den, int Vh,
+                           const int *active, int nact, hipStream_t s);
 hipError_t blas_finalize(const double *partial, int pstride, int nw, const int *active, int nact,
                          int mode, double *rr, double *alpha, double *beta, double *out,
                          hipStream_t s);

@@ -38,7 +38,7 @@ class wd_solver_params(C.Structure):
 
 class wd_solver_stats(C.Structure):
     _fields_ = [("iters", C.c_int), ("reliable_updates", C.c_int), ("true_resid", C.c_double),
-                ("seconds", C.c_double), ("status", C.c_int)]
+                ("seconds", C.c_double), ("status", C.c_int), ("iters_fp64", C.c_int)]
 
 
 class wd_hmc_params(C.Structure):
@@ -76,6 +76,13 @@ _SIGS = {
     "wd_tune": (C.c_int, [_P, C.c_int, C.c_int, C.c_char_p, C.c_size_t]),
     "wd_bench_dslash": (C.c_int, [_P, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int,
                                   C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "wd_session_create": (C.c_int, [_P, C.c_int, C.POINTER(wd_solver_params), C.POINTER(_P)]),
+    "wd_session_destroy": (C.c_int, [_P]),
+    "wd_session_add": (C.c_int, [_P, _P, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int32)]),
+    "wd_session_step": (C.c_int, [_P, C.c_int]),
+    "wd_session_poll": (C.c_int, [_P, C.POINTER(C.c_int32), C.POINTER(wd_solver_stats)]),
+    "wd_session_take": (C.c_int, [_P, C.c_int, _P]),
+    "wd_session_bytes": (C.c_size_t, [_I32x4, C.c_int, C.POINTER(wd_solver_params)]),
     "wd_hmc_defaults": (None, [C.POINTER(wd_hmc_params)]),
     "wd_hmc_draw": (C.c_int, [_P, _P, _P, C.c_uint64, C.c_uint32]),
     "wd_md_force": (C.c_int, [_P, _P, _P, _P, C.c_double, C.c_double, C.POINTER(wd_solver_params),
@@ -202,7 +209,7 @@ def wd_cg_solve(ctx, x, phi, kappa, params=None, check=True):
     status = lib().wd_cg_solve(ctx, _ptr(x), _ptr(phi), nrhs, karr, C.byref(p), st)
     if check and status not in (WD_OK, WD_ERR_NOCONV, WD_ERR_NAN):
         _check(status)
-    stats = [dict(iters=s.iters, reliable_updates=s.reliable_updates, true_resid=s.true_resid,
+    stats = [dict(iters=s.iters, iters_fp64=s.iters_fp64, reliable_updates=s.reliable_updates, true_resid=s.true_resid,
                   seconds=s.seconds, status=s.status) for s in st]
     return status, stats
 
@@ -272,6 +279,53 @@ def wd_bench_dslash(ctx, nrhs, prec, epi=0, iters=20, tuned=1):
     _check(lib().wd_bench_dslash(ctx, int(nrhs), int(prec), int(epi), int(iters), int(tuned),
                                  C.byref(ms), C.byref(by)))
     return ms.value, by.value
+
+
+def wd_session_create(ctx, max_rhs, params=None):
+    h = C.c_void_p()
+    p = params if params is not None else wd_solver_defaults()
+    _check(lib().wd_session_create(ctx, int(max_rhs), C.byref(p), C.byref(h)))
+    return h
+
+
+def wd_session_destroy(sess):
+    _check(lib().wd_session_destroy(sess))
+
+
+def wd_session_add(sess, phi, kappa):
+    """phi: complex128 [nrhs, sites, 4, 3] device tensor; returns the slots."""
+    _c128(phi, (4, 3), "phi")
+    nrhs = 1 if phi.dim() == 3 else phi.shape[0]
+    ks = [float(kappa)] * nrhs if np.isscalar(kappa) else [float(k) for k in kappa]
+    if len(ks) != nrhs:
+        raise ValueError("one kappa per right-hand side")
+    slots = (C.c_int32 * nrhs)()
+    _check(lib().wd_session_add(sess, _ptr(phi), nrhs, (C.c_double * nrhs)(*ks), slots))
+    return list(slots)
+
+
+def wd_session_step(sess, k_iters):
+    _check(lib().wd_session_step(sess, int(k_iters)))
+
+
+def wd_session_poll(sess, max_rhs):
+    """(states list, stats list) for every slot."""
+    state = (C.c_int32 * max_rhs)()
+    st = (wd_solver_stats * max_rhs)()
+    _check(lib().wd_session_poll(sess, state, st))
+    stats = [dict(iters=s.iters, iters_fp64=s.iters_fp64, reliable_updates=s.reliable_updates, true_resid=s.true_resid,
+                  seconds=s.seconds, status=s.status) for s in st]
+    return list(state), stats
+
+
+def wd_session_take(sess, slot, x):
+    _c128(x, (4, 3), "x")
+    _check(lib().wd_session_take(sess, int(slot), _ptr(x)))
+
+
+def wd_session_bytes(dims, max_rhs, params=None):
+    p = C.byref(params) if params is not None else None
+    return int(lib().wd_session_bytes(_dims(dims), int(max_rhs), p))
 
 
 def wd_hmc_defaults():

@@ -108,3 +108,34 @@ def test_noconv_and_nan_and_zero(wd):
     assert np.all(Xh[1] == 0)
     assert np.all(np.isfinite(Xh[0]))
     lat.close()
+
+
+@pytest.mark.parametrize("prec", ["F16", "F16L", "F32"])
+def test_near_singular_operator_finishes_in_fp64(wd, oracle, prec):
+    """8^4, eps = 0.5, field seed 1003 at kappa = 0.14757 lies next to a
+    near-zero mode of Mhat (lowest eigenvalue of Mhat^dag Mhat about 5e-7
+    against a largest of about 2.1: condition number about 4e6), beyond what
+    FP16 arithmetic resolves.  The mixed solve must still reach 1e-10: the
+    right-hand side whose true residual stalls over its reliable updates is
+    finished by FP64 iterations (iters_fp64 > 0), and the FP64-only solve
+    needs no escalation."""
+    dims = (8, 8, 8, 8)
+    U = li.random_su3_field(dims, 0.5, seed=1003)
+    b = li.gaussian_spinor(li.volume(dims) // 2, seed=704, nrhs=2)[1:2]
+    code = {"F16": wd.WD_F16, "F16L": wd.WD_F16 | wd.WD_LINKS_F16, "F32": wd.WD_F32}[prec]
+    lat = wd.Lattice(dims)
+    lat.gauge_load(dev(U), recon=12)
+    kap = 0.14757
+    res = {}
+    for name, pc in (("mixed", code), ("fp64", wd.WD_F64)):
+        x = empty_like_dev(b)
+        st, stats = lat.cg_solve(x, dev(b), [kap], wd.solver_params(prec=pc, maxiter=3000))
+        assert st == wd.WD_OK, stats
+        tr = true_resid(oracle, dims, U, kap, host(x)[0], b[0], eo=True)
+        assert tr <= 1.2e-10, tr
+        res[name] = stats[0]
+    note(f"near-singular {prec}: mixed {res['mixed']['iters']} its ({res['mixed']['iters_fp64']} fp64, "
+         f"{res['mixed']['reliable_updates']} RU), fp64 {res['fp64']['iters']} its")
+    assert res["mixed"]["iters_fp64"] > 0
+    assert res["fp64"]["iters_fp64"] == res["fp64"]["iters"]
+    lat.close()

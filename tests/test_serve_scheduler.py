@@ -1,0 +1,142 @@
+"""The serving scheduler on the CPU with a fake executor: every request
+completes with its own results (slot reuse), the byte budget and the device's
+free memory bound admission, admission is FIFO per lattice, new requests join
+running batches (continuous batching), and latencies are accounted."""
+import threading
+import time
+
+import numpy as np
+import pytest
+
+from paper_1207_2223_amd.serve import SLOT_DONE, SLOT_FREE, SLOT_RUNNING, Admission, Request, Server
+
+
+class FakeExecutor:
+    """Slots finish after `need(kappa)` iterations; the 'solution' is 2 phi."""
+
+    def __init__(self, capacity, slot_bytes=100, step_time=0.002, need_fn=None):
+        self.capacity = capacity
+        self.need_fn = need_fn or (lambda k: int(round(1000 * k)) % 7 * 8 + 8)
+        self.slot_bytes = slot_bytes
+        self.step_time = step_time
+        self.state = [SLOT_FREE] * capacity
+        self.count = [0] * capacity
+        self.need = [0] * capacity
+        self.val = [None] * capacity
+        self.lock = threading.Lock()
+        self.max_running = 0
+
+    def io_bytes(self, nrhs):
+        return 10 * nrhs
+
+    def add(self, req):
+        free = [s for s in range(self.capacity) if self.state[s] == SLOT_FREE]
+        assert len(free) >= req.nrhs
+        slots = free[:req.nrhs]
+        for j, s in enumerate(slots):
+            self.state[s] = SLOT_RUNNING
+            self.count[s] = 0
+            self.need[s] = self.need_fn(req.kappa[j])
+            self.val[s] = 2 * req.phi[j]
+        self.max_running = max(self.max_running, sum(st != SLOT_FREE for st in self.state))
+        return slots
+
+    def step(self, k):
+        time.sleep(self.step_time)
+        for s in range(self.capacity):
+            if self.state[s] == SLOT_RUNNING:
+                self.count[s] += k
+                if self.count[s] >= self.need[s]:
+                    self.state[s] = SLOT_DONE
+
+    def poll(self):
+        stats = [dict(iters=self.count[s], status=0, true_resid=0.0, reliable_updates=0, seconds=0.0)
+                 for s in range(self.capacity)]
+        return list(self.state), stats
+
+    def take(self, req):
+        out = np.stack([self.val[s] for s in req.slots])
+        for s in req.slots:
+            assert self.state[s] == SLOT_DONE
+            self.state[s] = SLOT_FREE
+        return out
+
+
+def make_requests(n, lattices, seed=0, max_nrhs=3, gap=0.001):
+    rng = np.random.default_rng(seed)
+    reqs = []
+    for i in range(n):
+        nrhs = int(rng.integers(1, max_nrhs + 1))
+        phi = rng.standard_normal((nrhs, 4, 4, 3)) + 1j * rng.standard_normal((nrhs, 4, 4, 3))
+        reqs.append(Request(rid=i, lattice=lattices[i % len(lattices)], phi=phi,
+                            kappa=list(rng.uniform(0.14, 0.157, nrhs)), arrival=i * gap))
+    return reqs
+
+
+def test_all_complete_with_their_own_results():
+    ex = {"a": FakeExecutor(3), "b": FakeExecutor(4)}
+    srv = Server(ex, Admission(10 ** 9), k_iters=8)
+    reqs = make_requests(20, ["a", "b"])
+    summ = srv.run(reqs)
+    assert summ["completed"] == 20 and summ["rhs_solved"] == sum(r.nrhs for r in reqs)
+    for r in reqs:
+        assert np.array_equal(r.x, 2 * r.phi)
+        assert r.finished >= r.admitted >= 0
+        assert r.latency >= r.finished - r.admitted
+    assert ex["a"].max_running <= 3 and ex["b"].max_running <= 4
+    assert summ["latency_p99_s"] >= summ["latency_p50_s"] > 0
+
+
+def test_budget_bounds_admission_and_fifo_order():
+    ex = {"a": FakeExecutor(8)}
+    # every request costs nrhs*100 + nrhs*10 bytes; a budget of 330 admits at most 3 RHS
+    adm = Admission(330)
+    srv = Server(ex, adm, k_iters=8)
+    reqs = make_requests(12, ["a"], max_nrhs=3)
+    srv.run(reqs)
+    assert adm.peak <= 330 and adm.in_use == 0
+    assert ex["a"].max_running <= 3
+    adm_order = sorted(reqs, key=lambda r: r.admitted)
+    assert [r.rid for r in adm_order] == sorted(r.rid for r in reqs)  # FIFO
+
+
+def test_free_memory_bounds_admission():
+    # a device with 250 free bytes that the admitted requests use up
+    adm = Admission(10 ** 9)
+    adm.free_fn = lambda: 250 - adm.in_use
+    ex = {"a": FakeExecutor(8)}
+    srv = Server(ex, adm, k_iters=8)
+    reqs = make_requests(6, ["a"], max_nrhs=2)
+    srv.run(reqs)
+    # with 250 free bytes at most 2 RHS (220 bytes) fit at a time
+    assert ex["a"].max_running <= 2
+
+
+def test_continuous_batching_joins_running_batch():
+    ex = {"a": FakeExecutor(4, step_time=0.01, need_fn=lambda k: 400 if k > 0.155 else 8)}
+    srv = Server(ex, Admission(10 ** 9), k_iters=8)
+    phi = np.ones((1, 4, 4, 3), complex)
+    long_req = Request(0, "a", phi, [0.1556], arrival=0.0)   # needs many iterations
+    late_req = Request(1, "a", 3 * phi, [0.15], arrival=0.03)
+    srv.run([long_req, late_req])
+    assert late_req.admitted < long_req.finished
+    assert np.array_equal(late_req.x, 6 * phi)
+
+
+def test_oversized_request_is_an_error():
+    ex = {"a": FakeExecutor(2)}
+    srv = Server(ex, Admission(10 ** 9), k_iters=8)
+    bad = Request(0, "a", np.zeros((3, 4, 4, 3), complex), [0.15] * 3)
+    with pytest.raises(ValueError):
+        srv.run([bad])
+
+
+def test_latency_accounting_with_arrivals():
+    ex = {"a": FakeExecutor(3, step_time=0.002)}
+    srv = Server(ex, Admission(10 ** 9), k_iters=8)
+    reqs = make_requests(8, ["a"], gap=0.01)
+    summ = srv.run(reqs)
+    for r in reqs:
+        assert r.admitted >= r.arrival - 1e-3
+    lat = sorted(r.latency for r in reqs)
+    assert abs(summ["latency_p50_s"] - float(np.percentile(lat, 50))) < 1e-12
