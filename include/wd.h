@@ -162,7 +162,8 @@ typedef struct wd_session wd_session;
 
 /* Create a session of max_rhs slots (1..1024) solving with parameters p
  * (NULL = defaults; p->maxiter bounds each slot, p->poll is unused).
- * Allocates the whole state up front (WD_ERR_OOM if it does not fit). */
+ * Allocates the state of max_rhs slots (WD_ERR_OOM if it does not fit);
+ * wd_session_resize changes the number later. */
 wd_status wd_session_create(wd_ctx *c, int max_rhs, const wd_solver_params *p, wd_session **s);
 
 /* Free the session and its device state.  NULL is accepted. */
@@ -179,8 +180,20 @@ wd_status wd_session_add(wd_session *s, const double *phi, int nrhs, const doubl
  * (synchronises the context's stream). */
 wd_status wd_session_step(wd_session *s, int k_iters);
 
-/* Slot states (HOST [max_rhs], 0 free, 1 running, 2 done; may be NULL) and
- * stats (HOST [max_rhs], may be NULL; seconds = time since creation). */
+/* Change the number of slots to max_rhs (1..1024).  Slots below the smaller
+ * of the old and new counts keep their state (running solves continue
+ * unchanged, bitwise); shrinking needs every slot >= max_rhs to be free
+ * (WD_ERR_STATE otherwise).  The device state is reallocated at the new
+ * size, so memory is returned on shrinking.  WD_ERR_OOM leaves the session
+ * unchanged.  Synchronises the context's stream. */
+wd_status wd_session_resize(wd_session *s, int max_rhs);
+
+/* Current number of slots (0 for NULL). */
+int wd_session_capacity(const wd_session *s);
+
+/* Slot states (HOST [wd_session_capacity(s)], 0 free, 1 running, 2 done;
+ * may be NULL) and stats (HOST [wd_session_capacity(s)], may be NULL;
+ * seconds = time since creation). */
 wd_status wd_session_poll(wd_session *s, int32_t *state, wd_solver_stats *st);
 
 /* Copy the solution of a done slot to x ([sites][4][3] device) and free the

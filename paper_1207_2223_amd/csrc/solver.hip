@@ -71,6 +71,7 @@ struct BatchSolver {
     // restart p = r when the true residual exceeds the recursive one by more
     // than this factor (in |r|^2): the recursion has lost its accuracy
     static constexpr double kDriftRestart = 4.0;
+    static constexpr int kScalars = 9;  // per-slot device scalars (bb .. rr_s)
 
     wd_ctx *c = nullptr;
     wd_solver_params p{};
@@ -96,7 +97,6 @@ struct BatchSolver {
         c = ctx;
         p = prm;
         pre = prefix;
-        cap = capacity;
         WD_TRY(decode_prec(c, p.prec_sloppy, &sp, &lk, &xp));
         if (!p.eo && sp != SP_F64) return set_error(WD_ERR_ARG, "the full-lattice solver runs in FP64 only");
         mixed = sp != SP_F64;
@@ -106,8 +106,33 @@ struct BatchSolver {
         pstride = 2 * nw1 + 1;
         nwF = p.eo ? nw1 : ngroups_of(2 * Vh);
         nwD = p.eo ? nw1 : 2 * nw1;
+        WD_TRY(bind(capacity));
+        state.assign(cap, SLOT_FREE);
+        iters.assign(cap, 0);
+        iters64.assign(cap, 0);
+        rus.assign(cap, 0);
+        status.assign(cap, WD_OK);
+        last_ru.assign(cap, 0);
+        stall.assign(cap, 0);
+        bbh.assign(cap, 0.0);
+        maxrr.assign(cap, 0.0);
+        best.assign(cap, 0.0);
+        tres.assign(cap, 0.0);
+        kap.assign(cap, 0.0);
+        active.clear();
+        active64.clear();
+        const char *te = getenv("WD_SOLVER_TRACE");
+        trace = te && te[0] == '1';
+        return WD_OK;
+    }
+
+    // Device state of `capacity` slots (the named workspaces are created, or
+    // found with at least the needed size) and the pinned read-back buffer.
+    wd_status bind(int capacity)
+    {
+        cap = capacity;
         void *vp;
-        WD_TRY(ws_get(c, nm("scal"), sizeof(double) * 9 * cap, &vp));
+        WD_TRY(ws_get(c, nm("scal"), sizeof(double) * kScalars * cap, &vp));
         bb = (double *)vp;
         rr = bb + cap;
         alpha = rr + cap;
@@ -142,23 +167,83 @@ struct BatchSolver {
         } else {
             lane_s = lane_d;
         }
+        if (hbuf) (void)hipHostFree(hbuf);
+        hbuf = nullptr;
         WD_HIP(hipHostMalloc((void **)&hbuf, sizeof(double) * cap, hipHostMallocDefault));
-        state.assign(cap, SLOT_FREE);
-        iters.assign(cap, 0);
-        iters64.assign(cap, 0);
-        rus.assign(cap, 0);
-        status.assign(cap, WD_OK);
-        last_ru.assign(cap, 0);
-        stall.assign(cap, 0);
-        bbh.assign(cap, 0.0);
-        maxrr.assign(cap, 0.0);
-        best.assign(cap, 0.0);
-        tres.assign(cap, 0.0);
-        kap.assign(cap, 0.0);
-        active.clear();
-        active64.clear();
-        const char *te = getenv("WD_SOLVER_TRACE");
-        trace = te && te[0] == '1';
+        return WD_OK;
+    }
+
+    // Change the number of slots to ncap, keeping the state of slots below
+    // min(cap, ncap); slots at or above ncap must be free.  Every new buffer
+    // is allocated before any old one is released, so WD_ERR_OOM leaves the
+    // solver as it was.
+    wd_status resize(int ncap)
+    {
+        if (ncap == cap) return WD_OK;
+        for (int j = ncap; j < cap; j++)
+            if (state[j] != SLOT_FREE) return set_error(WD_ERR_STATE, "slot %d is in use", j);
+        struct Spec {
+            std::string name;
+            size_t per_slot;
+            int kind;  // 0: rows of per_slot bytes; 1: kScalars arrays of cap doubles; 2: scratch
+        };
+        std::vector<Spec> sp_list = {{nm("scal"), sizeof(double) * kScalars, 1},
+                                     {nm("partial"), sizeof(double) * pstride * 2, 2},
+                                     {nm("ids"), sizeof(int) * 3, 2},
+                                     {nm("b"), (size_t)b64.rs, 0},
+                                     {nm("x"), (size_t)x64.rs, 0},
+                                     {nm("r"), (size_t)r64.rs, 0},
+                                     {nm("to"), (size_t)to64.rs, 0},
+                                     {nm("te"), (size_t)te64.rs, 0},
+                                     {nm("ap"), (size_t)Ap64.rs, 0},
+                                     {nm("p"), (size_t)p64.rs, 0}};
+        if (mixed)
+            for (auto f : {std::make_pair("ps", &ps), std::make_pair("rs", &rs), std::make_pair("t2s", &t2s),
+                           std::make_pair("tos", &tos), std::make_pair("xs", &xs)})
+                sp_list.push_back({nm(f.first), (size_t)f.second->rs, 0});
+        const hipStream_t s = c->stream;
+        WD_HIP(hipStreamSynchronize(s));
+        std::vector<void *> fresh(sp_list.size(), nullptr);
+        for (size_t i = 0; i < sp_list.size(); i++) {
+            if (hipMalloc(&fresh[i], sp_list[i].per_slot * ncap) != hipSuccess) {
+                (void)hipGetLastError();
+                for (size_t q = 0; q < i; q++) (void)hipFree(fresh[q]);
+                return set_error(WD_ERR_OOM, "session resize to %d slots: device allocation failed", ncap);
+            }
+        }
+        const int keep = std::min(cap, ncap);
+        for (size_t i = 0; i < sp_list.size(); i++) {
+            auto it = c->ws.find(sp_list[i].name);
+            char *old = (char *)it->second.first;
+            if (sp_list[i].kind == 0 && keep > 0) {
+                WD_HIP(hipMemcpyAsync(fresh[i], old, sp_list[i].per_slot * keep, hipMemcpyDeviceToDevice, s));
+            } else if (sp_list[i].kind == 1 && keep > 0) {
+                for (int a = 0; a < kScalars; a++)
+                    WD_HIP(hipMemcpyAsync((double *)fresh[i] + (size_t)a * ncap, (double *)old + (size_t)a * cap,
+                                          sizeof(double) * keep, hipMemcpyDeviceToDevice, s));
+            }
+        }
+        WD_HIP(hipStreamSynchronize(s));
+        for (size_t i = 0; i < sp_list.size(); i++) {
+            auto it = c->ws.find(sp_list[i].name);
+            (void)hipFree(it->second.first);
+            it->second = {fresh[i], sp_list[i].per_slot * ncap};
+        }
+        WD_TRY(bind(ncap));
+        state.resize(cap, SLOT_FREE);
+        iters.resize(cap, 0);
+        iters64.resize(cap, 0);
+        rus.resize(cap, 0);
+        status.resize(cap, WD_OK);
+        last_ru.resize(cap, 0);
+        stall.resize(cap, 0);
+        bbh.resize(cap, 0.0);
+        maxrr.resize(cap, 0.0);
+        best.resize(cap, 0.0);
+        tres.resize(cap, 0.0);
+        kap.resize(cap, 0.0);
+        WD_TRY(upload_list(active, act));
+        WD_TRY(upload_list(active64, act64));
         return WD_OK;
     }
 
@@ -646,6 +731,16 @@ extern "C" wd_status wd_session_step(wd_session *s, int k_iters)
     c->use_tuned = s->bs.p.tuned != 0;
     return s->bs.step(k_iters);
 }
+
+extern "C" wd_status wd_session_resize(wd_session *s, int max_rhs)
+{
+    if (!s) return set_error(WD_ERR_ARG, "NULL session");
+    if (max_rhs < 1 || max_rhs > 1024) return set_error(WD_ERR_ARG, "max_rhs %d out of range", max_rhs);
+    WD_HIP(hipSetDevice(s->bs.c->device));
+    return s->bs.resize(max_rhs);
+}
+
+extern "C" int wd_session_capacity(const wd_session *s) { return s ? s->bs.cap : 0; }
 
 extern "C" wd_status wd_session_poll(wd_session *s, int32_t *state, wd_solver_stats *st)
 {

@@ -8,15 +8,18 @@ own worker thread, so work on different lattices overlaps on the device.
 
 Continuous batching: a worker alternates "admit what fits" and "run k
 iterations of every running slot"; requests arriving while others run join
-at the next step boundary as soon as their lattice has free slots and the
-HBM budget allows, and leave as soon as all their right-hand sides are done.
-Admission is FIFO per lattice and charges each request its bytes (session
-slots plus its input/output buffers) against a global budget, also checked
-against the device's actual free memory.
+at the next step boundary, and leave as soon as all their right-hand sides
+are done.  Admission is FIFO per lattice and by device memory: a session's
+slots are allocated when a request needs them (the session grows) and given
+back when its lattice's queue drains (it shrinks, or is freed when idle), so
+the bytes charged against the global budget -- session slots plus each
+request's input/output buffers -- are bytes actually held on the device; each
+admission is also checked against the device's free memory.
 
 The scheduler core (Admission, Server) is independent of the device: the
-executor interface is `capacity`, `slot_bytes`, `io_bytes(nrhs)`,
-`add(req) -> slots`, `step(k)`, `poll() -> states, stats`, `take(slot)`.
+executor interface is `max_slots`, `slot_bytes`, `io_bytes(nrhs)`,
+`grow_bytes(nrhs)`, `add(req) -> slots`, `step(k)`, `poll() -> states,
+stats`, `take(req)` and `shrink() -> bytes freed`.
 """
 import threading
 import time
@@ -112,21 +115,22 @@ class Server:
     def _admit(self, name, running):
         ex = self.ex[name]
         q = self.queues[name]
-        free = ex.capacity - sum(r.nrhs for r in running)
+        used = sum(r.nrhs for r in running)
         while q:
             req = q[0]
-            if req.nrhs > ex.capacity:
-                raise ValueError(f"request {req.rid} needs {req.nrhs} slots, lattice {name} has {ex.capacity}")
-            if req.nrhs > free:
+            if req.nrhs > ex.max_slots:
+                raise ValueError(f"request {req.rid} needs {req.nrhs} slots, lattice {name} has {ex.max_slots}")
+            if used + req.nrhs > ex.max_slots:
                 break
-            nbytes = req.nrhs * ex.slot_bytes + ex.io_bytes(req.nrhs)
-            if not self.adm.try_take(nbytes):
+            grow = ex.grow_bytes(req.nrhs)
+            io = ex.io_bytes(req.nrhs)
+            if not self.adm.try_take(grow + io):
                 break
             q.popleft()
-            req.nbytes = nbytes
+            req.nbytes = io
             req.admitted = self.now()
             req.slots = ex.add(req)
-            free -= req.nrhs
+            used += req.nrhs
             running.append(req)
 
     def _worker(self, name):
@@ -140,6 +144,7 @@ class Server:
                         if running:
                             break
                         if self.closed and not self.queues[name]:
+                            self.adm.give(ex.shrink())
                             return
                         self.cv.wait(timeout=0.05)
                 self.max_batch[name] = max(self.max_batch[name], sum(r.nrhs for r in running))
@@ -147,18 +152,26 @@ class Server:
                 self.steps[name] += 1
                 states, stats = ex.poll()
                 still = []
+                finished = False
                 for req in running:
                     if all(states[s] == SLOT_DONE for s in req.slots):
                         req.stats = [stats[s] for s in req.slots]
                         req.x = ex.take(req)
                         req.finished = self.now()
                         self.adm.give(req.nbytes)
+                        finished = True
                         with self.cv:
                             self.done.append(req)
-                            self.cv.notify_all()
                     else:
                         still.append(req)
                 running = still
+                if finished:
+                    with self.cv:
+                        if not self.queues[name]:
+                            # nothing waiting here: return the slots above the
+                            # highest one still in use (all of them when idle)
+                            self.adm.give(ex.shrink())
+                        self.cv.notify_all()
         except Exception as e:  # surfaced by run()
             self.errors.append(e)
             with self.cv:
@@ -208,10 +221,11 @@ class Server:
 
 
 class GpuExecutor:
-    """A lattice resident on the GPU: context + gauge field + solver session,
-    all work on its own stream."""
+    """A lattice resident on the GPU: context + gauge field, and a solver
+    session that grows to the slots admitted requests need (up to max_slots)
+    and shrinks when the scheduler says so; all work on its own stream."""
 
-    def __init__(self, dims, U, params, capacity, device=0):
+    def __init__(self, dims, U, params, max_slots, device=0):
         import torch
 
         from . import wd
@@ -221,27 +235,52 @@ class GpuExecutor:
         self.Vh = int(np.prod(dims)) // 2
         self.dev = torch.device(f"cuda:{device}")
         self.stream = torch.cuda.Stream(device=self.dev)
-        self.capacity = int(capacity)
+        self.max_slots = int(max_slots)
+        self.params = params
         with torch.cuda.stream(self.stream):
             self.lat = wd.Lattice(self.dims, device=device, stream=self.stream)
             Ud = torch.from_numpy(np.ascontiguousarray(U)).to(self.dev)
             self.lat.gauge_load(Ud, recon=12)
             self.stream.synchronize()
             del Ud
-        self.sess = wd.wd_session_create(self.lat.ctx, self.capacity, params)
+        self.sess = None
+        self.cap = 0
+        self.in_use = set()
         self.slot_bytes = wd.wd_session_bytes(self.dims, 1, params)
+        self.gauge_bytes = wd.wd_bytes_required(self.dims, 0, params)
         self.bufs = {}
 
     def io_bytes(self, nrhs):
         return 2 * nrhs * self.Vh * 192
 
+    def _needed_cap(self, nrhs):
+        free = self.cap - len(self.in_use)
+        return self.cap + max(0, nrhs - free)
+
+    def grow_bytes(self, nrhs):
+        return (self._needed_cap(nrhs) - self.cap) * self.slot_bytes
+
+    def _resize(self, cap):
+        if cap == self.cap:
+            return
+        if cap == 0:
+            self.wd.wd_session_destroy(self.sess)
+            self.sess = None
+        elif self.sess is None:
+            self.sess = self.wd.wd_session_create(self.lat.ctx, cap, self.params)
+        else:
+            self.wd.wd_session_resize(self.sess, cap)
+        self.cap = cap
+
     def add(self, req):
         torch = self.torch
+        self._resize(self._needed_cap(req.nrhs))
         with torch.cuda.stream(self.stream):
             phi = torch.from_numpy(np.ascontiguousarray(req.phi)).to(self.dev, non_blocking=False)
             x = torch.empty_like(phi)
         self.stream.synchronize()
         slots = self.wd.wd_session_add(self.sess, phi, req.kappa)
+        self.in_use.update(slots)
         self.bufs[req.rid] = x
         del phi
         return slots
@@ -250,19 +289,27 @@ class GpuExecutor:
         self.wd.wd_session_step(self.sess, k)
 
     def poll(self):
-        return self.wd.wd_session_poll(self.sess, self.capacity)
+        return self.wd.wd_session_poll(self.sess, self.cap)
 
     def take(self, req):
         x = self.bufs.pop(req.rid)
         for j, s in enumerate(req.slots):
             self.wd.wd_session_take(self.sess, s, x[j])
+            self.in_use.discard(s)
         self.stream.synchronize()
         return x.cpu().numpy()
+
+    def shrink(self):
+        """Free the slots above the highest one in use; returns the bytes."""
+        old = self.cap
+        self._resize(max(self.in_use) + 1 if self.in_use else 0)
+        return (old - self.cap) * self.slot_bytes
 
     def close(self):
         if self.sess is not None:
             self.wd.wd_session_destroy(self.sess)
             self.sess = None
+            self.cap = 0
         self.lat.close()
 
 

@@ -80,6 +80,8 @@ _SIGS = {
     "wd_session_destroy": (C.c_int, [_P]),
     "wd_session_add": (C.c_int, [_P, _P, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int32)]),
     "wd_session_step": (C.c_int, [_P, C.c_int]),
+    "wd_session_resize": (C.c_int, [_P, C.c_int]),
+    "wd_session_capacity": (C.c_int, [_P]),
     "wd_session_poll": (C.c_int, [_P, C.POINTER(C.c_int32), C.POINTER(wd_solver_stats)]),
     "wd_session_take": (C.c_int, [_P, C.c_int, _P]),
     "wd_session_bytes": (C.c_size_t, [_I32x4, C.c_int, C.POINTER(wd_solver_params)]),
@@ -308,8 +310,20 @@ def wd_session_step(sess, k_iters):
     _check(lib().wd_session_step(sess, int(k_iters)))
 
 
-def wd_session_poll(sess, max_rhs):
+def wd_session_resize(sess, max_rhs):
+    _check(lib().wd_session_resize(sess, int(max_rhs)))
+
+
+def wd_session_capacity(sess):
+    return int(lib().wd_session_capacity(sess))
+
+
+def wd_session_poll(sess, max_rhs=None):
     """(states list, stats list) for every slot."""
+    cap = wd_session_capacity(sess)
+    if max_rhs is not None and max_rhs != cap:
+        raise ValueError(f"the session has {cap} slots, not {max_rhs}")
+    max_rhs = cap
     state = (C.c_int32 * max_rhs)()
     st = (wd_solver_stats * max_rhs)()
     _check(lib().wd_session_poll(sess, state, st))

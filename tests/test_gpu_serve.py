@@ -34,7 +34,7 @@ def _requests(lattices, n, seed):
 
 def _solve_alone(wd, spec, params, req, k):
     from paper_1207_2223_amd.serve import SLOT_DONE, GpuExecutor
-    ex = GpuExecutor(spec["dims"], spec["U"], params, capacity=req.nrhs)
+    ex = GpuExecutor(spec["dims"], spec["U"], params, max_slots=req.nrhs)
     try:
         slots = ex.add(req)
         req.slots = slots
@@ -55,7 +55,7 @@ def test_results_same_alone_and_in_the_mix(wd, oracle):
                 "b": {"dims": (6, 4, 4, 6), "U": li.random_su3_field((6, 4, 4, 6), 0.5, seed=1004)}}
     params = wd.solver_params(prec=wd.WD_F16, tol=1e-10, maxiter=5000)
     k = 8
-    ex = {n: GpuExecutor(s["dims"], s["U"], params, capacity=6) for n, s in lattices.items()}
+    ex = {n: GpuExecutor(s["dims"], s["U"], params, max_slots=6) for n, s in lattices.items()}
     free = lambda: torch.cuda.mem_get_info()[0]
     srv = Server(ex, Admission(8 << 30, free_fn=free), k_iters=k)
     reqs = _requests(lattices, 10, seed=7)
@@ -100,4 +100,61 @@ def test_session_errors(wd):
     states, _ = wd.wd_session_poll(s, 2)
     assert states[slots[0]] == 0 and states[slots[1]] == 2
     wd.wd_session_destroy(s)
+    lat.close()
+
+
+def test_resize_keeps_running_slots_bitwise(wd):
+    """A session grown while a slot runs, and shrunk while another runs,
+    gives bitwise the results of a session that never changed size."""
+    import torch
+    dims = (6, 4, 4, 6)
+    Vh = li.volume(dims) // 2
+    lat = wd.Lattice(dims)
+    lat.gauge_load(dev(li.random_su3_field(dims, 0.5, seed=1004)), recon=12)
+    params = wd.solver_params(prec=wd.WD_F16, tol=1e-10, maxiter=4000)
+    phi = dev(li.gaussian_spinor(Vh, seed=11, nrhs=2))
+    kap = [0.150, 0.153]
+
+    def run_to_done(s, slots):
+        for _ in range(1000):
+            wd.wd_session_step(s, 8)
+            states, stats = wd.wd_session_poll(s)
+            if all(states[q] == 2 for q in slots):
+                return stats
+        raise AssertionError("session did not finish")
+
+    ref = wd.wd_session_create(lat.ctx, 2, params)
+    slots = wd.wd_session_add(ref, phi, kap)
+    st_ref = run_to_done(ref, slots)
+    x_ref = torch.empty_like(phi)
+    for j, q in enumerate(slots):
+        wd.wd_session_take(ref, q, x_ref[j])
+    wd.wd_session_destroy(ref)
+
+    s = wd.wd_session_create(lat.ctx, 1, params)
+    (q0,) = wd.wd_session_add(s, phi[:1].contiguous(), kap[:1])
+    for _ in range(3):
+        wd.wd_session_step(s, 8)
+    wd.wd_session_resize(s, 4)
+    assert wd.wd_session_capacity(s) == 4
+    (q1,) = wd.wd_session_add(s, phi[1:].contiguous(), kap[1:])
+    assert (q0, q1) == (0, 1)
+    x = torch.empty_like(phi)
+    stats = run_to_done(s, [q0])
+    wd.wd_session_take(s, q0, x[0])
+    states, _ = wd.wd_session_poll(s)
+    if states[q1] == 1:
+        with pytest.raises(wd.WDError) as e:
+            wd.wd_session_resize(s, 1)
+        assert e.value.status == wd.WD_ERR_STATE
+    wd.wd_session_resize(s, 2)
+    stats2 = run_to_done(s, [q1])
+    wd.wd_session_take(s, q1, x[1])
+    wd.wd_session_resize(s, 1)
+    assert wd.wd_session_capacity(s) == 1
+    wd.wd_session_destroy(s)
+    torch.cuda.synchronize()
+    note(f"resize: iters {stats[q0]['iters']}, {stats2[q1]['iters']} vs {st_ref[0]['iters']}, {st_ref[1]['iters']}")
+    assert stats[q0]["iters"] == st_ref[slots[0]]["iters"] and stats2[q1]["iters"] == st_ref[slots[1]]["iters"]
+    assert torch.equal(x, x_ref)
     lat.close()

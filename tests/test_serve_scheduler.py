@@ -12,26 +12,49 @@ from paper_1207_2223_amd.serve import SLOT_DONE, SLOT_FREE, SLOT_RUNNING, Admiss
 
 
 class FakeExecutor:
-    """Slots finish after `need(kappa)` iterations; the 'solution' is 2 phi."""
+    """Slots finish after `need(kappa)` iterations; the 'solution' is 2 phi.
+    Like the GPU executor, it holds only the slots it has grown to."""
 
-    def __init__(self, capacity, slot_bytes=100, step_time=0.002, need_fn=None):
-        self.capacity = capacity
+    def __init__(self, max_slots, slot_bytes=100, step_time=0.002, need_fn=None, held=None):
+        self.max_slots = max_slots
         self.need_fn = need_fn or (lambda k: int(round(1000 * k)) % 7 * 8 + 8)
         self.slot_bytes = slot_bytes
         self.step_time = step_time
-        self.state = [SLOT_FREE] * capacity
-        self.count = [0] * capacity
-        self.need = [0] * capacity
-        self.val = [None] * capacity
-        self.lock = threading.Lock()
+        self.state, self.count, self.need, self.val = [], [], [], []
         self.max_running = 0
+        self.max_cap = 0
+        self.held = held if held is not None else {"now": 0, "max": 0}
+
+    @property
+    def cap(self):
+        return len(self.state)
+
+    def _set_cap(self, cap):
+        d = cap - self.cap
+        if d > 0:
+            self.state += [SLOT_FREE] * d
+            self.count += [0] * d
+            self.need += [0] * d
+            self.val += [None] * d
+        else:
+            assert all(s == SLOT_FREE for s in self.state[cap:])
+            del self.state[cap:], self.count[cap:], self.need[cap:], self.val[cap:]
+        self.held["now"] += d * self.slot_bytes
+        self.held["max"] = max(self.held["max"], self.held["now"])
+        self.max_cap = max(self.max_cap, cap)
 
     def io_bytes(self, nrhs):
         return 10 * nrhs
 
+    def _missing(self, nrhs):
+        return max(0, nrhs - sum(s == SLOT_FREE for s in self.state))
+
+    def grow_bytes(self, nrhs):
+        return self._missing(nrhs) * self.slot_bytes
+
     def add(self, req):
-        free = [s for s in range(self.capacity) if self.state[s] == SLOT_FREE]
-        assert len(free) >= req.nrhs
+        self._set_cap(self.cap + self._missing(req.nrhs))
+        free = [s for s in range(self.cap) if self.state[s] == SLOT_FREE]
         slots = free[:req.nrhs]
         for j, s in enumerate(slots):
             self.state[s] = SLOT_RUNNING
@@ -43,7 +66,7 @@ class FakeExecutor:
 
     def step(self, k):
         time.sleep(self.step_time)
-        for s in range(self.capacity):
+        for s in range(self.cap):
             if self.state[s] == SLOT_RUNNING:
                 self.count[s] += k
                 if self.count[s] >= self.need[s]:
@@ -51,7 +74,7 @@ class FakeExecutor:
 
     def poll(self):
         stats = [dict(iters=self.count[s], status=0, true_resid=0.0, reliable_updates=0, seconds=0.0)
-                 for s in range(self.capacity)]
+                 for s in range(self.cap)]
         return list(self.state), stats
 
     def take(self, req):
@@ -60,6 +83,12 @@ class FakeExecutor:
             assert self.state[s] == SLOT_DONE
             self.state[s] = SLOT_FREE
         return out
+
+    def shrink(self):
+        used = [s for s in range(self.cap) if self.state[s] != SLOT_FREE]
+        old = self.cap
+        self._set_cap(max(used) + 1 if used else 0)
+        return (old - self.cap) * self.slot_bytes
 
 
 def make_requests(n, lattices, seed=0, max_nrhs=3, gap=0.001):
@@ -85,6 +114,8 @@ def test_all_complete_with_their_own_results():
         assert r.latency >= r.finished - r.admitted
     assert ex["a"].max_running <= 3 and ex["b"].max_running <= 4
     assert summ["latency_p99_s"] >= summ["latency_p50_s"] > 0
+    # every slot is given back once the stream has drained
+    assert ex["a"].cap == 0 and ex["b"].cap == 0 and srv.adm.in_use == 0
 
 
 def test_budget_bounds_admission_and_fifo_order():
@@ -110,6 +141,21 @@ def test_free_memory_bounds_admission():
     srv.run(reqs)
     # with 250 free bytes at most 2 RHS (220 bytes) fit at a time
     assert ex["a"].max_running <= 2
+
+
+def test_budget_is_shared_by_lattices_and_counts_held_slots():
+    # 3 slots' worth of budget (plus io) shared by two lattices: the slots the
+    # two sessions hold together never exceed it, and both make progress
+    held = {"now": 0, "max": 0}
+    ex = {"a": FakeExecutor(4, held=held), "b": FakeExecutor(4, held=held)}
+    adm = Admission(3 * 100 + 3 * 10)
+    srv = Server(ex, adm, k_iters=8)
+    reqs = make_requests(16, ["a", "b"], max_nrhs=2, seed=3)
+    summ = srv.run(reqs)
+    assert summ["completed"] == 16
+    assert held["max"] <= 300 and held["now"] == 0
+    assert adm.peak <= 330 and adm.in_use == 0
+    assert ex["a"].max_cap >= 1 and ex["b"].max_cap >= 1
 
 
 def test_continuous_batching_joins_running_batch():
