@@ -1,18 +1,32 @@
 #!/usr/bin/env python3
 """Benchmark of the Wilson-Dirac hot path on one MI355X.
 
-A step is one batched solve of M^dag M x = phi (even-odd, Mhat^dag Mhat) for
-all right-hand sides of the workload to a true FP64 relative residual of
-1e-10: the stencil sweeps, fused CG vector updates, device reductions and
-FP64 reliable updates, i.e. every stage of the path.  Inputs (gauge field,
-sources) are resident in HBM before the timed region starts.
+Workloads (--workload):
 
-Default workload: 32^3 x 64 lattice, one random SU(3) field (eps = 0.5),
-12 Gaussian right-hand sides solved together, kappa = 0.156, FP16 spinors
-with per-site norms, FP32 12-real links, FP32 arithmetic, FP64 reliable
-updates.  Printed: one JSON line with solves/s (value), the FP64 solve rate
-on the same inputs, the dominant kernel's roofline entry (live HIP-event
-timing) and the CPU oracle baseline.
+  c3_32c64_12rhs (default)  A step is one batched solve of M^dag M x = phi
+      (even-odd, Mhat^dag Mhat) for 12 Gaussian right-hand sides on a 32^3 x 64
+      lattice (one random SU(3) field, eps = 0.5, kappa = 0.156) to a true FP64
+      relative residual of 1e-10: the stencil sweeps, fused CG vector updates,
+      device reductions and FP64 reliable updates, i.e. every stage of the
+      path.  FP16 spinors with per-site norms, FP32 12-real links, FP32
+      arithmetic, FP64 reliable updates.  Inputs are resident in HBM before
+      the timed region starts.
+  c2_16c32, c1_4c4  The same on 16^3 x 32 (8 RHS, kappa 0.155) and 4^4.
+  c4_serving  Poisson arrivals of solve requests on four resident lattices
+      (8^4, 12^3 x 24, 16^3 x 32, 24^3 x 48; 1-8 RHS each, kappa uniform in
+      [0.14, 0.157], tol 1e-10) through the continuous-batching server under a
+      device-memory budget: a saturation pass (all requests at once) gives
+      solves/s; passes at 0.5, 0.8 and 1.0 times the saturation request rate
+      give p50/p99 latency.
+  c5_hmc  Two-flavour HMC on 16^3 x 32: Wilson plaquette action beta = 5.6,
+      kappa = 0.156, leapfrog tau = 1 in 50 steps, mixed-precision force
+      solves (tol 1e-8), FP64 Hamiltonian solves (1e-10).  From a cold start,
+      --warmup molecular-dynamics trajectories (no accept/reject) thermalise
+      the field, then --steps HMC trajectories are measured.
+
+Printed: one JSON line with the workload's rate (value), the FP64 rate on the
+same inputs, the dominant stencil kernel's roofline entry (HIP events on the
+context's stream) and the CPU oracle baseline.
 """
 import argparse
 import json
@@ -26,17 +40,25 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+METRIC = "Dslash HBM GB/s + GFLOP/s; M†M solves/s mixed vs FP64 at 1e-10, p99 latency"
+FLOP_SITE = 1320.0     # per output site and RHS of one hopping sweep
 
 WORKLOADS = {
     # name: dims, eps, kappa, nrhs, seed index
     "c3_32c64_12rhs": dict(dims=(32, 32, 32, 64), eps=0.5, kappa=0.156, nrhs=12, cfg=2),
     "c2_16c32": dict(dims=(16, 16, 16, 32), eps=0.5, kappa=0.155, nrhs=8, cfg=1),
     "c1_4c4": dict(dims=(4, 4, 4, 4), eps=0.3, kappa=0.15, nrhs=1, cfg=0),
+    "c4_serving": dict(lattices={"8^4": (8, 8, 8, 8), "12^3x24": (12, 12, 12, 24),
+                                 "16^3x32": (16, 16, 16, 32), "24^3x48": (24, 24, 24, 48)},
+                       eps=0.5, kappa=(0.14, 0.157), nrhs=(1, 8), cfg=3, max_slots=8,
+                       budget_gib=6.0, requests=100, loads=(0.5, 0.8, 1.0)),
+    "c5_hmc": dict(dims=(16, 16, 16, 32), beta=5.6, kappa=0.156, tau=1.0, nsteps=50, cfg=4),
 }
 PRECS = {"f64": 0, "f32": 1, "f16": 2, "f16l16": 2 | 0x10, "f32l16": 1 | 0x10,
          "f16r18": 2 | 0x20, "f32r18": 1 | 0x20}
 DTYPE = {"f64": "f64", "f32": "f32", "f16": "f16+norm/f32", "f16l16": "f16+norm/f32",
          "f32l16": "f32", "f16r18": "f16+norm/f32", "f32r18": "f32"}
+DEFAULT_STEPS = {"c4_serving": (1, 1), "c5_hmc": (20, 30)}
 
 
 def log(msg):
@@ -46,34 +68,39 @@ def log(msg):
 def parse():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=None, help="timed steps (default 3; c5: 20 trajectories)")
+    ap.add_argument("--warmup", type=int, default=None, help="untimed steps (default 1; c5: 30 trajectories)")
     ap.add_argument("--workload", default="c3_32c64_12rhs", choices=sorted(WORKLOADS))
     ap.add_argument("--prec", default="f16", choices=sorted(PRECS))
-    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison solve")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--tuned", type=int, default=1, help="autotune launch shapes before timing")
+    ap.add_argument("--requests", type=int, default=None, help="c4: requests per pass")
     ap.add_argument("--tune-only", action="store_true",
                     help="autotune (filling WD_TUNE_CACHE when set) and exit")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one plain 1 GiB device copy (counter calibration)")
-    return ap.parse_args()
+    a = ap.parse_args()
+    ds, dw = DEFAULT_STEPS.get(a.workload, (3, 1))
+    a.steps = ds if a.steps is None else a.steps
+    a.warmup = dw if a.warmup is None else a.warmup
+    return a
 
 
 def make_inputs(w):
     import lattice_inputs as li
     dims = w["dims"]
     t = time.time()
-    U = li.random_su3_field(dims, w["eps"], seed=li.config_seed(w["cfg"]))
+    U = li.unit_field(dims)
     B = li.gaussian_spinor(li.volume(dims) // 2, seed=li.config_seed(w["cfg"]) + 1000, nrhs=w["nrhs"])
     log(f"[bench] inputs {dims} nrhs {w['nrhs']} generated in {time.time() - t:.1f}s")
     return U, B
 
 
-def cpu_baseline(U, dims, kappa, iters_per_solve, budget_s):
-    """Oracle (plain C, OpenMP) applications of Mhat^dag Mhat on one RHS,
-    scaled to solves/s with the FP64 iteration count of the GPU solve."""
+def oracle_apply_seconds(U, dims, kappa, budget_s, max_n=50):
+    """Seconds per oracle application of Mhat^dag Mhat on one RHS, and the
+    number of applications timed (within budget_s)."""
     from oracle import wdref
     import lattice_inputs as li
     wdref.lib()
@@ -83,29 +110,69 @@ def cpu_baseline(U, dims, kappa, iters_per_solve, budget_s):
     while True:
         wdref.mhatdag_mhat(dims, U, kappa, b)
         n += 1
-        if time.time() - t0 > budget_s or n >= 50:
+        if time.time() - t0 > budget_s or n >= max_n:
             break
-    t_apply = (time.time() - t0) / n
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {
-        "value": 1.0 / (t_apply * iters_per_solve),
-        "unit": "solves/s",
-        "cores": cores,
-        "kind": "oracle",
-        "sample": (f"{n} oracle applications of Mhat^dag Mhat on one {dims} right-hand side "
-                   f"({t_apply:.3f} s each), times {iters_per_solve} CG iterations per solve"),
-    }
+    return (time.time() - t0) / n, n
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
-              "multi-GPU sharding is not part of this build", file=sys.stderr)
-        sys.exit(2)
-    import torch
-    from paper_1207_2223_amd import wd
+def oracle_cores():
+    return int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
 
+
+def kernel_roofline(report, wall_s=None):
+    """Roofline entry of the stencil instance with the largest total time in
+    a wd_timing_report dict {name: (launches, total_ms, bytes, site_rhs)}."""
+    name, (n, ms, by, units) = max(report.items(), key=lambda kv: kv[1][1])
+    avg_ms = ms / n
+    achieved = (by / n) / (avg_ms * 1e-3) / 1e9
+    all_ms = sum(v[1] for v in report.values())
+    all_by = sum(v[2] for v in report.values())
+    dom = {"name": name, "launches": n, "avg_us": avg_ms * 1e3, "bytes_per_launch": by / n,
+           "site_rhs_per_launch": units / n, "GFLOP_s": FLOP_SITE * (units / n) / (avg_ms * 1e-3) / 1e9}
+    roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": None}
+    sten = {"GB_s_all_launches": all_by / (all_ms * 1e-3) / 1e9}
+    if wall_s:
+        sten["share_of_step"] = all_ms * 1e-3 / wall_s
+    return dom, roof, sten
+
+
+def instrumented(wd, torch, ctx, fn):
+    """Run fn() with per-launch HIP-event timing on ctx; returns the timing
+    report and the wall time of the run."""
+    wd.wd_timing_enable(ctx, True)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    fn()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t
+    report = wd.wd_timing_report(ctx)
+    wd.wd_timing_read(ctx)
+    wd.wd_timing_enable(ctx, False)
+    return report, wall
+
+
+def merge_reports(reports):
+    out = {}
+    for rep in reports:
+        for k, v in rep.items():
+            o = out.get(k, (0, 0.0, 0.0, 0.0))
+            out[k] = tuple(a + b for a, b in zip(o, v))
+    return out
+
+
+def base_record(args, value, unit, ms_per_step, dtype, config, higher=True):
+    return {"metric": METRIC, "value": value, "unit": unit, "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": higher,
+            "scaling": "weak", "vs_baseline": None, "dtype": dtype,
+            "data": "synthetic (seeded random SU(3) fields and Gaussian sources)", "config": config}
+
+
+# ---------------------------------------------------------------------------
+# c1 / c2 / c3: batched solves on one lattice
+# ---------------------------------------------------------------------------
+
+def bench_solve(args, wd, torch):
     w = WORKLOADS[args.workload]
     dims, kappa, nrhs = w["dims"], w["kappa"], w["nrhs"]
     U, B = make_inputs(w)
@@ -125,12 +192,11 @@ def main():
         log(f"[bench] autotune {time.time() - t:.1f}s")
     if args.tune_only:
         lat.close()
-        return
+        return None
     torch.cuda.synchronize()
 
     def solve(p):
-        st, stats = lat.cg_solve(Xd, Bd, [kappa] * nrhs, p)
-        return st, stats
+        return lat.cg_solve(Xd, Bd, [kappa] * nrhs, p)
 
     if args.copy_probe:
         a = torch.empty(1 << 27, dtype=torch.float64, device=dev)
@@ -144,7 +210,6 @@ def main():
     for k in range(args.warmup):
         st, stats = solve(params)
         log(f"[bench] warmup {k}: status {st} iters {[s['iters'] for s in stats][:4]}...")
-    wd.wd_timing_enable(lat.ctx, True)
     step_ms = []
     iters, resid, ok = [], [], True
     torch.cuda.synchronize()
@@ -160,19 +225,12 @@ def main():
             f"max true resid {resid[-1]:.2e}")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    report = wd.wd_timing_report(lat.ctx)
-    wd.wd_timing_read(lat.ctx)
-    wd.wd_timing_enable(lat.ctx, False)
     value = args.steps * nrhs / elapsed
-
-    # dominant stencil kernel by total time
-    name, (n, ms, by, units) = max(report.items(), key=lambda kv: kv[1][1])
-    avg_ms = ms / n
-    achieved = (by / n) / (avg_ms * 1e-3) / 1e9
-    flops_site = 1320.0
-    log(f"[bench] kernels: " + "; ".join(f"{k}: {v[0]} x {v[1] / v[0] * 1e3:.1f} us" for k, v in report.items()))
-    all_ms = sum(v[1] for v in report.values())
-    all_by = sum(v[2] for v in report.values())
+    # one more step with every stencil launch bracketed by HIP events (kept
+    # out of the timed steps: the events add launch overhead)
+    report, t_inst = instrumented(wd, torch, lat.ctx, lambda: solve(params))
+    log("[bench] kernels: " + "; ".join(f"{k}: {v[0]} x {v[1] / v[0] * 1e3:.1f} us" for k, v in report.items()))
+    dom, roof, sten = kernel_roofline(report, t_inst)
 
     fp64 = None
     if not args.no_fp64 and args.prec != "f64":
@@ -189,42 +247,303 @@ def main():
 
     cpu = None
     if not args.no_cpu:
-        cpu = cpu_baseline(U, dims, kappa, iters64, args.cpu_seconds)
+        t_apply, n = oracle_apply_seconds(U, dims, kappa, args.cpu_seconds)
+        cpu = {"value": 1.0 / (t_apply * iters64), "unit": "solves/s", "cores": oracle_cores(),
+               "kind": "oracle",
+               "sample": (f"{n} oracle applications of Mhat^dag Mhat on one {dims} right-hand side "
+                          f"({t_apply:.3f} s each), times {iters64} CG iterations per solve")}
         log(f"[bench] cpu oracle: {cpu['value']:.4g} solves/s ({cpu['sample']})")
+    lat.close()
 
-    out = {
-        "metric": "Dslash HBM GB/s + GFLOP/s; M†M solves/s mixed vs FP64 at 1e-10, p99 latency",
-        "value": value,
-        "unit": "solves/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": elapsed / args.steps * 1e3,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": DTYPE[args.prec],
-        "data": "synthetic (seeded random SU(3) field and Gaussian sources)",
-        "config": {"workload": f"{args.workload}: {'x'.join(map(str, dims))} lattice, {nrhs} RHS, "
-                               f"kappa {kappa}, eps {w['eps']}, even-odd CG to 1e-10",
-                   "prec_sloppy": args.prec, "nrhs": nrhs, "lattice": list(dims)},
+    out = base_record(args, value, "solves/s", elapsed / args.steps * 1e3, DTYPE[args.prec],
+                      {"workload": f"{args.workload}: {'x'.join(map(str, dims))} lattice, {nrhs} RHS, "
+                                   f"kappa {kappa}, eps {w['eps']}, even-odd CG to 1e-10",
+                       "prec_sloppy": args.prec, "nrhs": nrhs, "lattice": list(dims)})
+    out.update({
         "converged": bool(ok),
         "iters": iters[-1],
         "max_true_resid": max(resid),
         "latency_ms": {"p50": float(np.percentile(step_ms, 50)), "p99": float(np.percentile(step_ms, 99))},
-        "stencil": {"GB_s_all_launches": all_by / (all_ms * 1e-3) / 1e9,
-                    "share_of_step": all_ms / (elapsed * 1e3)},
-        "dominant_kernel": {"name": name, "launches": n, "avg_us": avg_ms * 1e3,
-                            "bytes_per_launch": by / n, "site_rhs_per_launch": units / n,
-                            "GFLOP_s": flops_site * (units / n) / (avg_ms * 1e-3) / 1e9},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+        "stencil": sten,
+        "dominant_kernel": dom,
+        "roofline": roof,
         "fp64": fp64,
         "mixed_vs_fp64": (value / fp64["solves_per_s"]) if fp64 else None,
         "cpu_baseline": cpu,
-    }
+    })
+    return out
+
+
+# ---------------------------------------------------------------------------
+# c4: serving stream
+# ---------------------------------------------------------------------------
+
+def bench_serving(args, wd, torch):
+    import lattice_inputs as li
+    from paper_1207_2223_amd.serve import Admission, GpuExecutor, Request, Server, poisson_arrivals
+    w = WORKLOADS["c4_serving"]
+    nreq = args.requests or w["requests"]
+    dev = torch.device("cuda:0")
+    names = list(w["lattices"])
+    fields, pools = {}, {}
+    t = time.time()
+    for i, name in enumerate(names):
+        dims = w["lattices"][name]
+        fields[name] = li.random_su3_field(dims, w["eps"], seed=li.config_seed(w["cfg"]) + i)
+        # a pool of max-nrhs device-resident sources per lattice; a request of
+        # n RHS takes n of them starting at a seeded offset
+        pools[name] = torch.from_numpy(li.gaussian_spinor(li.volume(dims) // 2, seed=li.config_seed(w["cfg"]) + 100 + i,
+                                                          nrhs=2 * w["nrhs"][1])).to(dev)
+    torch.cuda.synchronize()
+    log(f"[bench] serving inputs generated in {time.time() - t:.1f}s")
+    budget = int(w["budget_gib"] * (1 << 30))
+
+    def requests(n, seed):
+        rng = np.random.default_rng(seed)
+        out = []
+        for i in range(n):
+            name = names[int(rng.integers(len(names)))]
+            nrhs = int(rng.integers(w["nrhs"][0], w["nrhs"][1] + 1))
+            off = int(rng.integers(0, w["nrhs"][1] + 1))
+            kap = list(rng.uniform(w["kappa"][0], w["kappa"][1], nrhs))
+            out.append(Request(rid=i, lattice=name, phi=pools[name][off:off + nrhs], kappa=kap))
+        return out
+
+    def executors(prec):
+        p = wd.solver_params(prec=prec, tol=1e-10, maxiter=20000)
+        return {n: GpuExecutor(w["lattices"][n], fields[n], p, max_slots=w["max_slots"], keep_result=False)
+                for n in names}
+
+    def one_pass(ex, reqs, arrivals=None, timing=False):
+        for r, a in zip(reqs, arrivals if arrivals is not None else [0.0] * len(reqs)):
+            r.arrival, r.admitted, r.finished, r.stats = float(a), None, None, []
+        free = lambda: torch.cuda.mem_get_info()[0]
+        adm = Admission(budget, free_fn=free, reserve_bytes=1 << 30)
+        if timing:
+            for e in ex.values():
+                wd.wd_timing_enable(e.lat.ctx, True)
+        srv = Server(ex, adm, k_iters=8)
+        torch.cuda.synchronize()
+        summ = srv.run(reqs, realtime=arrivals is not None)
+        torch.cuda.synchronize()
+        reps = []
+        if timing:
+            for e in ex.values():
+                reps.append(wd.wd_timing_report(e.lat.ctx))
+                wd.wd_timing_read(e.lat.ctx)
+                wd.wd_timing_enable(e.lat.ctx, False)
+        st = [s for r in reqs for s in r.stats]
+        summ["all_converged"] = all(s["status"] == wd.WD_OK for s in st)
+        summ["max_true_resid"] = max(s["true_resid"] for s in st)
+        summ["fp64_escalated_rhs"] = sum(1 for s in st if 0 < s["iters_fp64"] < s["iters"])
+        return summ, merge_reports(reps)
+
+    prec = PRECS[args.prec]
+    ex = executors(prec)
+    for k in range(args.warmup):
+        summ, _ = one_pass(ex, requests(8, seed=900 + k))
+        log(f"[bench] serving warmup {k}: {summ['completed']} requests in {summ['makespan_s']:.2f}s")
+    reqs = requests(nreq, seed=1)
+    sat = []
+    for k in range(args.steps):
+        summ, _ = one_pass(ex, reqs)
+        sat.append(summ)
+        log(f"[bench] saturation pass {k}: {summ['rhs_solved']} RHS in {summ['makespan_s']:.2f}s = "
+            f"{summ['solves_per_s']:.1f} solves/s, p50 {summ['latency_p50_s']:.3f}s p99 {summ['latency_p99_s']:.3f}s, "
+            f"peak {summ['peak_bytes'] / 2**30:.2f} GiB, escalated {summ['fp64_escalated_rhs']}")
+    value = float(np.median([s["solves_per_s"] for s in sat]))
+    req_rate = float(np.median([s["completed"] / s["makespan_s"] for s in sat]))
+    sweep = []
+    for load in w["loads"]:
+        arr = poisson_arrivals(nreq, load * req_rate, np.random.default_rng(int(load * 100)))
+        summ, _ = one_pass(ex, reqs, arrivals=arr)
+        row = {"load": load, "arrival_rate_req_s": load * req_rate, "solves_per_s": summ["solves_per_s"],
+               "latency_p50_ms": summ["latency_p50_s"] * 1e3, "latency_p99_ms": summ["latency_p99_s"] * 1e3,
+               "latency_mean_ms": summ["latency_mean_s"] * 1e3, "peak_bytes": summ["peak_bytes"],
+               "max_batch": summ["max_batch"], "all_converged": summ["all_converged"]}
+        sweep.append(row)
+        log(f"[bench] load {load}: {row['arrival_rate_req_s']:.2f} req/s -> {row['solves_per_s']:.1f} solves/s, "
+            f"p50 {row['latency_p50_ms']:.0f} ms p99 {row['latency_p99_ms']:.0f} ms")
+    # the saturation pass once more with per-launch HIP events on every
+    # lattice's stream, for the kernel figures
+    _, report = one_pass(ex, reqs, timing=True)
+    for e in ex.values():
+        e.close()
+
+    fp64 = None
+    if not args.no_fp64 and args.prec != "f64":
+        ex64 = executors(0)
+        summ, _ = one_pass(ex64, reqs)
+        for e in ex64.values():
+            e.close()
+        fp64 = {"solves_per_s": summ["solves_per_s"], "latency_p50_ms": summ["latency_p50_s"] * 1e3,
+                "latency_p99_ms": summ["latency_p99_s"] * 1e3, "all_converged": summ["all_converged"]}
+        log(f"[bench] fp64 saturation pass: {summ['solves_per_s']:.1f} solves/s")
+
+    cpu = None
+    if not args.no_cpu:
+        # oracle seconds per application on each lattice, times the CG
+        # iterations every RHS of the saturation pass took
+        per = {}
+        budget_each = args.cpu_seconds / len(names)
+        for n in names:
+            per[n], cnt = oracle_apply_seconds(fields[n], w["lattices"][n], 0.15, budget_each, max_n=20)
+        t_est = sum(per[r.lattice] * s["iters"] for r in reqs for s in r.stats)
+        nrhs_all = sum(r.nrhs for r in reqs)
+        cpu = {"value": nrhs_all / t_est, "unit": "solves/s", "cores": oracle_cores(), "kind": "oracle",
+               "sample": ("oracle Mhat^dag Mhat applications timed on each lattice ("
+                          + ", ".join(f"{n} {per[n] * 1e3:.1f} ms" for n in names)
+                          + f"), times the CG iterations of each of the {nrhs_all} RHS of the saturation pass")}
+        log(f"[bench] cpu oracle: {cpu['value']:.4g} solves/s")
+
+    dom, roof, sten = kernel_roofline(report)
+    p08 = next((r for r in sweep if abs(r["load"] - 0.8) < 1e-9), sweep[-1])
+    out = base_record(args, value, "solves/s", float(np.median([s["makespan_s"] for s in sat])) * 1e3,
+                      DTYPE[args.prec],
+                      {"workload": (f"c4_serving: {nreq} requests on {', '.join(names)} lattices (eps {w['eps']}), "
+                                    f"{w['nrhs'][0]}-{w['nrhs'][1]} RHS each, kappa U[{w['kappa'][0]}, "
+                                    f"{w['kappa'][1]}], tol 1e-10, budget {w['budget_gib']} GiB"),
+                       "prec_sloppy": args.prec, "requests": nreq, "max_slots": w["max_slots"]})
+    out.update({
+        "converged": all(s["all_converged"] for s in sat),
+        "max_true_resid": max(s["max_true_resid"] for s in sat),
+        "latency_ms": {"p50": p08["latency_p50_ms"], "p99": p08["latency_p99_ms"], "at_load": p08["load"]},
+        "saturation": {"solves_per_s": value, "requests_per_s": req_rate,
+                       "latency_p50_ms": sat[0]["latency_p50_s"] * 1e3,
+                       "latency_p99_ms": sat[0]["latency_p99_s"] * 1e3, "peak_bytes": sat[0]["peak_bytes"],
+                       "fp64_escalated_rhs": sat[0]["fp64_escalated_rhs"], "steps": sat[0]["steps"]},
+        "load_sweep": sweep,
+        "stencil": sten,
+        "dominant_kernel": dom,
+        "roofline": roof,
+        "fp64": fp64,
+        "mixed_vs_fp64": (value / fp64["solves_per_s"]) if fp64 else None,
+        "cpu_baseline": cpu,
+    })
+    return out
+
+
+# ---------------------------------------------------------------------------
+# c5: HMC
+# ---------------------------------------------------------------------------
+
+def bench_hmc(args, wd, torch):
+    import lattice_inputs as li
+    w = WORKLOADS["c5_hmc"]
+    dims = w["dims"]
+    U = li.unit_field(dims)
+    dev = torch.device("cuda:0")
+    Ud = torch.from_numpy(U).to(dev)
+    lat = wd.Lattice(dims)
+    lat.gauge_load(Ud, recon=12)
+    force = wd.solver_params(prec=PRECS[args.prec], tol=1e-8, maxiter=20000, tuned=args.tuned)
+    hsol = wd.solver_params(prec=0, tol=1e-10, maxiter=20000, tuned=args.tuned)
+    if args.tuned:
+        for code in {PRECS[args.prec], 0}:
+            wd.wd_tune(lat.ctx, 1, code)
+
+    def traj(i, fparams, metropolis=True):
+        h = wd.hmc_params(beta=w["beta"], kappa=w["kappa"], tau=w["tau"], nsteps=w["nsteps"],
+                          seed=li.config_seed(w["cfg"]), traj=i, force=fparams, h=hsol,
+                          metropolis=metropolis)
+        return wd.hmc_trajectory(lat.ctx, Ud, h)
+
+    # thermalisation: molecular-dynamics trajectories (every proposal taken)
+    # from the cold start, then the measured HMC trajectories
+    for i in range(args.warmup):
+        r = traj(i, force, metropolis=False)
+        log(f"[bench] thermalisation {i}: dH {r['dH']:+.4f} acc {r['accepted']} plaq {r['plaquette']:.5f} "
+            f"cg {r['cg_iters']} {r['seconds']:.2f}s status {r['status']}")
+    rows = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        r = traj(args.warmup + i, force)
+        rows.append(r)
+        log(f"[bench] trajectory {i}: dH {r['dH']:+.4f} acc {r['accepted']} plaq {r['plaquette']:.5f} "
+            f"cg {r['cg_iters']} {r['seconds']:.2f}s status {r['status']}")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    value = 3600.0 * args.steps / elapsed
+    # one more trajectory with per-launch HIP events, for the kernel figures
+    U_keep = Ud.clone()
+    report, t_inst = instrumented(wd, torch, lat.ctx, lambda: traj(args.warmup + args.steps + 1, force))
+    Ud.copy_(U_keep)
+    lat.gauge_load(Ud, recon=12)
+    dom, roof, sten = kernel_roofline(report, t_inst)
+    emdh = np.array([r["exp_mdH"] for r in rows])
+    acc = float(np.mean([r["accepted"] for r in rows]))
+    cg_per_step = float(np.mean([r["cg_iters"] for r in rows])) / w["nsteps"]
+
+    fp64 = None
+    if not args.no_fp64 and args.prec != "f64":
+        # one more trajectory, with FP64 force solves
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        r64 = traj(args.warmup + args.steps, wd.solver_params(prec=0, tol=1e-8, maxiter=20000, tuned=args.tuned))
+        torch.cuda.synchronize()
+        t64 = time.perf_counter() - ts
+        fp64 = {"traj_per_hour": 3600.0 / t64, "seconds": t64, "dH": r64["dH"], "cg_iters": r64["cg_iters"]}
+        log(f"[bench] fp64-force trajectory: {t64:.2f}s dH {r64['dH']:+.4f}")
+
+    cpu = None
+    if not args.no_cpu:
+        from oracle import wdref
+        t_apply, n = oracle_apply_seconds(U, dims, w["kappa"], args.cpu_seconds * 0.7)
+        t = time.time()
+        wdref.gauge_force(dims, U, w["beta"])
+        t_gf = time.time() - t
+        h_iters = 2 * cg_per_step  # two H solves at about a force solve's count each, FP64 (labelled)
+        t_traj = w["nsteps"] * (cg_per_step * t_apply + t_gf) + h_iters * t_apply
+        cpu = {"value": 3600.0 / t_traj, "unit": "traj/h", "cores": oracle_cores(), "kind": "oracle",
+               "sample": (f"extrapolated: {n} oracle Mhat^dag Mhat applications on {dims} ({t_apply:.3f} s each) "
+                          f"times the GPU's {cg_per_step:.0f} CG iterations per MD step, plus one oracle gauge force "
+                          f"({t_gf:.3f} s), times {w['nsteps']} steps, plus two Hamiltonian solves")}
+        log(f"[bench] cpu oracle: {cpu['value']:.4g} traj/h")
     lat.close()
-    print(json.dumps(out), flush=True)
+
+    out = base_record(args, value, "traj/h", elapsed / args.steps * 1e3, DTYPE[args.prec],
+                      {"workload": (f"c5_hmc: {'x'.join(map(str, dims))} lattice, beta {w['beta']}, kappa {w['kappa']}, "
+                                    f"leapfrog tau {w['tau']} in {w['nsteps']} steps, force solves {args.prec} tol 1e-8, "
+                                    f"H solves FP64 1e-10, cold start, {args.warmup} MD thermalisation trajectories"),
+                       "prec_sloppy": args.prec, "lattice": list(dims)})
+    out.update({
+        "acceptance": acc,
+        "exp_minus_dH": {"mean": float(emdh.mean()),
+                         "stderr": float(emdh.std(ddof=1) / np.sqrt(len(emdh))) if len(emdh) > 1 else None},
+        "dH": [r["dH"] for r in rows],
+        "plaquette": [r["plaquette"] for r in rows],
+        "cg_iters_per_md_step": cg_per_step,
+        "all_ok": all(r["status"] == wd.WD_OK for r in rows),
+        "latency_ms": {"p50": float(np.percentile([r["seconds"] for r in rows], 50)) * 1e3,
+                       "p99": float(np.percentile([r["seconds"] for r in rows], 99)) * 1e3},
+        "stencil": sten,
+        "dominant_kernel": dom,
+        "roofline": roof,
+        "fp64": fp64,
+        "mixed_vs_fp64": (value / fp64["traj_per_hour"]) if fp64 else None,
+        "cpu_baseline": cpu,
+    })
+    return out
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
+              "multi-GPU sharding is not part of this build", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_1207_2223_amd import wd
+    wd.lib()
+    if args.workload == "c4_serving":
+        out = bench_serving(args, wd, torch)
+    elif args.workload == "c5_hmc":
+        out = bench_hmc(args, wd, torch)
+    else:
+        out = bench_solve(args, wd, torch)
+    if out is not None:
+        print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":

@@ -219,6 +219,9 @@ typedef struct {
     uint64_t seed;                 /* Philox key                                      */
     wd_solver_params force_solver; /* solves inside the force (eo must be 1)          */
     wd_solver_params h_solver;     /* the final-Hamiltonian solve (eo must be 1)      */
+    int metropolis;                /* 1: accept iff u < exp(-dH); 0: accept every    */
+                                   /* proposal (molecular-dynamics trajectories for  */
+                                   /* thermalisation; dH is still computed)          */
 } wd_hmc_params;
 
 typedef struct {
@@ -234,7 +237,8 @@ typedef struct {
 } wd_hmc_result;
 
 /* Defaults: beta 5.6, kappa 0.156, tau 1, 50 steps, seed 1, traj 0; force
- * solves FP16-sloppy to 1e-8, final solve FP64 to 1e-10.  h: host pointer. */
+ * solves FP16-sloppy to 1e-8, final solve FP64 to 1e-10; Metropolis on.
+ * h: host pointer. */
 void wd_hmc_defaults(wd_hmc_params *h);
 
 /* The refresh draws of a trajectory: momenta P [V][4][3][3] (Hermitian
@@ -256,7 +260,8 @@ wd_status wd_md_force(wd_ctx *c, double *F, const double *U, const double *phi, 
 /* One HMC trajectory (Sec. 3 steps 1-3): draw p and chi (wd_hmc_draw),
  * phi_e = Mhat^dag chi_e, H_old = 1/2 sum tr p^2 + S_g + chi^dag chi,
  * leapfrog P-Q-P with U <- exp(i dtau p) U and p <- p - dtau F, H_new with a
- * final solve, Metropolis with u from Philox (0, traj, 'M', 0).  U
+ * final solve, Metropolis with u from Philox (0, traj, 'M', 0) (or accept
+ * without the test when h->metropolis is 0).  U
  * ([V][4][3][3], device) is replaced by the proposal when accepted and left
  * unchanged otherwise; the context's packed links follow U either way.
  * h, r: host pointers.  A failed solve rejects and returns its status. */

@@ -581,6 +581,7 @@ void wd_hmc_defaults(wd_hmc_params *h)
     h->force_solver.prec_sloppy = WD_F16;
     wd_solver_defaults(&h->h_solver);
     h->h_solver.tol = 1e-10;
+    h->metropolis = 1;
 }
 
 wd_status wd_hmc_draw(wd_ctx *c, double *P, double *chi, uint64_t seed, uint32_t traj)
@@ -681,7 +682,7 @@ wd_status hmc_trajectory(wd_ctx *c, double *U, const wd_hmc_params *h, wd_hmc_re
     uint32_t rr[4];
     philox4x32_10(ctr, (uint32_t)h->seed, (uint32_t)(h->seed >> 32), rr);
     const double u = unif53(rr[0], rr[1]);
-    const bool acc = (st == WD_OK) && std::isfinite(dH) && (u < std::exp(-dH));
+    const bool acc = (st == WD_OK) && std::isfinite(dH) && (!h->metropolis || u < std::exp(-dH));
     if (acc) {
         HIPCHK(hipMemcpyAsync(U, w.U, w.nl * sizeof(double), hipMemcpyDeviceToDevice, s));
     } else {

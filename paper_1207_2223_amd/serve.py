@@ -47,7 +47,7 @@ class Request:
 
     @property
     def nrhs(self):
-        return self.phi.shape[0]
+        return int(self.phi.shape[0])
 
     @property
     def latency(self):
@@ -120,6 +120,8 @@ class Server:
             req = q[0]
             if req.nrhs > ex.max_slots:
                 raise ValueError(f"request {req.rid} needs {req.nrhs} slots, lattice {name} has {ex.max_slots}")
+            if req.nrhs * ex.slot_bytes + ex.io_bytes(req.nrhs) > self.adm.budget:
+                raise ValueError(f"request {req.rid} needs more than the whole budget of {self.adm.budget} bytes")
             if used + req.nrhs > ex.max_slots:
                 break
             grow = ex.grow_bytes(req.nrhs)
@@ -225,7 +227,7 @@ class GpuExecutor:
     session that grows to the slots admitted requests need (up to max_slots)
     and shrinks when the scheduler says so; all work on its own stream."""
 
-    def __init__(self, dims, U, params, max_slots, device=0):
+    def __init__(self, dims, U, params, max_slots, device=0, keep_result=True):
         import torch
 
         from . import wd
@@ -249,6 +251,7 @@ class GpuExecutor:
         self.slot_bytes = wd.wd_session_bytes(self.dims, 1, params)
         self.gauge_bytes = wd.wd_bytes_required(self.dims, 0, params)
         self.bufs = {}
+        self.keep_result = keep_result
 
     def io_bytes(self, nrhs):
         return 2 * nrhs * self.Vh * 192
@@ -276,7 +279,10 @@ class GpuExecutor:
         torch = self.torch
         self._resize(self._needed_cap(req.nrhs))
         with torch.cuda.stream(self.stream):
-            phi = torch.from_numpy(np.ascontiguousarray(req.phi)).to(self.dev, non_blocking=False)
+            if isinstance(req.phi, torch.Tensor):  # a source already on the device
+                phi = req.phi.to(self.dev).clone()
+            else:
+                phi = torch.from_numpy(np.ascontiguousarray(req.phi)).to(self.dev, non_blocking=False)
             x = torch.empty_like(phi)
         self.stream.synchronize()
         slots = self.wd.wd_session_add(self.sess, phi, req.kappa)
@@ -297,7 +303,9 @@ class GpuExecutor:
             self.wd.wd_session_take(self.sess, s, x[j])
             self.in_use.discard(s)
         self.stream.synchronize()
-        return x.cpu().numpy()
+        # keep_result=False drops the solution after it has been unpacked (a
+        # throughput measurement that does not collect results)
+        return x.cpu().numpy() if self.keep_result else None
 
     def shrink(self):
         """Free the slots above the highest one in use; returns the bytes."""

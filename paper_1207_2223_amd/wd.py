@@ -44,7 +44,8 @@ class wd_solver_stats(C.Structure):
 class wd_hmc_params(C.Structure):
     _fields_ = [("beta", C.c_double), ("kappa", C.c_double), ("tau", C.c_double),
                 ("nsteps", C.c_int), ("traj", C.c_uint32), ("seed", C.c_uint64),
-                ("force_solver", wd_solver_params), ("h_solver", wd_solver_params)]
+                ("force_solver", wd_solver_params), ("h_solver", wd_solver_params),
+                ("metropolis", C.c_int)]
 
 
 class wd_hmc_result(C.Structure):
@@ -376,10 +377,12 @@ def hmc_trajectory(ctx, U, params, check=True):
     return {k: getattr(r, k) for k, _ in wd_hmc_result._fields_}
 
 
-def hmc_params(beta=5.6, kappa=0.156, tau=1.0, nsteps=50, seed=1, traj=0, force=None, h=None):
+def hmc_params(beta=5.6, kappa=0.156, tau=1.0, nsteps=50, seed=1, traj=0, force=None, h=None,
+               metropolis=True):
     p = wd_hmc_defaults()
     p.beta, p.kappa, p.tau, p.nsteps, p.seed, p.traj = (float(beta), float(kappa), float(tau),
                                                         int(nsteps), int(seed), int(traj))
+    p.metropolis = 1 if metropolis else 0
     if force is not None:
         p.force_solver = force
     if h is not None:

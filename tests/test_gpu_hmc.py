@@ -113,3 +113,30 @@ def test_reject_leaves_field_and_context_unchanged(wd):
     assert torch.equal(out, out2)
     lat.close()
     lat2.close()
+
+
+def test_md_trajectory_without_metropolis_takes_the_proposal(wd, oracle):
+    """metropolis = 0 accepts the leapfrog proposal whatever dH is: with
+    three steps for tau = 1 the oracle's dH is about 175 (a certain
+    rejection under the test), and the field returned is the oracle's leapfrog
+    result from the same Philox draws."""
+    dims = (4, 4, 4, 4)
+    V = li.volume(dims)
+    U0 = li.random_su3_field(dims, 0.5, seed=70)
+    beta, kappa, tau, n, seed, traj = 5.6, 0.12, 1.0, 3, 71, 0
+    tight = wd.solver_params(tol=1e-13)
+    lat = wd.Lattice(dims)
+    Ud = dev(U0)
+    hp = wd.hmc_params(beta, kappa, tau, n, seed=seed, traj=traj, force=tight, h=tight, metropolis=False)
+    r = wd.hmc_trajectory(lat.ctx, Ud, hp)
+    assert r["status"] == wd.WD_OK and r["accepted"] == 1
+    assert r["dH"] > 100
+    P = oracle.draw_momenta(dims, seed, traj)
+    chi = oracle.draw_chi(V // 2, seed, traj)
+    phi = oracle.mhat(dims, U0, kappa, chi, dagger=True)
+    Uo, _, _ = oracle.leapfrog(dims, U0, P, beta, kappa, phi, tau, n, eo=True, tol=1e-13)
+    err = np.abs(host(Ud) - Uo).max()
+    note(f"MD trajectory dH {r['dH']:.3f}, accepted {r['accepted']}, |U - U_oracle| {err:.2e}")
+    assert err <= 1e-9
+    assert abs(r["plaquette"] - oracle.plaquette(dims, Uo)) <= 1e-11
+    lat.close()
