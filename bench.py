@@ -92,7 +92,7 @@ def make_inputs(w):
     import lattice_inputs as li
     dims = w["dims"]
     t = time.time()
-    U = li.unit_field(dims)
+    U = li.random_su3_field(dims, w["eps"], seed=li.config_seed(w["cfg"]))
     B = li.gaussian_spinor(li.volume(dims) // 2, seed=li.config_seed(w["cfg"]) + 1000, nrhs=w["nrhs"])
     log(f"[bench] inputs {dims} nrhs {w['nrhs']} generated in {time.time() - t:.1f}s")
     return U, B

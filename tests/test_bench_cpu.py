@@ -1,0 +1,39 @@
+"""Host-side pieces of bench.py: the workload inputs follow the stated
+recipe (a random SU(3) field, not the free field), the roofline arithmetic,
+and the single-GPU guard."""
+import subprocess
+import sys
+import os
+
+import numpy as np
+
+import lattice_inputs as li
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_solve_workload_inputs_follow_the_recipe():
+    import bench
+    w = bench.WORKLOADS["c1_4c4"]
+    U, B = bench.make_inputs(w)
+    assert np.array_equal(U, li.random_su3_field(w["dims"], w["eps"], seed=li.config_seed(w["cfg"])))
+    assert not np.allclose(U, li.unit_field(w["dims"]))
+    assert B.shape == (w["nrhs"], li.volume(w["dims"]) // 2, 4, 3)
+
+
+def test_kernel_roofline_arithmetic():
+    import bench
+    rep = {"a": (10, 20.0, 8e9, 1e7), "b": (10, 5.0, 1e9, 1e7)}
+    dom, roof, sten = bench.kernel_roofline(rep, wall_s=0.05)
+    assert dom["name"] == "a" and abs(dom["avg_us"] - 2000.0) < 1e-9
+    assert abs(roof["achieved"] - 8e8 / 2e-3 / 1e9) < 1e-9
+    assert abs(roof["frac"] - roof["achieved"] / 8000.0) < 1e-12
+    assert abs(sten["share_of_step"] - 0.5) < 1e-12
+    merged = bench.merge_reports([rep, {"a": (1, 1.0, 1.0, 1.0)}])
+    assert merged["a"] == (11, 21.0, 8e9 + 1.0, 1e7 + 1.0)
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=60)
+    assert r.returncode == 2 and "one GPU" in r.stderr
