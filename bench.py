@@ -65,6 +65,41 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def stencil_source_hash():
+    """sha256 over the stencil kernel sources (headers and instantiations):
+    counter figures taken on other sources are not reported."""
+    import glob
+    import hashlib
+    csrc = os.path.join(ROOT, "paper_1207_2223_amd", "csrc")
+    files = sorted(glob.glob(os.path.join(csrc, "dslash*.hip")) +
+                   [os.path.join(csrc, "dslash_impl.h"), os.path.join(csrc, "wd_device.h")])
+    h = hashlib.sha256()
+    for f in files:
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def counter_traffic(workload, prec, kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summaries
+    (profiles/*.md lines 'traffic-record: workload=.. prec=.. hash=..
+    bytes_per_launch=.. kernel=..'), or None when no record matches the
+    workload, precision, kernel and current stencil sources."""
+    import glob
+    h = stencil_source_hash()
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
+        with open(path) as fh:
+            for line in fh:
+                if not line.startswith("traffic-record:"):
+                    continue
+                rec = dict(kv.split("=", 1) for kv in line[len("traffic-record:"):].strip().split(" ; "))
+                if (rec.get("workload") == workload and rec.get("prec") == prec and rec.get("hash") == h
+                        and rec.get("kernel") == kernel):
+                    return float(rec["bytes_per_launch"])
+    return None
+
+
 def parse():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -231,6 +266,7 @@ def bench_solve(args, wd, torch):
     report, t_inst = instrumented(wd, torch, lat.ctx, lambda: solve(params))
     log("[bench] kernels: " + "; ".join(f"{k}: {v[0]} x {v[1] / v[0] * 1e3:.1f} us" for k, v in report.items()))
     dom, roof, sten = kernel_roofline(report, t_inst)
+    roof["traffic"] = counter_traffic(args.workload, args.prec, dom["name"])
 
     fp64 = None
     if not args.no_fp64 and args.prec != "f64":
