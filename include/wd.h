@@ -83,6 +83,9 @@ typedef struct {
     double delta;     /* reliable update when |r| < delta * max|r| since the last  */
     int poll;         /* iterations between host checks of the residual norms       */
     int tuned;        /* 1: use autotuned launch shapes (wd_tune), 0: defaults      */
+    int graphs;       /* 1: run the poll iterations of a step as one captured HIP   */
+                      /* graph, replayed while the active set is unchanged; 0:    */
+                      /* launch each kernel (same results bit for bit)            */
 } wd_solver_params;
 
 /* Per right-hand-side solver statistics. */
@@ -98,7 +101,7 @@ typedef struct {
 } wd_solver_stats;
 
 /* Fill p with the defaults: tol 1e-10, maxiter 20000, FP64, eo 1, delta 0.1,
- * poll 8, tuned 0.  p: host pointer. */
+ * poll 8, tuned 0, graphs 1.  p: host pointer. */
 void wd_solver_defaults(wd_solver_params *p);
 
 /* Create a context for one lattice on HIP device `device`, issuing work on

@@ -155,11 +155,15 @@ wd_status run_sweep(wd_ctx *c, const Sweep &sw, const TuneCfg *cfg)
     const int ntiles = (int)((c->Vh + spb - 1) / spb);
     a.tpp = 1;
     a.nzl = 1;
-    if (t.remap == 2) {
-        if (!slab_order_ok(c->g, spb))
-            return set_error(WD_ERR_ARG, "z-slab tile order needs Lz %% 8 == 0 and whole tiles per plane");
+    a.nys = 1;
+    if (t.remap > 4 || t.remap < 0) return set_error(WD_ERR_ARG, "tile order %d unknown", t.remap);
+    if (t.remap >= 2) {
+        if (!slab_order_ok(c->g, spb, t.remap))
+            return set_error(WD_ERR_ARG, "z-slab tile order %d needs Lz %% 8 == 0 and whole tiles per plane "
+                             "and stripe", t.remap);
         a.tpp = c->g.Lxh * c->g.L[1] / spb;
         a.nzl = c->g.L[2] / 8;
+        a.nys = remap_stripes(t.remap);
     }
     const long long grid = (long long)ntiles * a.G;
     if (grid > 0x7fffffffLL) return set_error(WD_ERR_ARG, "grid too large");
@@ -194,10 +198,11 @@ wd_status run_sweep(wd_ctx *c, const Sweep &sw, const TuneCfg *cfg)
     return WD_OK;
 }
 
-bool slab_order_ok(const Geom &g, int spb)
+bool slab_order_ok(const Geom &g, int spb, int remap)
 {
     const int plane = g.Lxh * g.L[1];
-    return g.L[2] % 8 == 0 && spb > 0 && plane % spb == 0;
+    if (g.L[2] % 8 != 0 || spb <= 0 || plane % spb != 0) return false;
+    return (plane / spb) % remap_stripes(remap) == 0;
 }
 
 static wd_status upload(wd_ctx *c, void *dst, const void *src, size_t bytes)
@@ -258,6 +263,7 @@ void wd_solver_defaults(wd_solver_params *p)
     p->delta = 0.1;
     p->poll = 8;
     p->tuned = 0;
+    p->graphs = 1;
 }
 
 static wd_status check_dims(const int32_t *dims, long long *V)
@@ -321,6 +327,8 @@ wd_status wd_destroy(wd_ctx *c)
         (void)hipEventDestroy(e.first);
         (void)hipEventDestroy(e.second);
     }
+    for (auto &g : c->graphs) (void)hipGraphExecDestroy(g.second);
+    if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
     delete c;
     return WD_OK;
 }

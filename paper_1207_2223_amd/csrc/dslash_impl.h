@@ -107,18 +107,23 @@ __global__ void __launch_bounds__(256) dslash_kernel(DslashArgs a)
     typedef typename SpinorIO<SP>::real real;
     static_assert(sizeof(typename LinkIO<LK>::real) == sizeof(real), "link/spinor precision pair");
     int tile, grp;
-    if (a.remap == 2) {
+    if (a.remap >= 2) {
         // XCD x (= block id mod 8, the dispatch round-robin) owns z-planes
-        // [x*nzl, (x+1)*nzl) for all t; its j-th block takes RHS group
-        // j mod G of the (j / G)-th tile in (t, z, tile-in-plane) order,
-        // z fastest among planes, so the t and z neighbours of a tile were
-        // read a few tiles earlier on the same XCD (same L2).
+        // [x*nzl, (x+1)*nzl) for all t.  Each plane's tpp tiles form nys
+        // stripes (consecutive tiles, i.e. ranges of y); the XCD sweeps one
+        // stripe of its slab through all t before the next.  Its j-th block
+        // takes RHS group j mod G of the (j / G)-th tile in (stripe, t, z,
+        // tile-in-stripe) order, z fastest among planes, so the t and z
+        // neighbours of a tile were read a few tiles earlier on the same XCD
+        // (same L2), and a narrower stripe keeps that window smaller.
         const int x = blockIdx.x & 7, j = blockIdx.x >> 3;
         const int sidx = j / a.G;
         grp = j - sidx * a.G;
-        const int q = sidx % a.tpp, zt = sidx / a.tpp;
-        const int zl = zt % a.nzl, t = zt / a.nzl;
-        tile = ((t * a.g.L[2]) + x * a.nzl + zl) * a.tpp + q;
+        const int tps = a.tpp / a.nys;
+        const int qs = sidx % tps, rest = sidx / tps;
+        const int zl = rest % a.nzl, ts = rest / a.nzl;
+        const int t = ts % a.g.L[3], st = ts / a.g.L[3];
+        tile = ((t * a.g.L[2]) + x * a.nzl + zl) * a.tpp + st * tps + qs;
     } else {
         const int L = a.remap ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
         tile = L / a.G;
@@ -159,26 +164,26 @@ __global__ void __launch_bounds__(256) dslash_kernel(DslashArgs a)
         double nrm = 0.0;
         if (live && rv[r]) {
             if (EPI == EPI_PLAIN) {
-                SpinorIO<SP>::store(a.out + rid[r] * a.out_rs, cs, i, acc[r]);
+                SpinorIO<SP>::template store<true>(a.out + rid[r] * a.out_rs, cs, i, acc[r]);
             } else if (EPI == EPI_XPAY) {
                 const real cf = (real)a.coef[rid[r]];
                 real xv[24];
-                SpinorIO<SP>::load(a.x + rid[r] * a.x_rs, cs, i, xv);
+                SpinorIO<SP>::template load<true>(a.x + rid[r] * a.x_rs, cs, i, xv);
 #pragma unroll
                 for (int k = 0; k < 24; k++) {
                     xv[k] = fmaT(cf, acc[r][k], xv[k]);
                     nrm = fmaT((double)xv[k], (double)xv[k], nrm);
                 }
-                SpinorIO<SP>::store(a.out + rid[r] * a.out_rs, cs, i, xv);
+                SpinorIO<SP>::template store<true>(a.out + rid[r] * a.out_rs, cs, i, xv);
             } else {
                 const real cf = (real)a.coef[rid[r]];
                 const real al = (real)a.alpha[rid[r]];
                 real ap[24], pv[24], rv_[24];
                 typename SpinorIO<XP>::real xv[24];
-                SpinorIO<SP>::load(a.x + rid[r] * a.x_rs, cs, i, ap);
-                SpinorIO<SP>::load(a.p + rid[r] * a.p_rs, cs, i, pv);
-                SpinorIO<SP>::load(a.r + rid[r] * a.r_rs, cs, i, rv_);
-                SpinorIO<XP>::load(a.xs + rid[r] * a.xs_rs, cs, i, xv);
+                SpinorIO<SP>::template load<true>(a.x + rid[r] * a.x_rs, cs, i, ap);
+                SpinorIO<SP>::template load<true>(a.p + rid[r] * a.p_rs, cs, i, pv);
+                SpinorIO<SP>::template load<true>(a.r + rid[r] * a.r_rs, cs, i, rv_);
+                SpinorIO<XP>::template load<true>(a.xs + rid[r] * a.xs_rs, cs, i, xv);
                 typedef typename SpinorIO<XP>::real xreal;
 #pragma unroll
                 for (int k = 0; k < 24; k++) {
@@ -187,8 +192,8 @@ __global__ void __launch_bounds__(256) dslash_kernel(DslashArgs a)
                     rv_[k] = fmaT(-al, ap[k], rv_[k]);
                     nrm = fmaT((double)rv_[k], (double)rv_[k], nrm);
                 }
-                SpinorIO<XP>::store(a.xs + rid[r] * a.xs_rs, cs, i, xv);
-                SpinorIO<SP>::store(a.r + rid[r] * a.r_rs, cs, i, rv_);
+                SpinorIO<XP>::template store<true>(a.xs + rid[r] * a.xs_rs, cs, i, xv);
+                SpinorIO<SP>::template store<true>(a.r + rid[r] * a.r_rs, cs, i, rv_);
             }
         }
         if (EPI != EPI_PLAIN && a.partial != nullptr) {

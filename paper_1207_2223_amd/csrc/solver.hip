@@ -72,6 +72,7 @@ struct BatchSolver {
     // than this factor (in |r|^2): the recursion has lost its accuracy
     static constexpr double kDriftRestart = 4.0;
     static constexpr int kScalars = 9;  // per-slot device scalars (bb .. rr_s)
+    static constexpr size_t kMaxGraphs = 32;  // captured steps kept per context
 
     wd_ctx *c = nullptr;
     wd_solver_params p{};
@@ -454,15 +455,99 @@ struct BatchSolver {
         return WD_OK;
     }
 
+    // Everything the kernel arguments of a step depend on: field and scalar
+    // addresses and strides, RHS counts (grid sizes), formats, launch shapes.
+    std::string graph_key(int k, int nact, int nact64) const
+    {
+        std::string key = pre;
+        auto add = [&key](unsigned long long v) {
+            key += '|';
+            key += std::to_string(v);
+        };
+        auto addf = [&add](const Field &f) {
+            add((unsigned long long)(uintptr_t)f.base);
+            add((unsigned long long)f.rs);
+            add((unsigned long long)f.ss);
+            add((unsigned long long)f.sp);
+            add((unsigned long long)f.nsub);
+            add((unsigned long long)f.cs);
+        };
+        for (unsigned long long v : {(unsigned long long)k, (unsigned long long)nact, (unsigned long long)nact64,
+                                     (unsigned long long)c->use_tuned, (unsigned long long)c->tune_gen,
+                                     (unsigned long long)sp, (unsigned long long)lk, (unsigned long long)xp,
+                                     (unsigned long long)c->lk64, (unsigned long long)p.eo,
+                                     (unsigned long long)pstride})
+            add(v);
+        for (const void *q : {(const void *)c->links64, (const void *)c->links32, (const void *)c->links16,
+                              (const void *)c->links32r, (const void *)coef1, (const void *)coef2,
+                              (const void *)rr, (const void *)alpha, (const void *)beta, (const void *)partial,
+                              (const void *)act, (const void *)act64})
+            add((unsigned long long)(uintptr_t)q);
+        for (const Lane *L : {&lane_s, &lane_d}) {
+            addf(L->P);
+            addf(L->R);
+            addf(L->T2);
+            addf(L->TO);
+            addf(L->X);
+        }
+        addf(Ap64);
+        return key;
+    }
+
+    // The k iterations of a step as one HIP graph: captured on the context's
+    // private stream the first time this key is seen, then replayed on the
+    // context's stream.  The graph holds kernel launches only (no memsets).
+    wd_status run_graph(int k, int nact, int nact64)
+    {
+        const std::string key = graph_key(k, nact, nact64);
+        hipGraphExec_t ex = nullptr;
+        for (auto &g : c->graphs)
+            if (g.first == key) ex = g.second;
+        if (!ex) {
+            if (!c->capture_stream)
+                WD_HIP(hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking));
+            const hipStream_t saved = c->stream;
+            WD_HIP(hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeThreadLocal));
+            c->stream = c->capture_stream;
+            wd_status st = WD_OK;
+            for (int kk = 0; kk < k && st == WD_OK; kk++) {
+                if (nact) st = iterate(lane_s, act, nact);
+                if (st == WD_OK && nact64) st = iterate(lane_d, act64, nact64);
+            }
+            c->stream = saved;
+            hipGraph_t gph = nullptr;
+            const hipError_t e = hipStreamEndCapture(c->capture_stream, &gph);
+            if (st != WD_OK) {
+                if (gph) (void)hipGraphDestroy(gph);
+                return st;
+            }
+            if (e != hipSuccess || !gph) return set_error(WD_ERR_HIP, "graph capture: %s", hipGetErrorString(e));
+            const hipError_t e2 = hipGraphInstantiate(&ex, gph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(gph);
+            if (e2 != hipSuccess) return set_error(WD_ERR_HIP, "graph instantiate: %s", hipGetErrorString(e2));
+            if (c->graphs.size() >= kMaxGraphs) {
+                (void)hipGraphExecDestroy(c->graphs.front().second);
+                c->graphs.erase(c->graphs.begin());
+            }
+            c->graphs.push_back({key, ex});
+        }
+        WD_HIP(hipGraphLaunch(ex, c->stream));
+        return WD_OK;
+    }
+
     // k iterations of every running RHS, then the residual checks.
     wd_status step(int k)
     {
         if ((active.empty() && active64.empty()) || k < 1) return WD_OK;
         const hipStream_t s = c->stream;
         const int nact = (int)active.size(), nact64 = (int)active64.size();
-        for (int kk = 0; kk < k; kk++) {
-            if (nact) WD_TRY(iterate(lane_s, act, nact));
-            if (nact64) WD_TRY(iterate(lane_d, act64, nact64));
+        if (p.graphs && !c->timing) {
+            WD_TRY(run_graph(k, nact, nact64));
+        } else {
+            for (int kk = 0; kk < k; kk++) {
+                if (nact) WD_TRY(iterate(lane_s, act, nact));
+                if (nact64) WD_TRY(iterate(lane_d, act64, nact64));
+            }
         }
         for (int j : active) iters[j] += k;
         for (int j : active64) {

@@ -233,9 +233,9 @@ extern "C" wd_status wd_tune(wd_ctx *c, int nrhs, int prec, char *report, size_t
     for (int rl : rls)
         for (int nr : nrs)
             for (int b : blocks)
-                for (int rm = 0; rm < 3; rm++) {
+                for (int rm = 0; rm < 5; rm++) {
                     if (!dslash_shape_supported(sp, nr, rl)) continue;
-                    if (rm == 2 && !slab_order_ok(c->g, b / rl)) continue;
+                    if (rm >= 2 && !slab_order_ok(c->g, b / rl, rm)) continue;
                     if (nr * rl > 2 * nrhs && !(nr == 1 && rl == 1)) continue;  // mostly idle lanes
                     TuneCfg q;
                     q.block = b;
@@ -260,6 +260,7 @@ extern "C" wd_status wd_tune(wd_ctx *c, int nrhs, int prec, char *report, size_t
             if (cache_lookup(cache, cache_key(c, nrhs, sp, lk, k.dag, k.epi), &cc, &us) &&
                 dslash_shape_supported(sp, cc.nr, cc.rl)) {
                 c->tuned[sweep_key(sp, lk, k.dag, k.epi)] = cc;
+                c->tune_gen++;
                 char line[256];
                 snprintf(line, sizeof(line),
                          "%s;sp=%d;lk=%d;nrhs=%d;block=%d;nr=%d;rl=%d;remap=%d;us=%.2f;GB/s=0.0;candidates=0;rejected=0\n",
@@ -331,6 +332,7 @@ extern "C" wd_status wd_tune(wd_ctx *c, int nrhs, int prec, char *report, size_t
         }
         if (st != WD_OK) break;
         c->tuned[sweep_key(sp, lk, k.dag, k.epi)] = bestc;
+        c->tune_gen++;
         if (cache && cache[0]) cache_store(cache, cache_key(c, nrhs, sp, lk, k.dag, k.epi), bestc, best * 1e3);
         Sweep swb = sw;
         const double gbs = sweep_bytes(c, swb) / (best * 1e-3) / 1e9;

@@ -115,55 +115,91 @@ __device__ __forceinline__ int neighbour(const Geom &g, int i, const int c[4])
 // ---------------------------------------------------------------------------
 // Spinor storage
 // ---------------------------------------------------------------------------
+// Vector loads and stores with an optional non-temporal hint (NT): data a
+// sweep touches once at its own site (epilogue operands and outputs) is
+// marked so that the L2 keeps the neighbour spinors and links, which are
+// read by up to eight sites.  The hint changes caching only, never values.
+typedef double dbl2_t __attribute__((ext_vector_type(2)));
+typedef float flt4_t __attribute__((ext_vector_type(4)));
+typedef unsigned u32x4_t __attribute__((ext_vector_type(4)));
+
+template <bool NT, typename V>
+__device__ __forceinline__ V ld_hint(const V *p)
+{
+    if constexpr (NT)
+        return __builtin_nontemporal_load(p);
+    else
+        return *p;
+}
+
+template <bool NT, typename V>
+__device__ __forceinline__ void st_hint(V *p, V v)
+{
+    if constexpr (NT)
+        __builtin_nontemporal_store(v, p);
+    else
+        *p = v;
+}
+
 template <int SP> struct SpinorIO;
 
 template <> struct SpinorIO<SP_F64> {
     typedef double real;
     static constexpr size_t site_bytes = 192;
-    template <typename T>
+    template <bool NT = false, typename T>
     __device__ static __forceinline__ void load(const char *f, int cs, int i, T v[24])
     {
-        const double2 *p = reinterpret_cast<const double2 *>(f);
+        const dbl2_t *p = reinterpret_cast<const dbl2_t *>(f);
 #pragma unroll
         for (int k = 0; k < 12; k++) {
-            double2 w = p[(size_t)k * cs + i];
+            const dbl2_t w = ld_hint<NT>(p + (size_t)k * cs + i);
             v[2 * k] = (T)w.x;
             v[2 * k + 1] = (T)w.y;
         }
     }
-    template <typename T>
+    template <bool NT = false, typename T>
     __device__ static __forceinline__ void store(char *f, int cs, int i, const T v[24])
     {
-        double2 *p = reinterpret_cast<double2 *>(f);
+        dbl2_t *p = reinterpret_cast<dbl2_t *>(f);
 #pragma unroll
-        for (int k = 0; k < 12; k++) p[(size_t)k * cs + i] = make_double2((double)v[2 * k], (double)v[2 * k + 1]);
+        for (int k = 0; k < 12; k++) {
+            dbl2_t w;
+            w.x = (double)v[2 * k];
+            w.y = (double)v[2 * k + 1];
+            st_hint<NT>(p + (size_t)k * cs + i, w);
+        }
     }
 };
 
 template <> struct SpinorIO<SP_F32> {
     typedef float real;
     static constexpr size_t site_bytes = 96;
-    template <typename T>
+    template <bool NT = false, typename T>
     __device__ static __forceinline__ void load(const char *f, int cs, int i, T v[24])
     {
-        const float4 *p = reinterpret_cast<const float4 *>(f);
+        const flt4_t *p = reinterpret_cast<const flt4_t *>(f);
 #pragma unroll
         for (int k = 0; k < 6; k++) {
-            float4 w = p[(size_t)k * cs + i];
+            const flt4_t w = ld_hint<NT>(p + (size_t)k * cs + i);
             v[4 * k] = (T)w.x;
             v[4 * k + 1] = (T)w.y;
             v[4 * k + 2] = (T)w.z;
             v[4 * k + 3] = (T)w.w;
         }
     }
-    template <typename T>
+    template <bool NT = false, typename T>
     __device__ static __forceinline__ void store(char *f, int cs, int i, const T v[24])
     {
-        float4 *p = reinterpret_cast<float4 *>(f);
+        flt4_t *p = reinterpret_cast<flt4_t *>(f);
 #pragma unroll
-        for (int k = 0; k < 6; k++)
-            p[(size_t)k * cs + i] = make_float4((float)v[4 * k], (float)v[4 * k + 1], (float)v[4 * k + 2],
-                                                (float)v[4 * k + 3]);
+        for (int k = 0; k < 6; k++) {
+            flt4_t w;
+            w.x = (float)v[4 * k];
+            w.y = (float)v[4 * k + 1];
+            w.z = (float)v[4 * k + 2];
+            w.w = (float)v[4 * k + 3];
+            st_hint<NT>(p + (size_t)k * cs + i, w);
+        }
     }
 };
 
@@ -172,19 +208,19 @@ template <> struct SpinorIO<SP_F32> {
 template <> struct SpinorIO<SP_F16> {
     typedef float real;
     static constexpr size_t site_bytes = 52;
-    template <typename T>
+    template <bool NT = false, typename T>
     __device__ static __forceinline__ void load(const char *f, int cs, int i, T v[24])
     {
         const half8_t *p = reinterpret_cast<const half8_t *>(f);
-        const float n = reinterpret_cast<const float *>(f + (size_t)48 * cs)[i];
+        const float n = ld_hint<NT>(reinterpret_cast<const float *>(f + (size_t)48 * cs) + i);
 #pragma unroll
         for (int k = 0; k < 3; k++) {
-            half8_t w = p[(size_t)k * cs + i];
+            const half8_t w = ld_hint<NT>(p + (size_t)k * cs + i);
 #pragma unroll
             for (int j = 0; j < 8; j++) v[8 * k + j] = (T)((float)w[j] * n);
         }
     }
-    template <typename T>
+    template <bool NT = false, typename T>
     __device__ static __forceinline__ void store(char *f, int cs, int i, const T v[24])
     {
         // The scaled value is rounded to FP32 and then to FP16 (RNE) by an
@@ -194,16 +230,16 @@ template <> struct SpinorIO<SP_F16> {
 #pragma unroll
         for (int j = 0; j < 24; j++) m = fmaxf(m, fabsf((float)v[j]));
         const float inv = (m > 0.f) ? 1.0f / m : 0.f;
-        uint4 *p = reinterpret_cast<uint4 *>(f);
+        u32x4_t *p = reinterpret_cast<u32x4_t *>(f);
 #pragma unroll
         for (int k = 0; k < 3; k++) {
-            uint32_t w[4];
+            u32x4_t w;
 #pragma unroll
             for (int j = 0; j < 4; j++)
                 w[j] = cvt_pk_f16((float)v[8 * k + 2 * j] * inv, (float)v[8 * k + 2 * j + 1] * inv);
-            p[(size_t)k * cs + i] = make_uint4(w[0], w[1], w[2], w[3]);
+            st_hint<NT>(p + (size_t)k * cs + i, w);
         }
-        reinterpret_cast<float *>(f + (size_t)48 * cs)[i] = m;
+        st_hint<NT>(reinterpret_cast<float *>(f + (size_t)48 * cs) + i, m);
     }
 };
 

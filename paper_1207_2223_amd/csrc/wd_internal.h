@@ -69,6 +69,7 @@ struct DslashArgs {
     int remap;             // tile order: 0 dispatch order, 1 XCD-contiguous, 2 XCD z-slabs
     int tpp;               // remap 2: tiles per (z, t) plane
     int nzl;               // remap 2: z planes per XCD
+    int nys;               // remap >= 2: stripes per plane (1, 2, 4 for remap 2, 3, 4)
     double *partial;       // partial[rid*pstride + pw_off + site/16] = sum |out|^2 (or |r|^2)
     int pstride;
     int pw_off;
@@ -163,6 +164,13 @@ struct wd_ctx {
     // whether the current call uses them
     std::map<std::string, wd::TuneCfg> tuned;
     bool use_tuned = false;
+    unsigned tune_gen = 0;  // bumped whenever `tuned` changes
+
+    // CG steps captured as HIP graphs (solver.hip), keyed by everything their
+    // kernel arguments depend on; a bounded FIFO.  Captured on a private
+    // stream, replayed on `stream`.
+    std::vector<std::pair<std::string, hipGraphExec_t>> graphs;
+    hipStream_t capture_stream = nullptr;
 };
 
 namespace wd {
@@ -198,7 +206,8 @@ wd_status upload_ints(wd_ctx *c, const std::string &name, const int *v, int n, i
 Field sub_view(const Field &f, int s);
 TuneCfg default_cfg(int sp);
 // Whether the z-slab tile order (remap 2) applies to tiles of spb sites.
-bool slab_order_ok(const Geom &g, int spb);
+bool slab_order_ok(const Geom &g, int spb, int remap = 2);
+inline int remap_stripes(int remap) { return remap <= 2 ? 1 : (remap == 3 ? 2 : 4); }
 const TuneCfg *tuned_cfg(const wd_ctx *c, const Sweep &sw);
 double sweep_bytes(const wd_ctx *c, const Sweep &sw);
 

@@ -33,7 +33,8 @@ class WDError(RuntimeError):
 
 class wd_solver_params(C.Structure):
     _fields_ = [("tol", C.c_double), ("maxiter", C.c_int), ("prec_sloppy", C.c_int),
-                ("eo", C.c_int), ("delta", C.c_double), ("poll", C.c_int), ("tuned", C.c_int)]
+                ("eo", C.c_int), ("delta", C.c_double), ("poll", C.c_int), ("tuned", C.c_int),
+                ("graphs", C.c_int)]
 
 
 class wd_solver_stats(C.Structure):
@@ -398,10 +399,10 @@ def wd_version():
     return lib().wd_version().decode()
 
 
-def solver_params(tol=1e-10, maxiter=20000, prec=WD_F64, eo=1, delta=0.1, poll=8, tuned=0):
+def solver_params(tol=1e-10, maxiter=20000, prec=WD_F64, eo=1, delta=0.1, poll=8, tuned=0, graphs=1):
     p = wd_solver_defaults()
-    p.tol, p.maxiter, p.prec_sloppy, p.eo, p.delta, p.poll, p.tuned = (
-        float(tol), int(maxiter), int(prec), int(eo), float(delta), int(poll), int(tuned))
+    p.tol, p.maxiter, p.prec_sloppy, p.eo, p.delta, p.poll, p.tuned, p.graphs = (
+        float(tol), int(maxiter), int(prec), int(eo), float(delta), int(poll), int(tuned), int(graphs))
     return p
 
 

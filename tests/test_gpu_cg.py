@@ -139,3 +139,32 @@ def test_near_singular_operator_finishes_in_fp64(wd, oracle, prec):
     assert res["mixed"]["iters_fp64"] > 0
     assert res["fp64"]["iters_fp64"] == res["fp64"]["iters"]
     lat.close()
+
+
+@pytest.mark.parametrize("prec", ["F64", "F16"])
+def test_graph_replay_equals_eager_launches(wd, prec):
+    """The poll iterations of each step replayed as a captured HIP graph
+    give bitwise the eager results.  Four RHS converge at different steps
+    (the active set shrinks, so new graphs are captured), kappa = 0.14757
+    sends one RHS to the FP64 lane in the mixed solve, every replay is
+    separated by the host's residual checks and eager reliable updates, and
+    a second graph solve in the same context reuses the cached graphs."""
+    dims = (8, 8, 8, 8)
+    U = li.random_su3_field(dims, 0.5, seed=1003)
+    B = li.gaussian_spinor(li.volume(dims) // 2, seed=704, nrhs=4)
+    kap = [0.14757, 0.15, 0.155, 0.157]
+    code = {"F64": wd.WD_F64, "F16": wd.WD_F16}[prec]
+    lat = wd.Lattice(dims)
+    lat.gauge_load(dev(U), recon=12)
+    out = []
+    for graphs in (0, 1, 1):
+        X = empty_like_dev(B)
+        st, stats = lat.cg_solve(X, dev(B), kap, wd.solver_params(prec=code, maxiter=3000, graphs=graphs))
+        assert st == wd.WD_OK, stats
+        out.append((host(X), [(s["iters"], s["iters_fp64"], s["reliable_updates"]) for s in stats]))
+    note(f"graphs {prec}: iters {out[0][1]}")
+    assert out[0][1] == out[1][1] == out[2][1]
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][0], out[2][0])
+    if prec == "F16":
+        assert out[0][1][0][1] > 0  # the FP64 lane ran inside the graphs too
+    lat.close()
