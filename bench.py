@@ -268,6 +268,9 @@ def bench_solve(args, wd, torch):
     dom, roof, sten = kernel_roofline(report, t_inst)
     roof["traffic"] = counter_traffic(args.workload, args.prec, dom["name"])
 
+    stream = copy_bandwidth(torch)
+    dsl = dslash_section(wd, Ud, dims, stream, PRECS[args.prec], nrhs, tuned=args.tuned)
+
     fp64 = None
     if not args.no_fp64 and args.prec != "f64":
         p64 = wd.solver_params(prec=0, eo=1, tuned=args.tuned)
@@ -305,9 +308,58 @@ def bench_solve(args, wd, torch):
         "roofline": roof,
         "fp64": fp64,
         "mixed_vs_fp64": (value / fp64["solves_per_s"]) if fp64 else None,
+        "stream_copy_GB_s": stream,
+        "dslash": dsl,
         "cpu_baseline": cpu,
     })
     return out
+
+
+def copy_bandwidth(torch, gib=2):
+    """Device copy bandwidth (read + write bytes / time) of a 2 GiB torch
+    copy, median of 5: the achievable-HBM yardstick next to the 8 TB/s peak."""
+    n = (gib << 30) // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    ts = []
+    for _ in range(5):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        e1.synchronize()
+        ts.append(e0.elapsed_time(e1) * 1e-3)
+    del a, b
+    torch.cuda.empty_cache()
+    return 2 * (gib << 30) / float(np.median(ts)) / 1e9
+
+
+def dslash_section(wd, Ud, dims, stream_gbs, prec, nrhs, tuned=1):
+    """The hopping stencil alone (one parity sweep D_oe, plain and with the
+    fused CG update), on a context of its own: one RHS in FP64, FP32, FP16
+    and FP16 with FP16 links, and the workload's RHS count in its precision.
+    Algorithmic GB/s, its fraction of the 8 TB/s peak and of the measured copy
+    bandwidth, GFLOP/s at 1320 flop per site and RHS; autotuned shapes."""
+    Vh = int(np.prod(dims)) // 2
+    lat = wd.Lattice(dims)
+    lat.gauge_load(Ud, recon=12)
+    rows = []
+    cases = [("f64", 0, 1), ("f32", 1, 1), ("f16", 2, 1), ("f16l16", 2 | 0x10, 1)]
+    cases.append((next(k for k, v in PRECS.items() if v == prec), prec, nrhs))
+    for name, code, n in cases:
+        if tuned:
+            wd.wd_tune(lat.ctx, n, code)
+        for epi, ename in ((0, "plain"), (2, "cg-update")):
+            ms, by = wd.wd_bench_dslash(lat.ctx, n, code, epi=epi, iters=20, tuned=tuned)
+            gbs = by / (ms * 1e-3) / 1e9
+            rows.append({"prec": name, "nrhs": n, "sweep": ename, "us": ms * 1e3, "bytes": by,
+                         "GB_s": gbs, "frac_peak": gbs / HBM_PEAK_GBS, "frac_copy": gbs / stream_gbs,
+                         "GFLOP_s": FLOP_SITE * Vh * n / (ms * 1e-3) / 1e9})
+            log(f"[bench] dslash {name} nrhs {n} {ename}: {ms * 1e3:.1f} us {gbs:.0f} GB/s "
+                f"({gbs / HBM_PEAK_GBS * 100:.1f} % of peak, {gbs / stream_gbs * 100:.1f} % of copy)")
+    lat.close()
+    return rows
 
 
 # ---------------------------------------------------------------------------

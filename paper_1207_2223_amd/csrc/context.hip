@@ -156,13 +156,13 @@ wd_status run_sweep(wd_ctx *c, const Sweep &sw, const TuneCfg *cfg)
     a.tpp = 1;
     a.nzl = 1;
     a.nys = 1;
-    if (t.remap > 4 || t.remap < 0) return set_error(WD_ERR_ARG, "tile order %d unknown", t.remap);
+    if (t.remap >= kTileOrders || t.remap < 0) return set_error(WD_ERR_ARG, "tile order %d unknown", t.remap);
     if (t.remap >= 2) {
         if (!slab_order_ok(c->g, spb, t.remap))
-            return set_error(WD_ERR_ARG, "z-slab tile order %d needs Lz %% 8 == 0 and whole tiles per plane "
-                             "and stripe", t.remap);
+            return set_error(WD_ERR_ARG, "slab tile order %d needs Lz (or Lt) %% 8 == 0 and whole tiles per "
+                             "plane and stripe", t.remap);
         a.tpp = c->g.Lxh * c->g.L[1] / spb;
-        a.nzl = c->g.L[2] / 8;
+        a.nzl = (t.remap >= 5 ? c->g.L[3] : c->g.L[2]) / 8;
         a.nys = remap_stripes(t.remap);
     }
     const long long grid = (long long)ntiles * a.G;
@@ -201,7 +201,7 @@ wd_status run_sweep(wd_ctx *c, const Sweep &sw, const TuneCfg *cfg)
 bool slab_order_ok(const Geom &g, int spb, int remap)
 {
     const int plane = g.Lxh * g.L[1];
-    if (g.L[2] % 8 != 0 || spb <= 0 || plane % spb != 0) return false;
+    if (g.L[remap >= 5 ? 3 : 2] % 8 != 0 || spb <= 0 || plane % spb != 0) return false;
     return (plane / spb) % remap_stripes(remap) == 0;
 }
 

@@ -64,12 +64,11 @@ __device__ __forceinline__ void hop_dir(const DslashArgs &a, int i, const int c[
             real v[24], h[12], w[12];
             const real sc = load_nb<SP>(a.in + rid[r] * a.in_rs, cs, j, v);
             project<MU, SF>(v, h);
-            if constexpr (SP == SP_F16) {
-#pragma unroll
-                for (int k = 0; k < 12; k++) h[k] *= sc;
-            }
             su3_mul_half<false>(u, h, w);
-            accumulate<MU, SF>(acc[r], w);
+            if constexpr (SP == SP_F16)
+                accumulate_scaled<MU, SF>(acc[r], w, sc);
+            else
+                accumulate<MU, SF>(acc[r], w);
         }
     }
     {
@@ -81,12 +80,11 @@ __device__ __forceinline__ void hop_dir(const DslashArgs &a, int i, const int c[
             real v[24], h[12], w[12];
             const real sc = load_nb<SP>(a.in + rid[r] * a.in_rs, cs, j, v);
             project<MU, SB>(v, h);
-            if constexpr (SP == SP_F16) {
-#pragma unroll
-                for (int k = 0; k < 12; k++) h[k] *= sc;
-            }
             su3_mul_half<true>(u, h, w);
-            accumulate<MU, SB>(acc[r], w);
+            if constexpr (SP == SP_F16)
+                accumulate_scaled<MU, SB>(acc[r], w, sc);
+            else
+                accumulate<MU, SB>(acc[r], w);
         }
     }
 }
@@ -107,7 +105,26 @@ __global__ void __launch_bounds__(256) dslash_kernel(DslashArgs a)
     typedef typename SpinorIO<SP>::real real;
     static_assert(sizeof(typename LinkIO<LK>::real) == sizeof(real), "link/spinor precision pair");
     int tile, grp;
-    if (a.remap >= 2) {
+    if (a.remap >= 5) {
+        // XCD x owns t-planes [x*ntl, (x+1)*ntl) (ntl = Lt / 8, held in nzl)
+        // and walks them t-fastest: a tile's t-neighbours are the tiles just
+        // before and after it on the same XCD, its z-neighbours ntl tiles
+        // away.  Order 5 takes (tile-in-plane, z, t), order 6 (z,
+        // tile-in-plane, t), slowest to fastest.
+        const int x = blockIdx.x & 7, j = blockIdx.x >> 3;
+        const int sidx = j / a.G;
+        grp = j - sidx * a.G;
+        const int tl = sidx % a.nzl, rest = sidx / a.nzl;
+        int z, q;
+        if (a.remap == 5) {
+            z = rest % a.g.L[2];
+            q = rest / a.g.L[2];
+        } else {
+            q = rest % a.tpp;
+            z = rest / a.tpp;
+        }
+        tile = ((x * a.nzl + tl) * a.g.L[2] + z) * a.tpp + q;
+    } else if (a.remap >= 2) {
         // XCD x (= block id mod 8, the dispatch round-robin) owns z-planes
         // [x*nzl, (x+1)*nzl) for all t.  Each plane's tpp tiles form nys
         // stripes (consecutive tiles, i.e. ranges of y); the XCD sweeps one

@@ -233,7 +233,7 @@ extern "C" wd_status wd_tune(wd_ctx *c, int nrhs, int prec, char *report, size_t
     for (int rl : rls)
         for (int nr : nrs)
             for (int b : blocks)
-                for (int rm = 0; rm < 5; rm++) {
+                for (int rm = 0; rm < kTileOrders; rm++) {
                     if (!dslash_shape_supported(sp, nr, rl)) continue;
                     if (rm >= 2 && !slab_order_ok(c->g, b / rl, rm)) continue;
                     if (nr * rl > 2 * nrhs && !(nr == 1 && rl == 1)) continue;  // mostly idle lanes

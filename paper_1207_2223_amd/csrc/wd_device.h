@@ -456,6 +456,43 @@ __device__ __forceinline__ void accumulate(T acc[24], const T w[12])
     }
 }
 
+// acc += sc * (full 4-spinor rebuilt from w): the FP16 per-site norm folded
+// into the accumulation, one fused multiply-add per term.
+template <int MU, int S, typename T>
+__device__ __forceinline__ void accumulate_scaled(T acc[24], const T w[12], const T sc)
+{
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        const T a0r = w[2 * c], a0i = w[2 * c + 1];
+        const T a1r = w[6 + 2 * c], a1i = w[6 + 2 * c + 1];
+        acc[2 * c] = fmaT(sc, a0r, acc[2 * c]);
+        acc[2 * c + 1] = fmaT(sc, a0i, acc[2 * c + 1]);
+        acc[6 + 2 * c] = fmaT(sc, a1r, acc[6 + 2 * c]);
+        acc[6 + 2 * c + 1] = fmaT(sc, a1i, acc[6 + 2 * c + 1]);
+        if (MU == 0) {  // row2 = -S i h1, row3 = -S i h0    (-S i (a+ib) = S b - S i a)
+            acc[12 + 2 * c] = fmaT(S * sc, a1i, acc[12 + 2 * c]);
+            acc[12 + 2 * c + 1] = fmaT(-S * sc, a1r, acc[12 + 2 * c + 1]);
+            acc[18 + 2 * c] = fmaT(S * sc, a0i, acc[18 + 2 * c]);
+            acc[18 + 2 * c + 1] = fmaT(-S * sc, a0r, acc[18 + 2 * c + 1]);
+        } else if (MU == 1) {  // row2 = S h1, row3 = -S h0
+            acc[12 + 2 * c] = fmaT(S * sc, a1r, acc[12 + 2 * c]);
+            acc[12 + 2 * c + 1] = fmaT(S * sc, a1i, acc[12 + 2 * c + 1]);
+            acc[18 + 2 * c] = fmaT(-S * sc, a0r, acc[18 + 2 * c]);
+            acc[18 + 2 * c + 1] = fmaT(-S * sc, a0i, acc[18 + 2 * c + 1]);
+        } else if (MU == 2) {  // row2 = -S i h0, row3 = S i h1
+            acc[12 + 2 * c] = fmaT(S * sc, a0i, acc[12 + 2 * c]);
+            acc[12 + 2 * c + 1] = fmaT(-S * sc, a0r, acc[12 + 2 * c + 1]);
+            acc[18 + 2 * c] = fmaT(-S * sc, a1i, acc[18 + 2 * c]);
+            acc[18 + 2 * c + 1] = fmaT(S * sc, a1r, acc[18 + 2 * c + 1]);
+        } else {  // row2 = S h0, row3 = S h1
+            acc[12 + 2 * c] = fmaT(S * sc, a0r, acc[12 + 2 * c]);
+            acc[12 + 2 * c + 1] = fmaT(S * sc, a0i, acc[12 + 2 * c + 1]);
+            acc[18 + 2 * c] = fmaT(S * sc, a1r, acc[18 + 2 * c]);
+            acc[18 + 2 * c + 1] = fmaT(S * sc, a1i, acc[18 + 2 * c + 1]);
+        }
+    }
+}
+
 // w = U h for both half-spinor rows (h, w: 12 reals), or U^dag h.
 template <bool ADJ, typename T>
 __device__ __forceinline__ void su3_mul_half(const T u[18], const T h[12], T w[12])

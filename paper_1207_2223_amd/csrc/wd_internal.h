@@ -67,8 +67,8 @@ struct DslashArgs {
     int nact;
     int G;                 // RHS groups of RL*NR per tile
     int remap;             // tile order: 0 dispatch order, 1 XCD-contiguous, 2 XCD z-slabs
-    int tpp;               // remap 2: tiles per (z, t) plane
-    int nzl;               // remap 2: z planes per XCD
+    int tpp;               // remap >= 2: tiles per (z, t) plane
+    int nzl;               // remap 2-4: z planes per XCD; 5-6: t planes per XCD
     int nys;               // remap >= 2: stripes per plane (1, 2, 4 for remap 2, 3, 4)
     double *partial;       // partial[rid*pstride + pw_off + site/16] = sum |out|^2 (or |r|^2)
     int pstride;
@@ -206,8 +206,11 @@ wd_status upload_ints(wd_ctx *c, const std::string &name, const int *v, int n, i
 Field sub_view(const Field &f, int s);
 TuneCfg default_cfg(int sp);
 // Whether the z-slab tile order (remap 2) applies to tiles of spb sites.
+// Tile orders: 0 plain, 1 XCD round-robin, 2-4 z-slab per XCD in 1/2/4
+// y-stripes, 5-6 t-slab per XCD walked t-fastest.
+constexpr int kTileOrders = 7;
 bool slab_order_ok(const Geom &g, int spb, int remap = 2);
-inline int remap_stripes(int remap) { return remap <= 2 ? 1 : (remap == 3 ? 2 : 4); }
+inline int remap_stripes(int remap) { return remap <= 2 || remap >= 5 ? 1 : (remap == 3 ? 2 : 4); }
 const TuneCfg *tuned_cfg(const wd_ctx *c, const Sweep &sw);
 double sweep_bytes(const wd_ctx *c, const Sweep &sw);
 

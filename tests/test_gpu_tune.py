@@ -21,8 +21,9 @@ def wd():
 def _expected_candidates(dims, code, nrhs):
     """The tuner's candidate count: block {64,128,256} x RHS per lane x lanes
     per site x tile order {plain, XCD round-robin, z-slab with 1, 2, 4
-    y-stripes}, where the slab orders need Lz % 8 == 0 and a whole number of
-    tiles per plane and per stripe."""
+    y-stripes, t-slab walked t-fastest in two orders}, where the z-slab
+    orders need Lz % 8 == 0, the t-slab orders Lt % 8 == 0, and both a whole
+    number of tiles per plane and per stripe."""
     f64 = (code & 0xF) == 0
     shapes = [(1, 1), (2, 1), (1, 2), (2, 2), (1, 4), (2, 4)] if f64 else \
         [(nr, rl) for rl in (1, 2, 4) for nr in (1, 2, 3, 4)]
@@ -33,20 +34,22 @@ def _expected_candidates(dims, code, nrhs):
             continue
         for b in (64, 128, 256):
             spb = b // rl
-            for rm, ns in ((0, 0), (1, 0), (2, 1), (3, 2), (4, 4)):
-                if rm >= 2 and not (dims[2] % 8 == 0 and plane % spb == 0 and (plane // spb) % ns == 0):
+            for rm, ns in ((0, 0), (1, 0), (2, 1), (3, 2), (4, 4), (5, 1), (6, 1)):
+                slab = dims[3] if rm >= 5 else dims[2]
+                if rm >= 2 and not (slab % 8 == 0 and plane % spb == 0 and (plane // spb) % ns == 0):
                     continue
                 n += 1
     return n
 
 
 @pytest.mark.parametrize("prec", ["F64", "F32", "F16", "F16L", "F16R"])
-@pytest.mark.parametrize("dims", [(6, 4, 4, 6), (16, 8, 8, 4), (16, 16, 8, 4)])
+@pytest.mark.parametrize("dims", [(6, 4, 4, 6), (16, 8, 8, 4), (16, 16, 8, 4), (8, 8, 4, 8)])
 def test_tuner_all_shapes_bitwise_and_tuned_solve_identical(wd, oracle, prec, dims):
     """(6,4,4,6): Vh = 288, a ragged last tile for every block size;
     (16,8,8,4): Lz divisible by 8, so the z-slab tile order is a candidate;
     (16,16,8,4): 128 cb sites per plane, so the z-slab order in 2 and 4
-    y-stripes is a candidate too."""
+    y-stripes is a candidate too; (8,8,4,8): Lt divisible by 8, so the
+    t-slab orders are candidates."""
     code = {"F64": wd.WD_F64, "F32": wd.WD_F32, "F16": wd.WD_F16,
             "F16L": wd.WD_F16 | wd.WD_LINKS_F16, "F16R": wd.WD_F16 | wd.WD_LINKS_R18}[prec]
     V = li.volume(dims)
