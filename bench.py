@@ -109,6 +109,8 @@ def parse():
     ap.add_argument("--prec", default="f16", choices=sorted(PRECS))
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-dslash", action="store_true",
+                    help="skip the stencil-alone section and the copy-bandwidth probe")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--tuned", type=int, default=1, help="autotune launch shapes before timing")
     ap.add_argument("--requests", type=int, default=None, help="c4: requests per pass")
@@ -268,8 +270,10 @@ def bench_solve(args, wd, torch):
     dom, roof, sten = kernel_roofline(report, t_inst)
     roof["traffic"] = counter_traffic(args.workload, args.prec, dom["name"])
 
-    stream = copy_bandwidth(torch)
-    dsl = dslash_section(wd, Ud, dims, stream, PRECS[args.prec], nrhs, tuned=args.tuned)
+    stream = dsl = None
+    if not args.no_dslash:
+        stream = copy_bandwidth(torch)
+        dsl = dslash_section(wd, Ud, dims, stream, PRECS[args.prec], nrhs, tuned=args.tuned)
 
     fp64 = None
     if not args.no_fp64 and args.prec != "f64":
