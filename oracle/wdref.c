@@ -834,3 +834,81 @@ int wdref_hmc_trajectory(const int32_t d[4], double *U_, double beta, double kap
     free(U0); free(P); free(chi); free(phi);
     return st;
 }
+
+/* ------------------------------------------------------------------------ */
+/* End-of-trajectory measurements (Sec. 3: "at the end of each trajectory    */
+/* measurements are carried out on the gauge configuration"; the paper does  */
+/* not say which -- reading: Polyakov loop and the point-source pion         */
+/* correlator, besides the plaquette).                                       */
+/* ------------------------------------------------------------------------ */
+
+/* Polyakov loop: (1/V3) sum over spatial sites of (1/3) tr prod_t U_t(x,t),
+ * the product taken in increasing t.  out = {Re, Im}. */
+void wdref_polyakov(const int32_t d[4], const double *U_, double *out)
+{
+    const cplx *U = (const cplx *)U_;
+    const long v3 = (long)d[0] * d[1] * d[2];
+    cplx sum = 0;
+    for (long s = 0; s < v3; s++) {
+        cplx P[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1}, T[9];
+        for (int t = 0; t < d[3]; t++) {
+            mm(P, link(U, s + v3 * t, 3), T);
+            memcpy(P, T, sizeof(T));
+        }
+        sum += tr3(P) / 3.0;
+    }
+    sum /= (double)v3;
+    out[0] = creal(sum);
+    out[1] = cimag(sum);
+}
+
+/* Point-source propagator: column j = 3*spin + colour of psi ([12][V][4][3])
+ * solves M psi_j = b_j with b_j = delta(x, src) delta(spin) delta(colour), by
+ * CG on the full normal equations M^dag M psi = M^dag b (the definition, no
+ * even-odd split).  Returns 0 when all 12 converge to tol; iters (may be
+ * NULL) gets the summed CG iterations. */
+int wdref_point_propagator(const int32_t d[4], const double *U, double kappa, const int32_t src[4],
+                           double tol, int maxiter, double *psi_, int *iters)
+{
+    const long V = vol(d), n = V * 12;
+    int x0[4] = {src[0], src[1], src[2], src[3]};
+    const long s0 = lex_of(d, x0);
+    cplx *b = calloc(n, sizeof(cplx)), *rhs = malloc(sizeof(cplx) * n);
+    int status = 0, total = 0;
+    for (int j = 0; j < 12; j++) {
+        memset(b, 0, sizeof(cplx) * n);
+        b[s0 * 12 + j] = 1.0;
+        wilson(d, (const cplx *)U, kappa, b, rhs, 1); /* M^dag b */
+        int it;
+        double tr;
+        int st = wdref_cg(d, U, kappa, 0, (const double *)rhs, psi_ + (size_t)j * n * 2, tol, maxiter,
+                          &it, &tr, NULL);
+        total += it;
+        if (st != 0) status = st;
+    }
+    if (iters) *iters = total;
+    free(b);
+    free(rhs);
+    return status;
+}
+
+/* Pion correlator of a point-source propagator (psi as above):
+ * C(dt) = sum over spatial sites x and the 12 x 12 spin-colour entries of
+ * |psi_j(x, (t0 + dt) mod Lt)|^2, t0 = src time; by gamma_5-hermiticity this
+ * is the zero-momentum pseudoscalar two-point function tr[S S^dag]. */
+void wdref_pion_correlator(const int32_t d[4], const double *psi_, const int32_t src[4], double *corr)
+{
+    const cplx *psi = (const cplx *)psi_;
+    const long V = vol(d), v3 = (long)d[0] * d[1] * d[2];
+    for (int dt = 0; dt < d[3]; dt++) {
+        const int t = (src[3] + dt) % d[3];
+        double c = 0.0;
+        for (int j = 0; j < 12; j++)
+            for (long s = 0; s < v3; s++)
+                for (int k = 0; k < 12; k++) {
+                    const cplx z = psi[((size_t)j * V + s + v3 * t) * 12 + k];
+                    c += creal(z) * creal(z) + cimag(z) * cimag(z);
+                }
+        corr[dt] = c;
+    }
+}

@@ -59,6 +59,9 @@ def lib():
                                          C.c_int, C.POINTER(C.c_int)]),
             "wdref_hmc_trajectory": (C.c_int, [i32p, P, d, d, C.c_int, d, C.c_int,
                                                C.c_uint64, C.c_uint32, d, d, C.c_int, P]),
+            "wdref_polyakov": (None, [i32p, P, P]),
+            "wdref_point_propagator": (C.c_int, [i32p, P, d, i32p, d, C.c_int, P, C.POINTER(C.c_int)]),
+            "wdref_pion_correlator": (None, [i32p, P, i32p, P]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -281,3 +284,26 @@ def hmc_trajectory(dims, U, beta, kappa, tau, nsteps, seed, traj, eo=True, tol_f
     r["accepted"] = bool(r["accepted"])
     r["cg_iters"] = int(r["cg_iters"])
     return U, r
+
+
+def polyakov(dims, U):
+    out = np.zeros(2)
+    lib().wdref_polyakov(_dims(dims), _p(_c128(U)), _p(out))
+    return complex(out[0], out[1])
+
+
+def point_propagator(dims, U, kappa, src, tol=1e-12, maxiter=100000):
+    """psi [12][V][4][3]: column 3*spin + colour solves M psi = point source
+    at src (spin, colour); returns (psi, status, summed CG iterations)."""
+    V = volume(dims)
+    psi = np.zeros((12, V, 4, 3), np.complex128)
+    it = C.c_int(0)
+    st = lib().wdref_point_propagator(_dims(dims), _p(_c128(U)), float(kappa), _dims(src), float(tol),
+                                      int(maxiter), _p(psi), C.byref(it))
+    return psi, st, it.value
+
+
+def pion_correlator(dims, psi, src):
+    corr = np.zeros(dims[3])
+    lib().wdref_pion_correlator(_dims(dims), _p(_c128(psi)), _dims(src), _p(corr))
+    return corr
