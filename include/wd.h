@@ -270,6 +270,36 @@ wd_status wd_md_force(wd_ctx *c, double *F, const double *U, const double *phi, 
  * h, r: host pointers.  A failed solve rejects and returns its status. */
 wd_status hmc_trajectory(wd_ctx *c, double *U, const wd_hmc_params *h, wd_hmc_result *r);
 
+/* ---------------------------------------------------------------------- */
+/* Measurements on a configuration (Sec. 3: the program measures on the     */
+/* gauge configuration at the end of each trajectory; the observables are   */
+/* not named there -- reading: plaquette, Polyakov loop, pion correlator).   */
+/* ---------------------------------------------------------------------- */
+
+/* Polyakov loop (1/V3) sum_x (1/3) tr prod_{t=0}^{Lt-1} U_t(x, t) of the
+ * field U ([V][4][3][3], device; need not be the loaded one).  out: HOST
+ * [2] = {Re, Im}. */
+wd_status wd_polyakov(wd_ctx *c, const double *U, double *out);
+
+/* Point-source propagator of the loaded gauge field: column j = 3*spin +
+ * colour of psi ([12][V][4][3], device, full lattice) solves M psi_j = b_j,
+ * b_j = 1 at (src, spin, colour) and 0 elsewhere.  src: HOST int32[4]
+ * (x,y,z,t).  The 12 columns are one batched even-odd solve with parameters
+ * p (eo must be 1; NULL = defaults): Mhat^dag Mhat psi_e = Mhat^dag (b_e +
+ * kappa D_eo b_o), then psi_o = b_o + kappa D_oe psi_e; p->tol bounds the
+ * true residual of that normal equation.  st: HOST [12] or NULL.  Returns
+ * WD_ERR_NOCONV / WD_ERR_NAN as wd_cg_solve (psi then holds the best
+ * iterate); WD_ERR_ARG for a source outside the lattice. */
+wd_status wd_point_propagator(wd_ctx *c, double *psi, const int32_t src[4], double kappa,
+                              const wd_solver_params *p, wd_solver_stats *st);
+
+/* Pion (pseudoscalar, zero momentum) correlator of a point-source
+ * propagator psi ([12][V][4][3], device):  corr[dt] = sum over spatial x and
+ * all 144 spin-colour entries of |psi(x, (src_t + dt) mod Lt)|^2, i.e.
+ * tr S S^dag by gamma_5-hermiticity.  corr: HOST [Lt]; FP64 sums in a fixed
+ * order. */
+wd_status wd_pion_correlator(wd_ctx *c, double *corr, const double *psi, const int32_t src[4]);
+
 /* Index tables computed on the HOST from the definition above: nb [V][8]
  * (x+mu, x-mu for mu = 0..3), cb [V], par [V].  HOST pointers. */
 wd_status wd_index_tables(const int32_t dims[4], int32_t *nb, int32_t *cb, uint8_t *par);

@@ -92,6 +92,10 @@ _SIGS = {
     "wd_md_force": (C.c_int, [_P, _P, _P, _P, C.c_double, C.c_double, C.POINTER(wd_solver_params),
                               C.POINTER(C.c_int)]),
     "hmc_trajectory": (C.c_int, [_P, _P, C.POINTER(wd_hmc_params), C.POINTER(wd_hmc_result)]),
+    "wd_polyakov": (C.c_int, [_P, _P, C.POINTER(C.c_double)]),
+    "wd_point_propagator": (C.c_int, [_P, _P, _I32x4, C.c_double, C.POINTER(wd_solver_params),
+                                      C.POINTER(wd_solver_stats)]),
+    "wd_pion_correlator": (C.c_int, [_P, C.POINTER(C.c_double), _P, _I32x4]),
     "wd_last_error": (C.c_char_p, []),
     "wd_version": (C.c_char_p, []),
 }
@@ -391,6 +395,39 @@ def hmc_params(beta=5.6, kappa=0.156, tau=1.0, nsteps=50, seed=1, traj=0, force=
     return p
 
 
+def wd_polyakov(ctx, U):
+    """Complex Polyakov loop of U ([V][4][3][3] complex128 device tensor)."""
+    _c128(U, (4, 3, 3), "U")
+    out = (C.c_double * 2)()
+    _check(lib().wd_polyakov(ctx, _ptr(U), out))
+    return complex(out[0], out[1])
+
+
+def wd_point_propagator(ctx, psi, src, kappa, params=None, check=True):
+    """psi: complex128 [12, V, 4, 3] device tensor (written); returns
+    (status, stats list)."""
+    _c128(psi, (4, 3), "psi")
+    if psi.dim() != 4 or psi.shape[0] != 12:
+        raise ValueError("psi must be [12, V, 4, 3]")
+    p = params if params is not None else wd_solver_defaults()
+    st = (wd_solver_stats * 12)()
+    status = lib().wd_point_propagator(ctx, _ptr(psi), _dims(src), float(kappa), C.byref(p), st)
+    if check and status not in (WD_OK, WD_ERR_NOCONV, WD_ERR_NAN):
+        _check(status)
+    stats = [dict(iters=s.iters, iters_fp64=s.iters_fp64, reliable_updates=s.reliable_updates,
+                  true_resid=s.true_resid, seconds=s.seconds, status=s.status) for s in st]
+    return status, stats
+
+
+def wd_pion_correlator(ctx, psi, src, Lt):
+    _c128(psi, (4, 3), "psi")
+    if psi.dim() != 4 or psi.shape[0] != 12:
+        raise ValueError("psi must be [12, V, 4, 3]")
+    corr = (C.c_double * int(Lt))()
+    _check(lib().wd_pion_correlator(ctx, corr, _ptr(psi), _dims(src)))
+    return np.array(corr[:])
+
+
 def wd_last_error():
     return lib().wd_last_error().decode()
 
@@ -438,3 +475,18 @@ class Lattice:
 
     def cg_solve(self, x, phi, kappa, params=None, check=True):
         return wd_cg_solve(self.ctx, x, phi, kappa, params, check)
+
+    def polyakov(self, U):
+        if tuple(U.shape) != (self.V, 4, 3, 3):
+            raise ValueError(f"U has shape {tuple(U.shape)}, expected ({self.V}, 4, 3, 3)")
+        return wd_polyakov(self.ctx, U)
+
+    def point_propagator(self, psi, src, kappa, params=None, check=True):
+        if tuple(psi.shape) != (12, self.V, 4, 3):
+            raise ValueError(f"psi has shape {tuple(psi.shape)}, expected (12, {self.V}, 4, 3)")
+        return wd_point_propagator(self.ctx, psi, src, kappa, params, check)
+
+    def pion_correlator(self, psi, src):
+        if tuple(psi.shape) != (12, self.V, 4, 3):
+            raise ValueError(f"psi has shape {tuple(psi.shape)}, expected (12, {self.V}, 4, 3)")
+        return wd_pion_correlator(self.ctx, psi, src, self.dims[3])

@@ -1,0 +1,97 @@
+"""GPU parity of the measurements against the oracle: the Polyakov loop,
+the point-source propagator (the batched even-odd solve of the 12 columns
+with source reconstruction, against the oracle's full-lattice CG) for a
+source on an even and on an odd site, and the pion correlator."""
+import numpy as np
+import pytest
+
+import lattice_inputs as li
+from gpu_util import dev, host, note
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def wd():
+    from paper_1207_2223_amd import wd
+    wd.lib()
+    return wd
+
+
+@pytest.mark.parametrize("dims", [(4, 4, 4, 4), (8, 4, 4, 6)])
+def test_polyakov_matches_oracle(wd, oracle, dims):
+    U = li.random_su3_field(dims, 0.5, seed=93)
+    lat = wd.Lattice(dims)
+    p = lat.polyakov(dev(U))
+    ref = oracle.polyakov(dims, U)
+    note(f"polyakov {dims}: gpu {p:.12f} oracle {ref:.12f}")
+    assert abs(p - ref) <= 1e-13
+    assert abs(lat.polyakov(dev(li.unit_field(dims))) - 1.0) <= 1e-15
+    lat.close()
+
+
+@pytest.mark.parametrize("src", [(0, 0, 0, 0), (1, 2, 3, 1), (3, 0, 1, 5)])
+def test_point_propagator_and_correlator_match_oracle(wd, oracle, src):
+    """Sources on an even site (0,0,0,0: parity 0) and on odd sites (1,2,3,1)
+    and (3,0,1,5) (parity 1): both source reconstructions."""
+    import torch
+    dims = (4, 4, 4, 6)
+    kappa = 0.12
+    U = li.random_su3_field(dims, 0.4, seed=94)
+    lat = wd.Lattice(dims)
+    lat.gauge_load(dev(U), recon=12)
+    V = li.volume(dims)
+    psi = torch.empty((12, V, 4, 3), dtype=torch.complex128, device="cuda")
+    st, stats = lat.point_propagator(psi, src, kappa, wd.solver_params(tol=1e-13))
+    assert st == wd.WD_OK
+    ref, ost, _ = oracle.point_propagator(dims, U, kappa, src, tol=1e-13)
+    assert ost == 0
+    got = host(psi)
+    err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    corr = lat.pion_correlator(psi, src)
+    cref = oracle.pion_correlator(dims, got, src)
+    cref_o = oracle.pion_correlator(dims, ref, src)
+    note(f"propagator src {src}: rel err {err:.2e}, corr {np.round(corr[:3], 6)}")
+    assert err <= 1e-10
+    assert np.allclose(corr, cref, rtol=1e-13, atol=0)    # same propagator: summation order only
+    assert np.allclose(corr, cref_o, rtol=1e-9, atol=0)
+    lat.close()
+
+
+def test_mixed_precision_propagator(wd, oracle):
+    """The 12 columns in FP16 with FP64 reliable updates: the correlator
+    within 1e-8 of the oracle's, every column's even solve converged."""
+    import torch
+    dims = (8, 8, 8, 8)
+    src = (2, 5, 1, 3)
+    kappa = 0.13
+    U = li.random_su3_field(dims, 0.3, seed=95)
+    lat = wd.Lattice(dims)
+    lat.gauge_load(dev(U), recon=12)
+    psi = torch.empty((12, li.volume(dims), 4, 3), dtype=torch.complex128, device="cuda")
+    st, stats = lat.point_propagator(psi, src, kappa, wd.solver_params(prec=wd.WD_F16, tol=1e-10))
+    assert st == wd.WD_OK and all(s["status"] == wd.WD_OK for s in stats)
+    ref, _, _ = oracle.point_propagator(dims, U, kappa, src, tol=1e-12)
+    corr = lat.pion_correlator(psi, src)
+    cref = oracle.pion_correlator(dims, ref, src)
+    note(f"FP16 propagator 8^4: max rel corr err {np.max(np.abs(corr / cref - 1)):.2e}, "
+         f"iters {[s['iters'] for s in stats][:4]}")
+    assert np.allclose(corr, cref, rtol=1e-8, atol=0)
+    lat.close()
+
+
+def test_measurement_errors(wd):
+    import torch
+    dims = (4, 4, 4, 4)
+    lat = wd.Lattice(dims)
+    lat.gauge_load(dev(li.unit_field(dims)))
+    psi = torch.empty((12, 256, 4, 3), dtype=torch.complex128, device="cuda")
+    with pytest.raises(wd.WDError) as e:
+        lat.point_propagator(psi, (4, 0, 0, 0), 0.12)
+    assert e.value.status == wd.WD_ERR_ARG
+    with pytest.raises(wd.WDError) as e:
+        lat.point_propagator(psi, (0, 0, 0, 0), 0.12, wd.solver_params(eo=0))
+    assert e.value.status == wd.WD_ERR_ARG
+    with pytest.raises(ValueError):
+        lat.point_propagator(psi[:11], (0, 0, 0, 0), 0.12)
+    lat.close()
