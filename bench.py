@@ -18,6 +18,10 @@ Workloads (--workload):
       device-memory budget: a saturation pass (all requests at once) gives
       solves/s; passes at 0.5, 0.8 and 1.0 times the saturation request rate
       give p50/p99 latency.
+  c6_measure  The measurements on one configuration at the 32^3 x 64 shape
+      (the field of c3): point-source propagator (12 spin-colour columns in
+      one batched FP16 solve to 1e-10, source reconstruction), pion
+      correlator, plaquette and Polyakov loop; value in solves/s.
   c5_hmc  Two-flavour HMC on 16^3 x 32: Wilson plaquette action beta = 5.6,
       kappa = 0.156, leapfrog tau = 1 in 50 steps, mixed-precision force
       solves (tol 1e-8), FP64 Hamiltonian solves (1e-10).  From a cold start,
@@ -53,6 +57,7 @@ WORKLOADS = {
                        eps=0.5, kappa=(0.14, 0.157), nrhs=(1, 8), cfg=3, max_slots=8,
                        budget_gib=6.0, requests=100, loads=(0.5, 0.8, 1.0)),
     "c5_hmc": dict(dims=(16, 16, 16, 32), beta=5.6, kappa=0.156, tau=1.0, nsteps=50, cfg=4),
+    "c6_measure": dict(dims=(32, 32, 32, 64), eps=0.5, kappa=0.156, cfg=2, src=(0, 0, 0, 0)),
 }
 PRECS = {"f64": 0, "f32": 1, "f16": 2, "f16l16": 2 | 0x10, "f32l16": 1 | 0x10,
          "f16r18": 2 | 0x20, "f32r18": 1 | 0x20}
@@ -619,6 +624,95 @@ def bench_hmc(args, wd, torch):
     return out
 
 
+# ---------------------------------------------------------------------------
+# c6: measurements on a configuration
+# ---------------------------------------------------------------------------
+
+def bench_measure(args, wd, torch):
+    import lattice_inputs as li
+    w = WORKLOADS["c6_measure"]
+    dims, kappa, src = w["dims"], w["kappa"], w["src"]
+    t = time.time()
+    U = li.random_su3_field(dims, w["eps"], seed=li.config_seed(w["cfg"]))
+    log(f"[bench] field {dims} generated in {time.time() - t:.1f}s")
+    Ud = torch.from_numpy(U).to("cuda")
+    lat = wd.Lattice(dims)
+    lat.gauge_load(Ud, recon=12)
+    V = li.volume(dims)
+    psi = torch.empty((12, V, 4, 3), dtype=torch.complex128, device="cuda")
+    params = wd.solver_params(prec=PRECS[args.prec], eo=1, tol=1e-10, tuned=args.tuned)
+    if args.tuned:
+        for code in {PRECS[args.prec], 0}:
+            wd.wd_tune(lat.ctx, 12, code)
+
+    def measure(p):
+        st, stats = lat.point_propagator(psi, src, kappa, p)
+        corr = lat.pion_correlator(psi, src)
+        return st, stats, corr, lat.plaquette(Ud), lat.polyakov(Ud)
+
+    for k in range(args.warmup):
+        st, stats, corr, plaq, poly = measure(params)
+        log(f"[bench] warmup {k}: status {st} iters {stats[0]['iters']}")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ok = True
+    for k in range(args.steps):
+        ts = time.perf_counter()
+        st, stats, corr, plaq, poly = measure(params)
+        ok &= st == wd.WD_OK
+        log(f"[bench] step {k}: {(time.perf_counter() - ts) * 1e3:.1f} ms, status {st}, "
+            f"iters {max(s['iters'] for s in stats)}")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    value = 12 * args.steps / elapsed
+    report, t_inst = instrumented(wd, torch, lat.ctx, lambda: measure(params))
+    dom, roof, sten = kernel_roofline(report, t_inst)
+    roof["traffic"] = counter_traffic("c3_32c64_12rhs", args.prec, dom["name"])  # the same solve's kernels
+    meff = [float(np.log(corr[i] / corr[i + 1])) for i in range(min(12, len(corr) - 1))]
+
+    fp64 = None
+    if not args.no_fp64 and args.prec != "f64":
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        st64, s64, c64, _, _ = measure(wd.solver_params(prec=0, eo=1, tol=1e-10, tuned=args.tuned))
+        torch.cuda.synchronize()
+        t64 = time.perf_counter() - ts
+        fp64 = {"solves_per_s": 12 / t64, "iters": max(s["iters"] for s in s64),
+                "corr_max_rel_diff": float(np.max(np.abs(corr / c64 - 1)))}
+        log(f"[bench] fp64 measurement: {t64 * 1e3:.1f} ms, correlators differ by {fp64['corr_max_rel_diff']:.1e}")
+
+    cpu = None
+    if not args.no_cpu:
+        iters = fp64["iters"] if fp64 else max(s["iters"] for s in stats)
+        t_apply, n = oracle_apply_seconds(U, dims, kappa, args.cpu_seconds)
+        cpu = {"value": 1.0 / (t_apply * iters), "unit": "solves/s", "cores": oracle_cores(), "kind": "oracle",
+               "sample": (f"extrapolated: {n} oracle Mhat^dag Mhat applications on {dims} ({t_apply:.3f} s each) "
+                          f"times {iters} CG iterations per column (the oracle's own propagator runs CG on the "
+                          f"full normal equations, slower still)")}
+    lat.close()
+    out = base_record(args, value, "solves/s", elapsed / args.steps * 1e3, DTYPE[args.prec],
+                      {"workload": (f"c6_measure: {'x'.join(map(str, dims))} lattice (eps {w['eps']}), kappa {kappa}, "
+                                    f"point source {src}: 12 columns solved together to 1e-10, pion correlator, "
+                                    f"plaquette, Polyakov loop"),
+                       "prec_sloppy": args.prec, "lattice": list(dims)})
+    out.update({
+        "converged": bool(ok),
+        "configs_per_hour": 3600.0 * args.steps / elapsed,
+        "plaquette": plaq,
+        "polyakov": [poly.real, poly.imag],
+        "pion_correlator": [float(c) for c in corr],
+        "effective_mass": meff,
+        "latency_ms": {"p50": elapsed / args.steps * 1e3, "p99": elapsed / args.steps * 1e3},
+        "stencil": sten,
+        "dominant_kernel": dom,
+        "roofline": roof,
+        "fp64": fp64,
+        "mixed_vs_fp64": (value / fp64["solves_per_s"]) if fp64 else None,
+        "cpu_baseline": cpu,
+    })
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -632,6 +726,8 @@ def main():
         out = bench_serving(args, wd, torch)
     elif args.workload == "c5_hmc":
         out = bench_hmc(args, wd, torch)
+    elif args.workload == "c6_measure":
+        out = bench_measure(args, wd, torch)
     else:
         out = bench_solve(args, wd, torch)
     if out is not None:

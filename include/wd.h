@@ -276,6 +276,10 @@ wd_status hmc_trajectory(wd_ctx *c, double *U, const wd_hmc_params *h, wd_hmc_re
 /* not named there -- reading: plaquette, Polyakov loop, pion correlator).   */
 /* ---------------------------------------------------------------------- */
 
+/* Average plaquette (1/(6V)) sum_{x, mu<nu} (1/3) Re tr U_munu(x) of the
+ * field U ([V][4][3][3], device); *plaq: HOST.  FP64, fixed-order sums. */
+wd_status wd_plaquette(wd_ctx *c, const double *U, double *plaq);
+
 /* Polyakov loop (1/V3) sum_x (1/3) tr prod_{t=0}^{Lt-1} U_t(x, t) of the
  * field U ([V][4][3][3], device; need not be the loaded one).  out: HOST
  * [2] = {Re, Im}. */

@@ -584,6 +584,19 @@ void wd_hmc_defaults(wd_hmc_params *h)
     h->metropolis = 1;
 }
 
+wd_status wd_plaquette(wd_ctx *c, const double *U, double *plaq)
+{
+    if (!c || !U || !plaq) return set_error(WD_ERR_ARG, "NULL argument");
+    WD_HIP(hipSetDevice(c->device));
+    HmcWs w{};  // only the reduction buffers
+    void *p;
+    WD_TRY(ws_get(c, "pl_partial", sizeof(double) * ((size_t)c->V / 16 + 64), &p));
+    w.partial = (double *)p;
+    WD_TRY(ws_get(c, "pl_scal", sizeof(double) * 16, &p));
+    w.scal = (double *)p;
+    return plaquette_host(c, w, U, plaq);
+}
+
 wd_status wd_hmc_draw(wd_ctx *c, double *P, double *chi, uint64_t seed, uint32_t traj)
 {
     if (!c || !P || !chi) return set_error(WD_ERR_ARG, "NULL argument");

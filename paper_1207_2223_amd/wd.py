@@ -92,6 +92,7 @@ _SIGS = {
     "wd_md_force": (C.c_int, [_P, _P, _P, _P, C.c_double, C.c_double, C.POINTER(wd_solver_params),
                               C.POINTER(C.c_int)]),
     "hmc_trajectory": (C.c_int, [_P, _P, C.POINTER(wd_hmc_params), C.POINTER(wd_hmc_result)]),
+    "wd_plaquette": (C.c_int, [_P, _P, C.POINTER(C.c_double)]),
     "wd_polyakov": (C.c_int, [_P, _P, C.POINTER(C.c_double)]),
     "wd_point_propagator": (C.c_int, [_P, _P, _I32x4, C.c_double, C.POINTER(wd_solver_params),
                                       C.POINTER(wd_solver_stats)]),
@@ -395,6 +396,13 @@ def hmc_params(beta=5.6, kappa=0.156, tau=1.0, nsteps=50, seed=1, traj=0, force=
     return p
 
 
+def wd_plaquette(ctx, U):
+    _c128(U, (4, 3, 3), "U")
+    out = C.c_double(0)
+    _check(lib().wd_plaquette(ctx, _ptr(U), C.byref(out)))
+    return out.value
+
+
 def wd_polyakov(ctx, U):
     """Complex Polyakov loop of U ([V][4][3][3] complex128 device tensor)."""
     _c128(U, (4, 3, 3), "U")
@@ -475,6 +483,11 @@ class Lattice:
 
     def cg_solve(self, x, phi, kappa, params=None, check=True):
         return wd_cg_solve(self.ctx, x, phi, kappa, params, check)
+
+    def plaquette(self, U):
+        if tuple(U.shape) != (self.V, 4, 3, 3):
+            raise ValueError(f"U has shape {tuple(U.shape)}, expected ({self.V}, 4, 3, 3)")
+        return wd_plaquette(self.ctx, U)
 
     def polyakov(self, U):
         if tuple(U.shape) != (self.V, 4, 3, 3):

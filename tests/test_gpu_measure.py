@@ -22,6 +22,8 @@ def wd():
 def test_polyakov_matches_oracle(wd, oracle, dims):
     U = li.random_su3_field(dims, 0.5, seed=93)
     lat = wd.Lattice(dims)
+    pl = lat.plaquette(dev(U))
+    assert abs(pl - oracle.plaquette(dims, U)) <= 1e-14
     p = lat.polyakov(dev(U))
     ref = oracle.polyakov(dims, U)
     note(f"polyakov {dims}: gpu {p:.12f} oracle {ref:.12f}")
