@@ -60,10 +60,15 @@ typedef enum {
     WD_ERR_STATE = -7   /* call out of order (e.g. no gauge field loaded)      */
 } wd_status;
 
-typedef enum { WD_F64 = 0, WD_F32 = 1, WD_F16 = 2 } wd_prec;
-/* Or-ed into a WD_F32 / WD_F16 precision code: the sloppy operator reads
- * FP16 12-real links (WD_LINKS_F16) or FP32 links with all 18 reals
- * (WD_LINKS_R18, no reconstruction) instead of FP32 12-real links. */
+/* Sloppy spinor formats: FP64, FP32, FP16 with a per-site FP32 norm, and
+ * int16 fixed point with a per-site FP32 norm (q = rint(v * 32767 / n), n =
+ * max |v| over the site's 24 reals; 52 bytes per site like FP16; FP32
+ * arithmetic; 12-real FP32 or FP16 links). */
+typedef enum { WD_F64 = 0, WD_F32 = 1, WD_F16 = 2, WD_I16 = 3 } wd_prec;
+/* Or-ed into a WD_F32 / WD_F16 / WD_I16 precision code: the sloppy operator
+ * reads FP16 12-real links (WD_LINKS_F16) or FP32 links with all 18 reals
+ * (WD_LINKS_R18, no reconstruction; not with WD_I16) instead of FP32 12-real
+ * links. */
 #define WD_LINKS_F16 0x10
 #define WD_LINKS_R18 0x20
 typedef enum { WD_FULL = 0, WD_EVEN = 1, WD_ODD = 2 } wd_parity;

@@ -312,6 +312,7 @@ inline dim3 grid_of(int Vh, int nsub, int nact) { return dim3((nsub * Vh + kBloc
     case SP_F64: F(SP_F64); break;                                                                \
     case SP_F32: F(SP_F32); break;                                                                \
     case SP_F16: F(SP_F16); break;                                                                \
+    case SP_I16: F(SP_I16); break;                                                                \
     default: return hipErrorInvalidValue;                                                         \
     }
 
@@ -348,6 +349,8 @@ hipError_t blas_cg_update(const Field &x, const Field &p, const Field &r, const 
         hipLaunchKernelGGL((k_cg_update<SP_F32, SP_F32>), gr, dim3(kBlock), 0, s, fa(x), fa(p), fa(r), fa(Ap), alpha, Vh, p.nsub, active, partial, pstride);
     else if (p.sp == SP_F16 && x.sp == SP_F32)
         hipLaunchKernelGGL((k_cg_update<SP_F16, SP_F32>), gr, dim3(kBlock), 0, s, fa(x), fa(p), fa(r), fa(Ap), alpha, Vh, p.nsub, active, partial, pstride);
+    else if (p.sp == SP_I16 && x.sp == SP_F32)
+        hipLaunchKernelGGL((k_cg_update<SP_I16, SP_F32>), gr, dim3(kBlock), 0, s, fa(x), fa(p), fa(r), fa(Ap), alpha, Vh, p.nsub, active, partial, pstride);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
@@ -366,6 +369,7 @@ hipError_t blas_copy(const Field &dst, const Field &src, int Vh, const int *acti
     C2(SP_F64, SP_F64) C2(SP_F64, SP_F32) C2(SP_F64, SP_F16)
     C2(SP_F32, SP_F64) C2(SP_F32, SP_F32) C2(SP_F32, SP_F16)
     C2(SP_F16, SP_F64) C2(SP_F16, SP_F32) C2(SP_F16, SP_F16)
+    C2(SP_F64, SP_I16) C2(SP_F32, SP_I16) C2(SP_I16, SP_F64) C2(SP_I16, SP_F32) C2(SP_I16, SP_I16)
 #undef C2
     return hipErrorInvalidValue;
 }

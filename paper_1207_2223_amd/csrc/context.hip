@@ -89,10 +89,10 @@ wd_status decode_prec(const wd_ctx *c, int prec, int *sp, int *lk, int *xp)
 {
     const int base = prec & 0xf;
     const bool l16 = (prec & WD_LINKS_F16) != 0, r18 = (prec & WD_LINKS_R18) != 0;
-    if ((prec & ~(0xf | WD_LINKS_F16 | WD_LINKS_R18)) || base > WD_F16 || (base == WD_F64 && (l16 || r18)) ||
-        (l16 && r18))
+    if ((prec & ~(0xf | WD_LINKS_F16 | WD_LINKS_R18)) || base > WD_I16 || (base == WD_F64 && (l16 || r18)) ||
+        (l16 && r18) || (base == WD_I16 && r18))
         return set_error(WD_ERR_ARG, "bad precision code 0x%x", prec);
-    *sp = base == WD_F64 ? SP_F64 : (base == WD_F32 ? SP_F32 : SP_F16);
+    *sp = base == WD_F64 ? SP_F64 : (base == WD_F32 ? SP_F32 : (base == WD_F16 ? SP_F16 : SP_I16));
     *lk = *sp == SP_F64 ? c->lk64 : (l16 ? LK_F16_12 : (r18 ? LK_F32_18 : LK_F32_12));
     *xp = *sp == SP_F64 ? SP_F64 : SP_F32;
     return WD_OK;

@@ -9,6 +9,8 @@ hipError_t dslash_launch_f32_d0(const DslashArgs &a, int lk, int nr, int rl, int
 hipError_t dslash_launch_f32_d1(const DslashArgs &a, int lk, int nr, int rl, int epi, int block, int grid, hipStream_t s);
 hipError_t dslash_launch_f16_d0(const DslashArgs &a, int lk, int nr, int rl, int epi, int block, int grid, hipStream_t s);
 hipError_t dslash_launch_f16_d1(const DslashArgs &a, int lk, int nr, int rl, int epi, int block, int grid, hipStream_t s);
+hipError_t dslash_launch_i16_d0(const DslashArgs &a, int lk, int nr, int rl, int epi, int block, int grid, hipStream_t s);
+hipError_t dslash_launch_i16_d1(const DslashArgs &a, int lk, int nr, int rl, int epi, int block, int grid, hipStream_t s);
 
 hipError_t dslash_launch(const DslashArgs &a, int sp, int lk, int nr, int rl, int dag, int epi, int block,
                          int grid, hipStream_t s)
@@ -19,6 +21,8 @@ hipError_t dslash_launch(const DslashArgs &a, int sp, int lk, int nr, int rl, in
                          : dslash_launch_f32_d0(a, lk, nr, rl, epi, block, grid, s);
     if (sp == SP_F16) return dag ? dslash_launch_f16_d1(a, lk, nr, rl, epi, block, grid, s)
                          : dslash_launch_f16_d0(a, lk, nr, rl, epi, block, grid, s);
+    if (sp == SP_I16) return dag ? dslash_launch_i16_d1(a, lk, nr, rl, epi, block, grid, s)
+                         : dslash_launch_i16_d0(a, lk, nr, rl, epi, block, grid, s);
     return hipErrorInvalidValue;
 }
 

@@ -41,6 +41,15 @@ __device__ __forceinline__ real load_nb(const char *f, int cs, int j, real v[24]
             for (int q = 0; q < 8; q++) v[8 * k + q] = (real)(float)w[q];
         }
         return (real)reinterpret_cast<const float *>(f + (size_t)48 * cs)[j];
+    } else if constexpr (SP == SP_I16) {
+        const short8_t *p = reinterpret_cast<const short8_t *>(f);
+#pragma unroll
+        for (int k = 0; k < 3; k++) {
+            short8_t w = p[(size_t)k * cs + j];
+#pragma unroll
+            for (int q = 0; q < 8; q++) v[8 * k + q] = (real)(float)w[q];
+        }
+        return (real)SpinorIO<SP_I16>::step(reinterpret_cast<const float *>(f + (size_t)48 * cs)[j]);
     } else {
         SpinorIO<SP>::load(f, cs, j, v);
         return (real)1;
@@ -65,7 +74,7 @@ __device__ __forceinline__ void hop_dir(const DslashArgs &a, int i, const int c[
             const real sc = load_nb<SP>(a.in + rid[r] * a.in_rs, cs, j, v);
             project<MU, SF>(v, h);
             su3_mul_half<false>(u, h, w);
-            if constexpr (SP == SP_F16)
+            if constexpr (has_norm(SP))
                 accumulate_scaled<MU, SF>(acc[r], w, sc);
             else
                 accumulate<MU, SF>(acc[r], w);
@@ -81,7 +90,7 @@ __device__ __forceinline__ void hop_dir(const DslashArgs &a, int i, const int c[
             const real sc = load_nb<SP>(a.in + rid[r] * a.in_rs, cs, j, v);
             project<MU, SB>(v, h);
             su3_mul_half<true>(u, h, w);
-            if constexpr (SP == SP_F16)
+            if constexpr (has_norm(SP))
                 accumulate_scaled<MU, SB>(acc[r], w, sc);
             else
                 accumulate<MU, SB>(acc[r], w);

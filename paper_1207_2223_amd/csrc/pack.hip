@@ -162,6 +162,7 @@ hipError_t pack_spinor(const double *src, const Field &dst, int nrhs, int mode, 
     case SP_F64: hipLaunchKernelGGL(k_pack_spinor<SP_F64>, gr, dim3(kBlock), 0, s, src, dst.base, dst.rs, dst.ss, g, mode); break;
     case SP_F32: hipLaunchKernelGGL(k_pack_spinor<SP_F32>, gr, dim3(kBlock), 0, s, src, dst.base, dst.rs, dst.ss, g, mode); break;
     case SP_F16: hipLaunchKernelGGL(k_pack_spinor<SP_F16>, gr, dim3(kBlock), 0, s, src, dst.base, dst.rs, dst.ss, g, mode); break;
+    case SP_I16: hipLaunchKernelGGL(k_pack_spinor<SP_I16>, gr, dim3(kBlock), 0, s, src, dst.base, dst.rs, dst.ss, g, mode); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -177,6 +178,7 @@ hipError_t unpack_spinor(const Field &src, double *dst, int nrhs, int mode, cons
     case SP_F64: hipLaunchKernelGGL(k_unpack_spinor<SP_F64>, gr, dim3(kBlock), 0, s, src.base, src.rs, src.ss, dst, g, mode); break;
     case SP_F32: hipLaunchKernelGGL(k_unpack_spinor<SP_F32>, gr, dim3(kBlock), 0, s, src.base, src.rs, src.ss, dst, g, mode); break;
     case SP_F16: hipLaunchKernelGGL(k_unpack_spinor<SP_F16>, gr, dim3(kBlock), 0, s, src.base, src.rs, src.ss, dst, g, mode); break;
+    case SP_I16: hipLaunchKernelGGL(k_unpack_spinor<SP_I16>, gr, dim3(kBlock), 0, s, src.base, src.rs, src.ss, dst, g, mode); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -59,7 +59,9 @@ hipError_t fill(const Field &f, int Vh, int nrhs, unsigned seed, hipStream_t s)
     switch (f.sp) {
     case SP_F64: hipLaunchKernelGGL(k_fill<SP_F64>, gr, dim3(kBlock), 0, s, f.base, f.rs, Vh, f.cs, nrhs, seed); break;
     case SP_F32: hipLaunchKernelGGL(k_fill<SP_F32>, gr, dim3(kBlock), 0, s, f.base, f.rs, Vh, f.cs, nrhs, seed); break;
-    default: hipLaunchKernelGGL(k_fill<SP_F16>, gr, dim3(kBlock), 0, s, f.base, f.rs, Vh, f.cs, nrhs, seed); break;
+    case SP_F16: hipLaunchKernelGGL(k_fill<SP_F16>, gr, dim3(kBlock), 0, s, f.base, f.rs, Vh, f.cs, nrhs, seed); break;
+    case SP_I16: hipLaunchKernelGGL(k_fill<SP_I16>, gr, dim3(kBlock), 0, s, f.base, f.rs, Vh, f.cs, nrhs, seed); break;
+    default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }

@@ -23,7 +23,10 @@
 
 namespace wd {
 
-enum { SP_F64 = 0, SP_F32 = 1, SP_F16 = 2 };
+enum { SP_F64 = 0, SP_F32 = 1, SP_F16 = 2, SP_I16 = 3 };
+
+// Formats that store a per-site FP32 norm next to 16-bit values.
+__host__ __device__ constexpr bool has_norm(int sp) { return sp == SP_F16 || sp == SP_I16; }
 enum { LK_F64_18 = 0, LK_F64_12 = 1, LK_F32_12 = 2, LK_F16_12 = 3, LK_F32_18 = 4 };
 
 typedef _Float16 half8_t __attribute__((ext_vector_type(8)));
@@ -237,6 +240,51 @@ template <> struct SpinorIO<SP_F16> {
 #pragma unroll
             for (int j = 0; j < 4; j++)
                 w[j] = cvt_pk_f16((float)v[8 * k + 2 * j] * inv, (float)v[8 * k + 2 * j + 1] * inv);
+            st_hint<NT>(p + (size_t)k * cs + i, w);
+        }
+        st_hint<NT>(reinterpret_cast<float *>(f + (size_t)48 * cs) + i, m);
+    }
+};
+
+// int16 fixed point with a per-site FP32 norm n = max |v| over the 24 reals:
+// stored q = rint(v * (32767 / n)) in [-32767, 32767], read back as
+// q * (n / 32767); a zero site stores n = 0.  Same 52 bytes per site as FP16,
+// uniform absolute precision n / 65534 instead of FP16's relative 2^-11.
+typedef short short8_t __attribute__((ext_vector_type(8)));
+
+template <> struct SpinorIO<SP_I16> {
+    typedef float real;
+    static constexpr size_t site_bytes = 52;
+    __device__ static __forceinline__ float step(float n) { return n / 32767.0f; }
+    template <bool NT = false, typename T>
+    __device__ static __forceinline__ void load(const char *f, int cs, int i, T v[24])
+    {
+        const short8_t *p = reinterpret_cast<const short8_t *>(f);
+        const float sc = step(ld_hint<NT>(reinterpret_cast<const float *>(f + (size_t)48 * cs) + i));
+#pragma unroll
+        for (int k = 0; k < 3; k++) {
+            const short8_t w = ld_hint<NT>(p + (size_t)k * cs + i);
+#pragma unroll
+            for (int j = 0; j < 8; j++) v[8 * k + j] = (T)((float)w[j] * sc);
+        }
+    }
+    template <bool NT = false, typename T>
+    __device__ static __forceinline__ void store(char *f, int cs, int i, const T v[24])
+    {
+        float m = 0.f;
+#pragma unroll
+        for (int j = 0; j < 24; j++) m = fmaxf(m, fabsf((float)v[j]));
+        const float inv = (m > 0.f) ? 32767.0f / m : 0.f;
+        u32x4_t *p = reinterpret_cast<u32x4_t *>(f);
+#pragma unroll
+        for (int k = 0; k < 3; k++) {
+            u32x4_t w;
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                const int q0 = min(32767, max(-32767, (int)rintf((float)v[8 * k + 2 * j] * inv)));
+                const int q1 = min(32767, max(-32767, (int)rintf((float)v[8 * k + 2 * j + 1] * inv)));
+                w[j] = ((unsigned)q0 & 0xffffu) | ((unsigned)q1 << 16);
+            }
             st_hint<NT>(p + (size_t)k * cs + i, w);
         }
         st_hint<NT>(reinterpret_cast<float *>(f + (size_t)48 * cs) + i, m);

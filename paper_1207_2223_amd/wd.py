@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(_HERE, "libwd.so")
 
 WD_OK, WD_ERR_ARG, WD_ERR_DIMS, WD_ERR_OOM, WD_ERR_HIP, WD_ERR_NOCONV, WD_ERR_NAN, WD_ERR_STATE = (
     0, -1, -2, -3, -4, -5, -6, -7)
-WD_F64, WD_F32, WD_F16 = 0, 1, 2
+WD_F64, WD_F32, WD_F16, WD_I16 = 0, 1, 2, 3
 WD_LINKS_F16 = 0x10
 WD_LINKS_R18 = 0x20
 WD_FULL, WD_EVEN, WD_ODD = 0, 1, 2

@@ -44,11 +44,12 @@ def test_full_lattice_fp64_4444(wd, oracle):
     lat.close()
 
 
-@pytest.mark.parametrize("prec", ["F64", "F32", "F16", "F16L", "F16R"])
+@pytest.mark.parametrize("prec", ["F64", "F32", "F16", "F16L", "F16R", "I16", "I16L"])
 @pytest.mark.parametrize("dims", [(8, 8, 8, 8), (6, 4, 4, 6)])
 def test_even_odd_solves(wd, oracle, prec, dims):
     code = {"F64": wd.WD_F64, "F32": wd.WD_F32, "F16": wd.WD_F16,
-            "F16L": wd.WD_F16 | wd.WD_LINKS_F16, "F16R": wd.WD_F16 | wd.WD_LINKS_R18}[prec]
+            "F16L": wd.WD_F16 | wd.WD_LINKS_F16, "F16R": wd.WD_F16 | wd.WD_LINKS_R18,
+            "I16": wd.WD_I16, "I16L": wd.WD_I16 | wd.WD_LINKS_F16}[prec]
     V = li.volume(dims)
     kappa = 0.155
     U = li.random_su3_field(dims, 0.5, seed=li.config_seed(1))
@@ -66,10 +67,10 @@ def test_even_odd_solves(wd, oracle, prec, dims):
     lat.close()
 
 
-@pytest.mark.parametrize("prec", ["F64", "F16"])
+@pytest.mark.parametrize("prec", ["F64", "F16", "I16"])
 def test_multi_rhs_equals_single(wd, prec):
     dims = (6, 4, 4, 6)
-    code = {"F64": wd.WD_F64, "F16": wd.WD_F16}[prec]
+    code = {"F64": wd.WD_F64, "F16": wd.WD_F16, "I16": wd.WD_I16}[prec]
     V = li.volume(dims)
     U = li.random_su3_field(dims, 0.5, seed=21)
     B = li.gaussian_spinor(V // 2, seed=22, nrhs=3)

@@ -71,12 +71,16 @@ def test_dslash_fp64_full_lattice(wd, oracle, dims):
 
 
 @pytest.mark.parametrize("prec,tol", [("F32", 2e-6), ("F16", 4e-3), ("F16L", 5e-3), ("F32L", 2e-3),
-                                      ("F32R", 2e-6), ("F16R", 4e-3)])
+                                      ("F32R", 2e-6), ("F16R", 4e-3), ("I16", 2e-4), ("I16L", 3e-3)])
 def test_dslash_sloppy_precisions(wd, oracle, prec, tol):
+    """I16 (int16 fixed point, per-site norm): quantisation step n/32767 per
+    component, so about 1e-5 relative on Gaussian spinors -- well below
+    FP16's 2^-11 relative rounding -- plus the FP32 link rounding."""
     dims = (6, 4, 4, 6)
     code = {"F32": wd.WD_F32, "F16": wd.WD_F16, "F16L": wd.WD_F16 | wd.WD_LINKS_F16,
             "F32L": wd.WD_F32 | wd.WD_LINKS_F16, "F32R": wd.WD_F32 | wd.WD_LINKS_R18,
-            "F16R": wd.WD_F16 | wd.WD_LINKS_R18}[prec]
+            "F16R": wd.WD_F16 | wd.WD_LINKS_R18, "I16": wd.WD_I16,
+            "I16L": wd.WD_I16 | wd.WD_LINKS_F16}[prec]
     V = li.volume(dims)
     U = li.random_su3_field(dims, 0.5, seed=5)
     lat = wd.Lattice(dims)
@@ -142,4 +146,10 @@ def test_errors(wd):
     with pytest.raises(wd.WDError) as e:
         lat.dslash(x, x.clone(), wd.WD_EVEN)
     assert e.value.status == wd.WD_ERR_STATE
+    lat.gauge_load(dev(li.unit_field((4, 4, 4, 4))))
+    # precision codes outside the formats: unknown base, int16 with 18-real links, two link flags
+    for code in (4, wd.WD_I16 | wd.WD_LINKS_R18, wd.WD_F16 | wd.WD_LINKS_F16 | wd.WD_LINKS_R18):
+        with pytest.raises(wd.WDError) as e:
+            lat.dslash(x, x.clone(), wd.WD_EVEN, 0, code)
+        assert e.value.status == wd.WD_ERR_ARG
     lat.close()

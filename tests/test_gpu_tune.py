@@ -42,7 +42,7 @@ def _expected_candidates(dims, code, nrhs):
     return n
 
 
-@pytest.mark.parametrize("prec", ["F64", "F32", "F16", "F16L", "F16R"])
+@pytest.mark.parametrize("prec", ["F64", "F32", "F16", "F16L", "F16R", "I16"])
 @pytest.mark.parametrize("dims", [(6, 4, 4, 6), (16, 8, 8, 4), (16, 16, 8, 4), (8, 8, 4, 8)])
 def test_tuner_all_shapes_bitwise_and_tuned_solve_identical(wd, oracle, prec, dims):
     """(6,4,4,6): Vh = 288, a ragged last tile for every block size;
@@ -51,7 +51,8 @@ def test_tuner_all_shapes_bitwise_and_tuned_solve_identical(wd, oracle, prec, di
     y-stripes is a candidate too; (8,8,4,8): Lt divisible by 8, so the
     t-slab orders are candidates."""
     code = {"F64": wd.WD_F64, "F32": wd.WD_F32, "F16": wd.WD_F16,
-            "F16L": wd.WD_F16 | wd.WD_LINKS_F16, "F16R": wd.WD_F16 | wd.WD_LINKS_R18}[prec]
+            "F16L": wd.WD_F16 | wd.WD_LINKS_F16, "F16R": wd.WD_F16 | wd.WD_LINKS_R18,
+            "I16": wd.WD_I16}[prec]
     V = li.volume(dims)
     U = li.random_su3_field(dims, 0.5, seed=41)
     lat = wd.Lattice(dims)
