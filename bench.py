@@ -120,6 +120,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--tuned", type=int, default=1, help="autotune launch shapes before timing")
     ap.add_argument("--requests", type=int, default=None, help="c4: requests per pass")
+    ap.add_argument("--chrono", type=int, default=1, choices=(0, 1, 2),
+                    help="c5: force-solve starting vectors (0 zero, 1 previous, 2 extrapolated)")
     ap.add_argument("--tune-only", action="store_true",
                     help="autotune (filling WD_TUNE_CACHE when set) and exit")
     ap.add_argument("--copy-probe", action="store_true",
@@ -543,7 +545,7 @@ def bench_hmc(args, wd, torch):
     def traj(i, fparams, metropolis=True):
         h = wd.hmc_params(beta=w["beta"], kappa=w["kappa"], tau=w["tau"], nsteps=w["nsteps"],
                           seed=li.config_seed(w["cfg"]), traj=i, force=fparams, h=hsol,
-                          metropolis=metropolis)
+                          metropolis=metropolis, chrono=args.chrono)
         return wd.hmc_trajectory(lat.ctx, Ud, h)
 
     # thermalisation: molecular-dynamics trajectories (every proposal taken)
@@ -603,7 +605,8 @@ def bench_hmc(args, wd, torch):
     out = base_record(args, value, "traj/h", elapsed / args.steps * 1e3, DTYPE[args.prec],
                       {"workload": (f"c5_hmc: {'x'.join(map(str, dims))} lattice, beta {w['beta']}, kappa {w['kappa']}, "
                                     f"leapfrog tau {w['tau']} in {w['nsteps']} steps, force solves {args.prec} tol 1e-8, "
-                                    f"H solves FP64 1e-10, cold start, {args.warmup} MD thermalisation trajectories"),
+                                    f"H solves FP64 1e-10, cold start, {args.warmup} MD thermalisation trajectories, "
+                                    f"force-solve starting vectors {['zero', 'previous', 'extrapolated'][args.chrono]}"),
                        "prec_sloppy": args.prec, "lattice": list(dims)})
     out.update({
         "acceptance": acc,

@@ -91,6 +91,8 @@ typedef struct {
     int graphs;       /* 1: run the poll iterations of a step as one captured HIP   */
                       /* graph, replayed while the active set is unchanged; 0:    */
                       /* launch each kernel (same results bit for bit)            */
+    int initial_guess; /* wd_cg_solve: 1: x holds the starting vectors on entry  */
+                      /* (r0 = b - A x in FP64); 0: x0 = 0 (x is output only)     */
 } wd_solver_params;
 
 /* Per right-hand-side solver statistics. */
@@ -106,7 +108,7 @@ typedef struct {
 } wd_solver_stats;
 
 /* Fill p with the defaults: tol 1e-10, maxiter 20000, FP64, eo 1, delta 0.1,
- * poll 8, tuned 0, graphs 1.  p: host pointer. */
+ * poll 8, tuned 0, graphs 1, initial_guess 0.  p: host pointer. */
 void wd_solver_defaults(wd_solver_params *p);
 
 /* Create a context for one lattice on HIP device `device`, issuing work on
@@ -230,6 +232,12 @@ typedef struct {
     int metropolis;                /* 1: accept iff u < exp(-dH); 0: accept every    */
                                    /* proposal (molecular-dynamics trajectories for  */
                                    /* thermalisation; dH is still computed)          */
+    int chrono;                    /* force-solve starting vectors within a          */
+                                   /* trajectory: 0 zero; 1 the previous MD step's   */
+                                   /* solution; 2 the linear extrapolation 2x1 - x2  */
+                                   /* of the last two (the first solves from zero /  */
+                                   /* the previous one).  With 1 or 2 the MD is      */
+                                   /* reversible to the force-solve tolerance only   */
 } wd_hmc_params;
 
 typedef struct {

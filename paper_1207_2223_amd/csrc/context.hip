@@ -264,6 +264,7 @@ void wd_solver_defaults(wd_solver_params *p)
     p->poll = 8;
     p->tuned = 0;
     p->graphs = 1;
+    p->initial_guess = 0;
 }
 
 static wd_status check_dims(const int32_t *dims, long long *V)

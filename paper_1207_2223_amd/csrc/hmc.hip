@@ -308,6 +308,16 @@ __global__ void __launch_bounds__(kB) k_fermion_force(const double *U, const dou
 }
 
 // P -= eps F
+// x <- 2 x - xp, xp <- old x: linear extrapolation of the force solutions
+__global__ void __launch_bounds__(kB) k_extrapolate(double *x, double *xp, long long n)
+{
+    const long long i = (long long)blockIdx.x * kB + threadIdx.x;
+    if (i >= n) return;
+    const double cur = x[i];
+    x[i] = 2.0 * cur - xp[i];
+    xp[i] = cur;
+}
+
 __global__ void __launch_bounds__(kB) k_p_step(double *P, const double *F, long long n, double eps)
 {
     const long long i = (long long)blockIdx.x * kB + threadIdx.x;
@@ -428,7 +438,7 @@ using namespace wd;
 namespace {
 
 struct HmcWs {
-    double *U, *P, *F, *chi, *phi, *Xe, *Ye, *Xo, *Yo, *Xf, *Yf, *tmp, *partial, *scal;
+    double *U, *P, *F, *chi, *phi, *Xe, *Ye, *Xo, *Yo, *Xf, *Yf, *tmp, *partial, *scal, *Xp;
     size_t nl;   // doubles in a link field
     size_t ns;   // doubles in a parity spinor
 };
@@ -456,6 +466,7 @@ wd_status hmc_ws(wd_ctx *c, HmcWs *w)
     WD_TRY(get("hmc_Xf", 2 * w->ns, &w->Xf));
     WD_TRY(get("hmc_Yf", 2 * w->ns, &w->Yf));
     WD_TRY(get("hmc_tmp", w->ns, &w->tmp));
+    WD_TRY(get("hmc_Xp", w->ns, &w->Xp));  // the force solution of the step before (extrapolation)
     WD_TRY(get("hmc_partial", V * 4 * 18 / 16 + 64, &w->partial));  // largest reduction: a link field
     WD_TRY(get("hmc_scal", 16, &w->scal));
     return WD_OK;
@@ -582,6 +593,7 @@ void wd_hmc_defaults(wd_hmc_params *h)
     wd_solver_defaults(&h->h_solver);
     h->h_solver.tol = 1e-10;
     h->metropolis = 1;
+    h->chrono = 0;
 }
 
 wd_status wd_plaquette(wd_ctx *c, const double *U, double *plaq)
@@ -616,6 +628,7 @@ wd_status wd_md_force(wd_ctx *c, double *F, const double *U, const double *phi, 
     wd_solver_defaults(&sp);
     if (p) sp = *p;
     if (!sp.eo) return set_error(WD_ERR_ARG, "the force uses the even-odd action (eo = 1)");
+    sp.initial_guess = 0;  // the solve's workspace holds no caller data: x0 = 0
     WD_HIP(hipSetDevice(c->device));
     HmcWs w;
     WD_TRY(hmc_ws(c, &w));
@@ -638,6 +651,7 @@ wd_status hmc_trajectory(wd_ctx *c, double *U, const wd_hmc_params *h, wd_hmc_re
     if (h->nsteps < 1 || !(h->tau > 0) || !std::isfinite(h->beta) || !std::isfinite(h->kappa))
         return set_error(WD_ERR_ARG, "bad HMC parameters");
     if (!h->force_solver.eo || !h->h_solver.eo) return set_error(WD_ERR_ARG, "HMC uses the even-odd action");
+    if (h->chrono < 0 || h->chrono > 2) return set_error(WD_ERR_ARG, "chrono %d not in 0..2", h->chrono);
     WD_HIP(hipSetDevice(c->device));
     HmcWs w;
     WD_TRY(hmc_ws(c, &w));
@@ -660,9 +674,28 @@ wd_status hmc_trajectory(wd_ctx *c, double *U, const wd_hmc_params *h, wd_hmc_re
     const double V = (double)c->V;
     const double h_old = 0.5 * kin0 + beta * 6.0 * V * (1.0 - plaq0) + chi2;
 
-    // leapfrog P-Q-P
+    // leapfrog P-Q-P.  chrono 1: each force solve starts from the previous
+    // step's solution; chrono 2: from the linear extrapolation of the last
+    // two; the first solve of a trajectory (and with 2 the second, from the
+    // first) starts from zero.
+    wd_solver_params fsp = h->force_solver;
+    fsp.initial_guess = h->chrono ? 1 : 0;
+    if (h->chrono) HIPCHK(hipMemsetAsync(w.Xe, 0, w.ns * sizeof(double), s));
+    int nsolve = 0;
+    auto guess = [&]() -> wd_status {
+        if (h->chrono == 2 && nsolve == 1)
+            HIPCHK(hipMemcpyAsync(w.Xp, w.Xe, w.ns * sizeof(double), hipMemcpyDeviceToDevice, s));
+        if (h->chrono == 2 && nsolve >= 2) {
+            hipLaunchKernelGGL(k_extrapolate, dim3(nblk((long long)w.ns)), dim3(kB), 0, s, w.Xe, w.Xp,
+                               (long long)w.ns);
+            HIPCHK(hipGetLastError());
+        }
+        nsolve++;
+        return WD_OK;
+    };
     wd_status st = WD_OK;
-    st = md_force(c, w, beta, kappa, &h->force_solver, &it);
+    WD_TRY(guess());
+    st = md_force(c, w, beta, kappa, &fsp, &it);
     iters += it;
     if (st == WD_OK) {
         hipLaunchKernelGGL(k_p_step, dim3(nblk((long long)w.nl)), dim3(kB), 0, s, w.P, w.F, (long long)w.nl, 0.5 * eps);
@@ -670,7 +703,8 @@ wd_status hmc_trajectory(wd_ctx *c, double *U, const wd_hmc_params *h, wd_hmc_re
             hipLaunchKernelGGL(k_u_step, dim3(nblk(nl)), dim3(kB), 0, s, w.U, w.P, c->g, eps);
             HIPCHK(hipGetLastError());
             WD_TRY(reload_links(c, w.U));
-            st = md_force(c, w, beta, kappa, &h->force_solver, &it);
+            WD_TRY(guess());
+            st = md_force(c, w, beta, kappa, &fsp, &it);
             iters += it;
             if (st != WD_OK) break;
             hipLaunchKernelGGL(k_p_step, dim3(nblk((long long)w.nl)), dim3(kB), 0, s, w.P, w.F, (long long)w.nl,

@@ -367,7 +367,7 @@ struct BatchSolver {
 
     // Pack n right-hand sides (phi: [n][sites][4][3], device) into free slots
     // and initialise their CG state.  slots_out (host) receives the slots.
-    wd_status add(const double *phi, int n, const double *kappa, int *slots_out)
+    wd_status add(const double *phi, int n, const double *kappa, int *slots_out, const double *x0 = nullptr)
     {
         std::vector<int> slots;
         for (int j = 0; j < cap && (int)slots.size() < n; j++)
@@ -385,16 +385,32 @@ struct BatchSolver {
         WD_TRY(upload_list(slots, lst));
         HIPCHK(blas_norm(b64, Vh, lst, n, partial, pstride, s));
         HIPCHK(blas_finalize(partial, pstride, nwF, lst, n, FIN_STORE, rr, alpha, beta, bb, s));
+        if (x0) {
+            // start from x0: x = x0, r = b - A x0 in FP64, rr = |r|^2
+            for (int q = 0; q < n; q++) {
+                Field v = x64;
+                v.base = x64.base + slots[q] * x64.rs;
+                HIPCHK(pack_spinor(x0 + q * site_doubles, v, 1, p.eo ? 0 : 1, c->g, s));
+            }
+            WD_TRY(apply_A(SP_F64, c->lk64, x64, Ap64, lst, n, false));
+            HIPCHK(blas_resid(r64, b64, Ap64, Vh, lst, n, partial, pstride, s));
+        } else {
+            HIPCHK(blas_zero(x64, Vh, lst, n, s));
+            HIPCHK(blas_copy(r64, b64, Vh, lst, n, s));
+        }
         HIPCHK(blas_finalize(partial, pstride, nwF, lst, n, FIN_RR, rr, alpha, beta, nullptr, s));
-        HIPCHK(blas_zero(x64, Vh, lst, n, s));
-        HIPCHK(blas_copy(r64, b64, Vh, lst, n, s));
         if (mixed) {
-            HIPCHK(blas_copy(rs, b64, Vh, lst, n, s));
+            HIPCHK(blas_copy(rs, r64, Vh, lst, n, s));
             HIPCHK(blas_zero(xs, Vh, lst, n, s));
         }
         HIPCHK(blas_copy(lane_s.P, lane_s.R, Vh, lst, n, s));
+        std::vector<double> rr0(cap, 0.0);
+        HIPCHK(hipMemcpyAsync(hbuf, rr, sizeof(double) * cap, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        for (int q = 0; q < n; q++) rr0[slots[q]] = hbuf[slots[q]];
         HIPCHK(hipMemcpyAsync(hbuf, bb, sizeof(double) * cap, hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
+        const double tol2 = p.tol * p.tol;
         for (int q = 0; q < n; q++) {
             const int j = slots[q];
             bbh[j] = hbuf[j];
@@ -403,14 +419,18 @@ struct BatchSolver {
             last_ru[j] = 0;
             stall[j] = 0;
             tres[j] = 0.0;
-            maxrr[j] = best[j] = bbh[j];
-            if (!std::isfinite(bbh[j])) {
+            maxrr[j] = best[j] = rr0[j];
+            if (!std::isfinite(bbh[j]) || !std::isfinite(rr0[j])) {
                 state[j] = SLOT_DONE;
                 status[j] = WD_ERR_NAN;
                 tres[j] = NAN;
-            } else if (bbh[j] == 0.0) {
+            } else if (bbh[j] == 0.0 && rr0[j] == 0.0) {
                 state[j] = SLOT_DONE;
                 status[j] = WD_OK;
+            } else if (rr0[j] <= tol2 * bbh[j]) {  // the initial guess already meets tol
+                state[j] = SLOT_DONE;
+                status[j] = WD_OK;
+                tres[j] = std::sqrt(rr0[j] / bbh[j]);
             } else {
                 state[j] = SLOT_RUNNING;
                 status[j] = WD_ERR_NOCONV;
@@ -732,7 +752,7 @@ extern "C" wd_status wd_cg_solve(wd_ctx *c, double *x, const double *phi, int nr
         }
     } pscope{bs};
     WD_TRY(bs.init(c, nrhs, p, "cg_"));
-    WD_TRY(bs.add(phi, nrhs, kappa, nullptr));
+    WD_TRY(bs.add(phi, nrhs, kappa, nullptr, p.initial_guess ? x : nullptr));
     int it = 0;
     while (bs.running() && it < p.maxiter) {
         const int k = std::min(p.poll, p.maxiter - it);

@@ -34,7 +34,7 @@ class WDError(RuntimeError):
 class wd_solver_params(C.Structure):
     _fields_ = [("tol", C.c_double), ("maxiter", C.c_int), ("prec_sloppy", C.c_int),
                 ("eo", C.c_int), ("delta", C.c_double), ("poll", C.c_int), ("tuned", C.c_int),
-                ("graphs", C.c_int)]
+                ("graphs", C.c_int), ("initial_guess", C.c_int)]
 
 
 class wd_solver_stats(C.Structure):
@@ -46,7 +46,7 @@ class wd_hmc_params(C.Structure):
     _fields_ = [("beta", C.c_double), ("kappa", C.c_double), ("tau", C.c_double),
                 ("nsteps", C.c_int), ("traj", C.c_uint32), ("seed", C.c_uint64),
                 ("force_solver", wd_solver_params), ("h_solver", wd_solver_params),
-                ("metropolis", C.c_int)]
+                ("metropolis", C.c_int), ("chrono", C.c_int)]
 
 
 class wd_hmc_result(C.Structure):
@@ -384,11 +384,12 @@ def hmc_trajectory(ctx, U, params, check=True):
 
 
 def hmc_params(beta=5.6, kappa=0.156, tau=1.0, nsteps=50, seed=1, traj=0, force=None, h=None,
-               metropolis=True):
+               metropolis=True, chrono=False):
     p = wd_hmc_defaults()
     p.beta, p.kappa, p.tau, p.nsteps, p.seed, p.traj = (float(beta), float(kappa), float(tau),
                                                         int(nsteps), int(seed), int(traj))
     p.metropolis = 1 if metropolis else 0
+    p.chrono = int(chrono)
     if force is not None:
         p.force_solver = force
     if h is not None:
@@ -444,10 +445,12 @@ def wd_version():
     return lib().wd_version().decode()
 
 
-def solver_params(tol=1e-10, maxiter=20000, prec=WD_F64, eo=1, delta=0.1, poll=8, tuned=0, graphs=1):
+def solver_params(tol=1e-10, maxiter=20000, prec=WD_F64, eo=1, delta=0.1, poll=8, tuned=0, graphs=1,
+                  initial_guess=0):
     p = wd_solver_defaults()
     p.tol, p.maxiter, p.prec_sloppy, p.eo, p.delta, p.poll, p.tuned, p.graphs = (
         float(tol), int(maxiter), int(prec), int(eo), float(delta), int(poll), int(tuned), int(graphs))
+    p.initial_guess = int(initial_guess)
     return p
 
 

@@ -169,3 +169,39 @@ def test_graph_replay_equals_eager_launches(wd, prec):
     if prec == "F16":
         assert out[0][1][0][1] > 0  # the FP64 lane ran inside the graphs too
     lat.close()
+
+
+def test_initial_guess(wd, oracle):
+    """initial_guess = 1 starts from the vectors in x: from the solution of a
+    nearby operator (kappa + 1e-3) the mixed solve needs fewer iterations and
+    still meets 1e-10 by the oracle; from the exact solution it stops at once
+    (0 iterations); from x = 0 it equals the default solve bit for bit."""
+    import torch
+    dims = (8, 8, 8, 8)
+    U = li.random_su3_field(dims, 0.3, seed=31)
+    B = li.gaussian_spinor(li.volume(dims) // 2, seed=32, nrhs=2)
+    kap = [0.15, 0.152]
+    lat = wd.Lattice(dims)
+    lat.gauge_load(dev(U), recon=12)
+    X0 = empty_like_dev(B)
+    st, s0 = lat.cg_solve(X0, dev(B), kap, wd.solver_params(prec=wd.WD_F16))
+    assert st == wd.WD_OK
+    Xn = empty_like_dev(B)
+    st, _ = lat.cg_solve(Xn, dev(B), [k + 1e-3 for k in kap], wd.solver_params(prec=wd.WD_F16))
+    st, s1 = lat.cg_solve(Xn, dev(B), kap, wd.solver_params(prec=wd.WD_F16, initial_guess=1))
+    assert st == wd.WD_OK
+    note(f"initial guess: iters {[s['iters'] for s in s0]} from 0, {[s['iters'] for s in s1]} from a nearby solution")
+    assert all(a["iters"] < b["iters"] for a, b in zip(s1, s0))
+    Xh = host(Xn)
+    for j in range(2):
+        r = B[j] - oracle.mhatdag_mhat(dims, U, kap[j], Xh[j])
+        assert np.linalg.norm(r) / np.linalg.norm(B[j]) <= 1.01e-10
+    Xs = X0.clone()
+    st, s2 = lat.cg_solve(Xs, dev(B), kap, wd.solver_params(prec=wd.WD_F16, initial_guess=1))
+    assert st == wd.WD_OK and all(s["iters"] == 0 for s in s2)
+    assert torch.equal(Xs, X0)
+    Xz = torch.zeros_like(X0)
+    st, s3 = lat.cg_solve(Xz, dev(B), kap, wd.solver_params(prec=wd.WD_F16, initial_guess=1))
+    assert [s["iters"] for s in s3] == [s["iters"] for s in s0]
+    assert torch.equal(Xz, X0)
+    lat.close()

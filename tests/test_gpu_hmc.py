@@ -140,3 +140,33 @@ def test_md_trajectory_without_metropolis_takes_the_proposal(wd, oracle):
     assert err <= 1e-9
     assert abs(r["plaquette"] - oracle.plaquette(dims, Uo)) <= 1e-11
     lat.close()
+
+
+def test_chronological_force_solves(wd, oracle):
+    """chrono = 1 (each force solve starts from the previous step's solution)
+    and 2 (linear extrapolation of the last two): fewer CG iterations per
+    trajectory, and with tight force solves the same dH and field as the
+    oracle's trajectory (x0 = 0) to solver tolerance."""
+    dims = (4, 4, 4, 4)
+    U0 = li.random_su3_field(dims, 0.5, seed=50)
+    beta, kappa, tau, n = 5.6, 0.12, 0.5, 10
+    tight = wd.solver_params(tol=1e-13)
+    res = {}
+    for chrono in (0, 1, 2):
+        lat = wd.Lattice(dims)
+        Ud = dev(U0)
+        hp = wd.hmc_params(beta, kappa, tau, n, seed=51, traj=0, force=tight, h=tight, chrono=chrono)
+        res[chrono] = (wd.hmc_trajectory(lat.ctx, Ud, hp), host(Ud))
+        lat.close()
+    _, ro = oracle.hmc_trajectory(dims, U0, beta, kappa, tau, n, seed=51, traj=0, eo=True,
+                                  tol_force=1e-13, tol_h=1e-13)
+    r0 = res[0][0]
+    note(f"chrono: cg iters {r0['cg_iters']} -> {res[1][0]['cg_iters']} (previous) / {res[2][0]['cg_iters']} "
+         f"(extrapolated), dH {r0['dH']:.10f} / {res[1][0]['dH']:.10f} / {res[2][0]['dH']:.10f} "
+         f"(oracle {ro['dH']:.10f})")
+    for ch in (1, 2):
+        r1 = res[ch][0]
+        assert r1["status"] == wd.WD_OK and r1["cg_iters"] < r0["cg_iters"]
+        assert abs(r1["dH"] - ro["dH"]) <= 1e-6
+        assert bool(r1["accepted"]) == ro["accepted"]
+        assert np.abs(res[ch][1] - res[0][1]).max() <= 1e-10
