@@ -120,6 +120,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--tuned", type=int, default=1, help="autotune launch shapes before timing")
     ap.add_argument("--requests", type=int, default=None, help="c4: requests per pass")
+    ap.add_argument("--delta", type=float, default=0.02,
+                    help="reliable-update threshold of the mixed solves (c1-c3, c6)")
     ap.add_argument("--chrono", type=int, default=1, choices=(0, 1, 2),
                     help="c5: force-solve starting vectors (0 zero, 1 previous, 2 extrapolated)")
     ap.add_argument("--tune-only", action="store_true",
@@ -227,7 +229,7 @@ def bench_solve(args, wd, torch):
     Xd = torch.empty_like(Bd)
     lat = wd.Lattice(dims)
     lat.gauge_load(Ud, recon=12)
-    params = wd.solver_params(prec=PRECS[args.prec], eo=1, tuned=args.tuned)
+    params = wd.solver_params(prec=PRECS[args.prec], eo=1, tuned=args.tuned, delta=args.delta)
     if args.tuned:
         t = time.time()
         for code in {PRECS[args.prec], 0}:
@@ -309,7 +311,7 @@ def bench_solve(args, wd, torch):
     out = base_record(args, value, "solves/s", elapsed / args.steps * 1e3, DTYPE[args.prec],
                       {"workload": f"{args.workload}: {'x'.join(map(str, dims))} lattice, {nrhs} RHS, "
                                    f"kappa {kappa}, eps {w['eps']}, even-odd CG to 1e-10",
-                       "prec_sloppy": args.prec, "nrhs": nrhs, "lattice": list(dims)})
+                       "prec_sloppy": args.prec, "nrhs": nrhs, "lattice": list(dims), "delta": args.delta})
     out.update({
         "converged": bool(ok),
         "iters": iters[-1],
@@ -644,7 +646,7 @@ def bench_measure(args, wd, torch):
     lat.gauge_load(Ud, recon=12)
     V = li.volume(dims)
     psi = torch.empty((12, V, 4, 3), dtype=torch.complex128, device="cuda")
-    params = wd.solver_params(prec=PRECS[args.prec], eo=1, tol=1e-10, tuned=args.tuned)
+    params = wd.solver_params(prec=PRECS[args.prec], eo=1, tol=1e-10, tuned=args.tuned, delta=args.delta)
     if args.tuned:
         for code in {PRECS[args.prec], 0}:
             wd.wd_tune(lat.ctx, 12, code)
@@ -698,7 +700,7 @@ def bench_measure(args, wd, torch):
                       {"workload": (f"c6_measure: {'x'.join(map(str, dims))} lattice (eps {w['eps']}), kappa {kappa}, "
                                     f"point source {src}: 12 columns solved together to 1e-10, pion correlator, "
                                     f"plaquette, Polyakov loop"),
-                       "prec_sloppy": args.prec, "lattice": list(dims)})
+                       "prec_sloppy": args.prec, "lattice": list(dims), "delta": args.delta})
     out.update({
         "converged": bool(ok),
         "configs_per_hour": 3600.0 * args.steps / elapsed,
