@@ -162,7 +162,7 @@ wd_status run_sweep(wd_ctx *c, const Sweep &sw, const TuneCfg *cfg)
             return set_error(WD_ERR_ARG, "slab tile order %d needs Lz (or Lt) %% 8 == 0 and whole tiles per "
                              "plane and stripe", t.remap);
         a.tpp = c->g.Lxh * c->g.L[1] / spb;
-        a.nzl = (t.remap >= 5 ? c->g.L[3] : c->g.L[2]) / 8;
+        a.nzl = c->g.L[remap_slab_dim(t.remap)] / 8;
         a.nys = remap_stripes(t.remap);
     }
     const long long grid = (long long)ntiles * a.G;
@@ -201,7 +201,7 @@ wd_status run_sweep(wd_ctx *c, const Sweep &sw, const TuneCfg *cfg)
 bool slab_order_ok(const Geom &g, int spb, int remap)
 {
     const int plane = g.Lxh * g.L[1];
-    if (g.L[remap >= 5 ? 3 : 2] % 8 != 0 || spb <= 0 || plane % spb != 0) return false;
+    if (g.L[remap_slab_dim(remap)] % 8 != 0 || spb <= 0 || plane % spb != 0) return false;
     return (plane / spb) % remap_stripes(remap) == 0;
 }
 

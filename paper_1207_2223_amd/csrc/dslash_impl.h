@@ -114,7 +114,18 @@ __global__ void __launch_bounds__(256) dslash_kernel(DslashArgs a)
     typedef typename SpinorIO<SP>::real real;
     static_assert(sizeof(typename LinkIO<LK>::real) == sizeof(real), "link/spinor precision pair");
     int tile, grp;
-    if (a.remap >= 5) {
+    if (a.remap == 7) {
+        // z-slab per XCD as order 2, but RHS-group-major: the XCD sweeps its
+        // whole slab for one RHS group before the next, so only NR*RL RHS of
+        // spinor data are in flight (the links are re-read per group).
+        const int x = blockIdx.x & 7, j = blockIdx.x >> 3;
+        const int tx = (int)(gridDim.x / 8) / a.G;  // tiles per XCD
+        grp = j / tx;
+        const int sidx = j - grp * tx;
+        const int q = sidx % a.tpp, zt = sidx / a.tpp;
+        const int zl = zt % a.nzl, t = zt / a.nzl;
+        tile = ((t * a.g.L[2]) + x * a.nzl + zl) * a.tpp + q;
+    } else if (a.remap >= 5) {
         // XCD x owns t-planes [x*ntl, (x+1)*ntl) (ntl = Lt / 8, held in nzl)
         // and walks them t-fastest: a tile's t-neighbours are the tiles just
         // before and after it on the same XCD, its z-neighbours ntl tiles

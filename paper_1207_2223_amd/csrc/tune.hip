@@ -66,6 +66,21 @@ hipError_t fill(const Field &f, int Vh, int nrhs, unsigned seed, hipStream_t s)
     return hipGetLastError();
 }
 
+__global__ void __launch_bounds__(kBlock) k_fill_bytes(unsigned *p, long long n, unsigned v)
+{
+    const long long i = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) p[i] = v * 0x01010101u;
+}
+
+hipError_t fill_bytes(void *p, size_t bytes, unsigned v, hipStream_t s)
+{
+    const long long n = (long long)(bytes / 4);
+    if (n > 0)
+        hipLaunchKernelGGL(k_fill_bytes, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
+                           (unsigned *)p, n, v & 0xffu);
+    return hipGetLastError();
+}
+
 std::string sweep_key(int sp, int lk, int dag, int epi)
 {
     char b[64];
@@ -282,11 +297,16 @@ extern "C" wd_status wd_tune(wd_ctx *c, int nrhs, int prec, char *report, size_t
         int rejected = 0;
         for (size_t q = 0; q < cands.size(); q++) {
             const TuneCfg &cf = cands[q];
-            // correctness run on fresh inputs
+            // correctness run on fresh inputs, with every output poisoned first
+            // so that a shape that skips sites cannot pass on stale results
             if (k.epi == EPI_CGUPD) {
                 HIPCHK(hipMemcpyAsync(t.r.base, t.r0.base, sb * nrhs, hipMemcpyDeviceToDevice, s));
                 HIPCHK(hipMemcpyAsync(t.xs.base, t.xs0.base, xb * nrhs, hipMemcpyDeviceToDevice, s));
+            } else {
+                HIPCHK(fill(t.out, Vh, nrhs, 1000 + (unsigned)q, s));
             }
+            // (the same poison every time: slots no shape writes stay equal)
+            if (t.partial) HIPCHK(fill_bytes(t.partial, sizeof(double) * t.pstride * nrhs, 0xA5u, s));
             if ((st = run_sweep(c, sw, &cf)) != WD_OK) break;
             if (q == 0) {
                 HIPCHK(hipMemcpyAsync(t.outref.base, t.out.base, sb * nrhs, hipMemcpyDeviceToDevice, s));

@@ -207,10 +207,12 @@ Field sub_view(const Field &f, int s);
 TuneCfg default_cfg(int sp);
 // Whether the z-slab tile order (remap 2) applies to tiles of spb sites.
 // Tile orders: 0 plain, 1 XCD round-robin, 2-4 z-slab per XCD in 1/2/4
-// y-stripes, 5-6 t-slab per XCD walked t-fastest.
-constexpr int kTileOrders = 7;
+// y-stripes, 5-6 t-slab per XCD walked t-fastest, 7 z-slab per XCD with the
+// RHS groups outermost.
+constexpr int kTileOrders = 8;
 bool slab_order_ok(const Geom &g, int spb, int remap = 2);
 inline int remap_stripes(int remap) { return remap <= 2 || remap >= 5 ? 1 : (remap == 3 ? 2 : 4); }
+inline int remap_slab_dim(int remap) { return (remap == 5 || remap == 6) ? 3 : 2; }
 const TuneCfg *tuned_cfg(const wd_ctx *c, const Sweep &sw);
 double sweep_bytes(const wd_ctx *c, const Sweep &sw);
 

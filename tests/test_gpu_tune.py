@@ -21,9 +21,10 @@ def wd():
 def _expected_candidates(dims, code, nrhs):
     """The tuner's candidate count: block {64,128,256} x RHS per lane x lanes
     per site x tile order {plain, XCD round-robin, z-slab with 1, 2, 4
-    y-stripes, t-slab walked t-fastest in two orders}, where the z-slab
-    orders need Lz % 8 == 0, the t-slab orders Lt % 8 == 0, and both a whole
-    number of tiles per plane and per stripe."""
+    y-stripes, t-slab walked t-fastest in two orders, z-slab with the RHS
+    groups outermost}, where the z-slab orders need Lz % 8 == 0, the t-slab
+    orders Lt % 8 == 0, and all a whole number of tiles per plane and per
+    stripe."""
     f64 = (code & 0xF) == 0
     shapes = [(1, 1), (2, 1), (1, 2), (2, 2), (1, 4), (2, 4)] if f64 else \
         [(nr, rl) for rl in (1, 2, 4) for nr in (1, 2, 3, 4)]
@@ -34,8 +35,8 @@ def _expected_candidates(dims, code, nrhs):
             continue
         for b in (64, 128, 256):
             spb = b // rl
-            for rm, ns in ((0, 0), (1, 0), (2, 1), (3, 2), (4, 4), (5, 1), (6, 1)):
-                slab = dims[3] if rm >= 5 else dims[2]
+            for rm, ns in ((0, 0), (1, 0), (2, 1), (3, 2), (4, 4), (5, 1), (6, 1), (7, 1)):
+                slab = dims[3] if rm in (5, 6) else dims[2]
                 if rm >= 2 and not (slab % 8 == 0 and plane % spb == 0 and (plane // spb) % ns == 0):
                     continue
                 n += 1
