@@ -56,10 +56,66 @@ __device__ __forceinline__ real load_nb(const char *f, int cs, int j, real v[24]
     }
 }
 
+// FP16 neighbour spinor as 12 (re, im) half2 pairs, and its per-site norm.
+__device__ __forceinline__ float load_nb_h2(const char *f, int cs, int j, h2_t v[12])
+{
+    const half8_t *p = reinterpret_cast<const half8_t *>(f);
+#pragma unroll
+    for (int k = 0; k < 3; k++) {
+        const half8_t w = p[(size_t)k * cs + j];
+#pragma unroll
+        for (int q = 0; q < 4; q++) v[4 * k + q] = h2_t{w[2 * q], w[2 * q + 1]};
+    }
+    return reinterpret_cast<const float *>(f + (size_t)48 * cs)[j];
+}
+
+// FP16 spinors with FP16 links: dot2 matvec on FP16 inputs, FP32 results.
+template <int MU, int NR, bool DAG>
+__device__ __forceinline__ void hop_dir_f16dot(const DslashArgs &a, int i, const int c[4], const int rid[NR],
+                                               const bool rv[NR], float acc[NR][24])
+{
+    constexpr int SF = DAG ? +1 : -1;
+    constexpr int SB = -SF;
+    const int cs = a.g.cs;
+    h2_t A[9], B[9];
+    {
+        const int j = neighbour<MU, +1>(a.g, i, c);
+        link_forms_f16<false>(a.links, cs, a.P * 4 + MU, i, A, B);
+#pragma unroll
+        for (int r = 0; r < NR; r++) {
+            if (!rv[r]) continue;
+            h2_t v[12], h[6];
+            float w[12];
+            const float sc = load_nb_h2(a.in + rid[r] * a.in_rs, cs, j, v);
+            project_h2<MU, SF>(v, h);
+            su3_mul_half_dot2(A, B, h, w);
+            accumulate_scaled<MU, SF>(acc[r], w, sc);
+        }
+    }
+    {
+        const int j = neighbour<MU, -1>(a.g, i, c);
+        link_forms_f16<true>(a.links, cs, (1 - a.P) * 4 + MU, j, A, B);
+#pragma unroll
+        for (int r = 0; r < NR; r++) {
+            if (!rv[r]) continue;
+            h2_t v[12], h[6];
+            float w[12];
+            const float sc = load_nb_h2(a.in + rid[r] * a.in_rs, cs, j, v);
+            project_h2<MU, SB>(v, h);
+            su3_mul_half_dot2(A, B, h, w);
+            accumulate_scaled<MU, SB>(acc[r], w, sc);
+        }
+    }
+}
+
 template <int MU, int SP, int LK, int NR, bool DAG, typename real>
 __device__ __forceinline__ void hop_dir(const DslashArgs &a, int i, const int c[4],
                                         const int rid[NR], const bool rv[NR], real acc[NR][24])
 {
+    if constexpr (SP == SP_F16 && LK == LK_F16_12) {
+        hop_dir_f16dot<MU, NR, DAG>(a, i, c, rid, rv, acc);
+        return;
+    }
     constexpr int SF = DAG ? +1 : -1;  // forward: (1 - g) for H, (1 + g) for H^dag
     constexpr int SB = -SF;            // backward: the opposite projector
     const int cs = a.g.cs;

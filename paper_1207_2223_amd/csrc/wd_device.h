@@ -567,6 +567,100 @@ __device__ __forceinline__ void su3_mul_half(const T u[18], const T h[12], T w[1
 }
 
 // ---------------------------------------------------------------------------
+// FP16-input path (FP16 spinors with FP16 links): v_dot2_f32_f16 forms two
+// FP16 products and adds them to an FP32 accumulator, so a complex
+// multiply-add is two instructions instead of four FP32 FMAs.  Inputs stay
+// in FP16 (the stored spinor and link values; the projected half spinor,
+// whose FP16 sum of two FP16 values rounds exactly as the FP32 sum would when
+// rounded to FP16; the reconstructed third link row, rounded to FP16);
+// products and sums are FP32.
+// ---------------------------------------------------------------------------
+typedef _Float16 h2_t __attribute__((ext_vector_type(2)));
+
+// The two half2 forms of each link element for the dot-product matvec:
+//   plain   (u[a][b]):          re = A.h, A = (ur, -ui);  im = B.h, B = (ui, ur)
+//   adjoint (conj u[b][a]):     re = A.h, A = (ur,  ui);  im = B.h, B = (-ui, ur)
+// indexed [3a + b] for output colour a, input colour b.
+template <bool ADJ>
+__device__ __forceinline__ void link_forms_f16(const char *U, int cs, int blk, int i, h2_t A[9], h2_t B[9])
+{
+    const half4_t *p = reinterpret_cast<const half4_t *>(U) + (size_t)blk * 3 * cs;
+    float u[18];
+    _Float16 hv[18];
+#pragma unroll
+    for (int k = 0; k < 3; k++) {
+        const half4_t w = p[(size_t)k * cs + i];
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            hv[4 * k + j] = w[j];
+            u[4 * k + j] = (float)w[j];
+        }
+    }
+    reconstruct_row3(u);
+#pragma unroll
+    for (int k = 12; k < 18; k++) hv[k] = (_Float16)u[k];
+#pragma unroll
+    for (int a = 0; a < 3; a++)
+#pragma unroll
+        for (int b = 0; b < 3; b++) {
+            const int e = ADJ ? 3 * b + a : 3 * a + b;
+            const _Float16 ur = hv[2 * e], ui = hv[2 * e + 1];
+            if (ADJ) {
+                A[3 * a + b] = h2_t{ur, ui};
+                B[3 * a + b] = h2_t{-ui, ur};
+            } else {
+                A[3 * a + b] = h2_t{ur, -ui};
+                B[3 * a + b] = h2_t{ui, ur};
+            }
+        }
+}
+
+// (1 + S g_mu) projection on half2 pairs: v[3s + c] = (re, im) of spin s,
+// colour c; h[3r + c] for the two independent rows (as project()).
+template <int MU, int S>
+__device__ __forceinline__ void project_h2(const h2_t v[12], h2_t h[6])
+{
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        const h2_t p0 = v[c], p1 = v[3 + c], p2 = v[6 + c], p3 = v[9 + c];
+        const h2_t ip2 = h2_t{-p2.y, p2.x}, ip3 = h2_t{-p3.y, p3.x};  // i * p
+        const _Float16 s = (_Float16)S;
+        if (MU == 0) {
+            h[c] = p0 + s * ip3;
+            h[3 + c] = p1 + s * ip2;
+        } else if (MU == 1) {
+            h[c] = p0 - s * p3;
+            h[3 + c] = p1 + s * p2;
+        } else if (MU == 2) {
+            h[c] = p0 + s * ip2;
+            h[3 + c] = p1 - s * ip3;
+        } else {
+            h[c] = p0 + s * p2;
+            h[3 + c] = p1 + s * p3;
+        }
+    }
+}
+
+// w = U h (or U^dag h) for both rows, FP32 results in the float layout of
+// su3_mul_half.
+__device__ __forceinline__ void su3_mul_half_dot2(const h2_t A[9], const h2_t B[9], const h2_t h[6], float w[12])
+{
+#pragma unroll
+    for (int r = 0; r < 2; r++)
+#pragma unroll
+        for (int a = 0; a < 3; a++) {
+            float re = 0.f, im = 0.f;
+#pragma unroll
+            for (int b = 0; b < 3; b++) {
+                re = __builtin_amdgcn_fdot2(A[3 * a + b], h[3 * r + b], re, false);
+                im = __builtin_amdgcn_fdot2(B[3 * a + b], h[3 * r + b], im, false);
+            }
+            w[6 * r + 2 * a] = re;
+            w[6 * r + 2 * a + 1] = im;
+        }
+}
+
+// ---------------------------------------------------------------------------
 // Block-to-tile mapping.  Work-groups are dispatched round-robin over the
 // 8 XCDs (each with its own L2); remapping gives each XCD a contiguous run
 // of tiles so that neighbouring lattice slabs share one L2.
