@@ -56,6 +56,19 @@ __device__ __forceinline__ real load_nb(const char *f, int cs, int j, real v[24]
     }
 }
 
+// FP16 neighbour spinor as stored (24 halves), and its per-site norm.
+__device__ __forceinline__ float load_nb_half(const char *f, int cs, int j, _Float16 v[24])
+{
+    const half8_t *p = reinterpret_cast<const half8_t *>(f);
+#pragma unroll
+    for (int k = 0; k < 3; k++) {
+        const half8_t w = p[(size_t)k * cs + j];
+#pragma unroll
+        for (int q = 0; q < 8; q++) v[8 * k + q] = w[q];
+    }
+    return reinterpret_cast<const float *>(f + (size_t)48 * cs)[j];
+}
+
 // FP16 neighbour spinor as 12 (re, im) half2 pairs, and its per-site norm.
 __device__ __forceinline__ float load_nb_h2(const char *f, int cs, int j, h2_t v[12])
 {
@@ -126,9 +139,16 @@ __device__ __forceinline__ void hop_dir(const DslashArgs &a, int i, const int c[
 #pragma unroll
         for (int r = 0; r < NR; r++) {
             if (!rv[r]) continue;
-            real v[24], h[12], w[12];
-            const real sc = load_nb<SP>(a.in + rid[r] * a.in_rs, cs, j, v);
-            project<MU, SF>(v, h);
+            real h[12], w[12], sc;
+            if constexpr (SP == SP_F16) {
+                _Float16 v[24];
+                sc = load_nb_half(a.in + rid[r] * a.in_rs, cs, j, v);
+                project_mix<MU, SF>(v, h);
+            } else {
+                real v[24];
+                sc = load_nb<SP>(a.in + rid[r] * a.in_rs, cs, j, v);
+                project<MU, SF>(v, h);
+            }
             su3_mul_half<false>(u, h, w);
             if constexpr (has_norm(SP))
                 accumulate_scaled<MU, SF>(acc[r], w, sc);
@@ -142,9 +162,16 @@ __device__ __forceinline__ void hop_dir(const DslashArgs &a, int i, const int c[
 #pragma unroll
         for (int r = 0; r < NR; r++) {
             if (!rv[r]) continue;
-            real v[24], h[12], w[12];
-            const real sc = load_nb<SP>(a.in + rid[r] * a.in_rs, cs, j, v);
-            project<MU, SB>(v, h);
+            real h[12], w[12], sc;
+            if constexpr (SP == SP_F16) {
+                _Float16 v[24];
+                sc = load_nb_half(a.in + rid[r] * a.in_rs, cs, j, v);
+                project_mix<MU, SB>(v, h);
+            } else {
+                real v[24];
+                sc = load_nb<SP>(a.in + rid[r] * a.in_rs, cs, j, v);
+                project<MU, SB>(v, h);
+            }
             su3_mul_half<true>(u, h, w);
             if constexpr (has_norm(SP))
                 accumulate_scaled<MU, SB>(acc[r], w, sc);

@@ -468,6 +468,49 @@ __device__ __forceinline__ void project(const T v[24], T h[12])
     }
 }
 
+// project() on FP16 inputs with FP32 results.  Each term is one
+// mixed-precision fused multiply-add, b * (+-1) + a, on the FP16 values:
+// the conversions are exact and the sum is rounded once, so the result is
+// the value of converting first and adding in FP32, in half the
+// instructions.
+template <int MU, int S>
+__device__ __forceinline__ void project_mix(const _Float16 v[24], float h[12])
+{
+    // +-1 from a register the compiler cannot see into, so that the
+    // multiply-add is not simplified into an FP32 add of converted values
+    float one;
+    asm("s_mov_b32 %0, 1.0" : "=s"(one));
+    auto pm = [one](_Float16 a, _Float16 b, float sgn) { return __builtin_fmaf((float)b, sgn * one, (float)a); };
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        const _Float16 p0r = v[2 * c], p0i = v[2 * c + 1];
+        const _Float16 p1r = v[6 + 2 * c], p1i = v[6 + 2 * c + 1];
+        const _Float16 p2r = v[12 + 2 * c], p2i = v[12 + 2 * c + 1];
+        const _Float16 p3r = v[18 + 2 * c], p3i = v[18 + 2 * c + 1];
+        if (MU == 0) {
+            h[2 * c] = pm(p0r, p3i, -S);
+            h[2 * c + 1] = pm(p0i, p3r, S);
+            h[6 + 2 * c] = pm(p1r, p2i, -S);
+            h[6 + 2 * c + 1] = pm(p1i, p2r, S);
+        } else if (MU == 1) {
+            h[2 * c] = pm(p0r, p3r, -S);
+            h[2 * c + 1] = pm(p0i, p3i, -S);
+            h[6 + 2 * c] = pm(p1r, p2r, S);
+            h[6 + 2 * c + 1] = pm(p1i, p2i, S);
+        } else if (MU == 2) {
+            h[2 * c] = pm(p0r, p2i, -S);
+            h[2 * c + 1] = pm(p0i, p2r, S);
+            h[6 + 2 * c] = pm(p1r, p3i, S);
+            h[6 + 2 * c + 1] = pm(p1i, p3r, -S);
+        } else {
+            h[2 * c] = pm(p0r, p2r, S);
+            h[2 * c + 1] = pm(p0i, p2i, S);
+            h[6 + 2 * c] = pm(p1r, p3r, S);
+            h[6 + 2 * c + 1] = pm(p1i, p3i, S);
+        }
+    }
+}
+
 // acc += full 4-spinor rebuilt from the colour-rotated half spinor w.
 template <int MU, int S, typename T>
 __device__ __forceinline__ void accumulate(T acc[24], const T w[12])
