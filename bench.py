@@ -235,7 +235,7 @@ def bench_solve(args, wd, torch):
         for code in {PRECS[args.prec], 0}:
             for row in wd.wd_tune(lat.ctx, nrhs, code):
                 log(f"[bench] tuned {code:#x} {row['sweep']}: block {row['block']} nr {row['nr']} "
-                    f"rl {row['rl']} remap {row['remap']} {row['us']:.1f} us")
+                    f"rl {row['rl']} remap {row['remap']} occ {row['occ']} {row['us']:.1f} us")
         log(f"[bench] autotune {time.time() - t:.1f}s")
     if args.tune_only:
         lat.close()

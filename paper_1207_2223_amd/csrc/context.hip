@@ -151,6 +151,9 @@ wd_status run_sweep(wd_ctx *c, const Sweep &sw, const TuneCfg *cfg)
     a.partial = sw.partial;
     a.pstride = sw.pstride;
     a.pw_off = sw.pw_off;
+    if (t.occ != 0 && (t.occ < 2 || t.occ > kMaxOcc))
+        return set_error(WD_ERR_ARG, "work-group cap %d not 0 or in 2..%d", t.occ, kMaxOcc);
+    a.lds = occ_lds_bytes(t.occ);
     const int spb = t.block / rl;
     const int ntiles = (int)((c->Vh + spb - 1) / spb);
     a.tpp = 1;
@@ -277,6 +280,10 @@ static wd_status check_dims(const int32_t *dims, long long *V)
         v *= dims[mu];
     }
     if (v >= (1LL << 31)) return set_error(WD_ERR_DIMS, "volume %lld too large", v);
+    // the stencil addresses one chunk array (16-byte elements, one parity) with
+    // 32-bit byte offsets
+    if ((long long)padded_stride((int)(v / 2)) * 16 > 0xFFFFFFFFLL)
+        return set_error(WD_ERR_DIMS, "volume %lld too large: one parity's chunk array must stay below 4 GiB", v);
     *V = v;
     return WD_OK;
 }

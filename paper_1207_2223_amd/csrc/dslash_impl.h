@@ -56,36 +56,39 @@ __device__ __forceinline__ real load_nb(const char *f, int cs, int j, real v[24]
     }
 }
 
-// FP16 neighbour spinor as stored (24 halves), and its per-site norm.
+// FP16 neighbour spinor as stored (24 halves), and its per-site norm; UNI:
+// the field base is the same in every lane.
+template <bool UNI>
 __device__ __forceinline__ float load_nb_half(const char *f, int cs, int j, _Float16 v[24])
 {
-    const half8_t *p = reinterpret_cast<const half8_t *>(f);
+    const uint32_t off = UNI ? pin_v((uint32_t)j * 16u) : (uint32_t)j * 16u;
 #pragma unroll
     for (int k = 0; k < 3; k++) {
-        const half8_t w = p[(size_t)k * cs + j];
+        const half8_t w = ld_off<half8_t, UNI>(f + (size_t)k * cs * 16, off);
 #pragma unroll
         for (int q = 0; q < 8; q++) v[8 * k + q] = w[q];
     }
-    return reinterpret_cast<const float *>(f + (size_t)48 * cs)[j];
+    return ld_off<float, UNI>(f + (size_t)48 * cs, UNI ? pin_v((uint32_t)j * 4u) : (uint32_t)j * 4u);
 }
 
 // FP16 neighbour spinor as 12 (re, im) half2 pairs, and its per-site norm.
+template <bool UNI>
 __device__ __forceinline__ float load_nb_h2(const char *f, int cs, int j, h2_t v[12])
 {
-    const half8_t *p = reinterpret_cast<const half8_t *>(f);
+    const uint32_t off = UNI ? pin_v((uint32_t)j * 16u) : (uint32_t)j * 16u;
 #pragma unroll
     for (int k = 0; k < 3; k++) {
-        const half8_t w = p[(size_t)k * cs + j];
+        const half8_t w = ld_off<half8_t, UNI>(f + (size_t)k * cs * 16, off);
 #pragma unroll
         for (int q = 0; q < 4; q++) v[4 * k + q] = h2_t{w[2 * q], w[2 * q + 1]};
     }
-    return reinterpret_cast<const float *>(f + (size_t)48 * cs)[j];
+    return ld_off<float, UNI>(f + (size_t)48 * cs, UNI ? pin_v((uint32_t)j * 4u) : (uint32_t)j * 4u);
 }
 
 // FP16 spinors with FP16 links: dot2 matvec on FP16 inputs, FP32 results.
-template <int MU, int NR, bool DAG>
+template <int MU, int NR, bool DAG, bool UNI>
 __device__ __forceinline__ void hop_dir_f16dot(const DslashArgs &a, int i, const int c[4], const int rid[NR],
-                                               const bool rv[NR], float acc[NR][24])
+                                               float acc[NR][24])
 {
     constexpr int SF = DAG ? +1 : -1;
     constexpr int SB = -SF;
@@ -96,10 +99,9 @@ __device__ __forceinline__ void hop_dir_f16dot(const DslashArgs &a, int i, const
         link_forms_f16<false>(a.links, cs, a.P * 4 + MU, i, A, B);
 #pragma unroll
         for (int r = 0; r < NR; r++) {
-            if (!rv[r]) continue;
             h2_t v[12], h[6];
             float w[12];
-            const float sc = load_nb_h2(a.in + rid[r] * a.in_rs, cs, j, v);
+            const float sc = load_nb_h2<UNI>(a.in + rid[r] * a.in_rs, cs, j, v);
             project_h2<MU, SF>(v, h);
             su3_mul_half_dot2(A, B, h, w);
             accumulate_scaled<MU, SF>(acc[r], w, sc);
@@ -110,10 +112,9 @@ __device__ __forceinline__ void hop_dir_f16dot(const DslashArgs &a, int i, const
         link_forms_f16<true>(a.links, cs, (1 - a.P) * 4 + MU, j, A, B);
 #pragma unroll
         for (int r = 0; r < NR; r++) {
-            if (!rv[r]) continue;
             h2_t v[12], h[6];
             float w[12];
-            const float sc = load_nb_h2(a.in + rid[r] * a.in_rs, cs, j, v);
+            const float sc = load_nb_h2<UNI>(a.in + rid[r] * a.in_rs, cs, j, v);
             project_h2<MU, SB>(v, h);
             su3_mul_half_dot2(A, B, h, w);
             accumulate_scaled<MU, SB>(acc[r], w, sc);
@@ -121,12 +122,13 @@ __device__ __forceinline__ void hop_dir_f16dot(const DslashArgs &a, int i, const
     }
 }
 
-template <int MU, int SP, int LK, int NR, bool DAG, typename real>
+// UNI: the RHS ids (and so the field bases) are the same in every lane.
+template <int MU, int SP, int LK, int NR, bool DAG, bool UNI, typename real>
 __device__ __forceinline__ void hop_dir(const DslashArgs &a, int i, const int c[4],
-                                        const int rid[NR], const bool rv[NR], real acc[NR][24])
+                                        const int rid[NR], real acc[NR][24])
 {
     if constexpr (SP == SP_F16 && LK == LK_F16_12) {
-        hop_dir_f16dot<MU, NR, DAG>(a, i, c, rid, rv, acc);
+        hop_dir_f16dot<MU, NR, DAG, UNI>(a, i, c, rid, acc);
         return;
     }
     constexpr int SF = DAG ? +1 : -1;  // forward: (1 - g) for H, (1 + g) for H^dag
@@ -138,11 +140,10 @@ __device__ __forceinline__ void hop_dir(const DslashArgs &a, int i, const int c[
         LinkIO<LK>::load(a.links, cs, a.P * 4 + MU, i, u);
 #pragma unroll
         for (int r = 0; r < NR; r++) {
-            if (!rv[r]) continue;
             real h[12], w[12], sc;
             if constexpr (SP == SP_F16) {
                 _Float16 v[24];
-                sc = load_nb_half(a.in + rid[r] * a.in_rs, cs, j, v);
+                sc = load_nb_half<UNI>(a.in + rid[r] * a.in_rs, cs, j, v);
                 project_mix<MU, SF>(v, h);
             } else {
                 real v[24];
@@ -161,11 +162,10 @@ __device__ __forceinline__ void hop_dir(const DslashArgs &a, int i, const int c[
         LinkIO<LK>::load(a.links, cs, (1 - a.P) * 4 + MU, j, u);
 #pragma unroll
         for (int r = 0; r < NR; r++) {
-            if (!rv[r]) continue;
             real h[12], w[12], sc;
             if constexpr (SP == SP_F16) {
                 _Float16 v[24];
-                sc = load_nb_half(a.in + rid[r] * a.in_rs, cs, j, v);
+                sc = load_nb_half<UNI>(a.in + rid[r] * a.in_rs, cs, j, v);
                 project_mix<MU, SB>(v, h);
             } else {
                 real v[24];
@@ -260,8 +260,14 @@ __global__ void __launch_bounds__(256) dslash_kernel(DslashArgs a)
 #pragma unroll
     for (int r = 0; r < NR; r++) {
         const int slot = (grp * RL + lr) * NR + r;
+        // a slot past the active count computes on RHS 0 (present in every
+        // batch) without branches; its results are neither stored nor summed
         rv[r] = slot < a.nact;
         rid[r] = rv[r] ? a.active[slot] : 0;
+        // with one lane per site the slot depends on the block only, so the
+        // RHS id is the same in every lane: keep it (and the field bases
+        // derived from it) in scalar registers
+        if constexpr (RL == 1) rid[r] = __builtin_amdgcn_readfirstlane(rid[r]);
     }
 
     real acc[NR][24];
@@ -273,10 +279,10 @@ __global__ void __launch_bounds__(256) dslash_kernel(DslashArgs a)
     if (live) {
         int c[4];
         site_coords(a.g, i, a.P, c);
-        hop_dir<0, SP, LK, NR, DAG>(a, i, c, rid, rv, acc);
-        hop_dir<1, SP, LK, NR, DAG>(a, i, c, rid, rv, acc);
-        hop_dir<2, SP, LK, NR, DAG>(a, i, c, rid, rv, acc);
-        hop_dir<3, SP, LK, NR, DAG>(a, i, c, rid, rv, acc);
+        hop_dir<0, SP, LK, NR, DAG, RL == 1>(a, i, c, rid, acc);
+        hop_dir<1, SP, LK, NR, DAG, RL == 1>(a, i, c, rid, acc);
+        hop_dir<2, SP, LK, NR, DAG, RL == 1>(a, i, c, rid, acc);
+        hop_dir<3, SP, LK, NR, DAG, RL == 1>(a, i, c, rid, acc);
     }
 
 #pragma unroll
@@ -329,15 +335,15 @@ __global__ void __launch_bounds__(256) dslash_kernel(DslashArgs a)
     switch (epi) {                                                                                \
     case EPI_PLAIN:                                                                               \
         hipLaunchKernelGGL((dslash_kernel<SP_, LK_, NR_, RL_, DAG_, EPI_PLAIN, XP_>), dim3(grid),  \
-                           dim3(block), 0, s, a);                                                 \
+                           dim3(block), a.lds, s, a);                                                 \
         return hipGetLastError();                                                                 \
     case EPI_XPAY:                                                                                \
         hipLaunchKernelGGL((dslash_kernel<SP_, LK_, NR_, RL_, DAG_, EPI_XPAY, XP_>), dim3(grid),   \
-                           dim3(block), 0, s, a);                                                 \
+                           dim3(block), a.lds, s, a);                                                 \
         return hipGetLastError();                                                                 \
     case EPI_CGUPD:                                                                               \
         hipLaunchKernelGGL((dslash_kernel<SP_, LK_, NR_, RL_, DAG_, EPI_CGUPD, XP_>), dim3(grid),  \
-                           dim3(block), 0, s, a);                                                 \
+                           dim3(block), a.lds, s, a);                                                 \
         return hipGetLastError();                                                                 \
     default:                                                                                      \
         return hipErrorInvalidValue;                                                              \

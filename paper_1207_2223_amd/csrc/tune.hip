@@ -177,7 +177,8 @@ static wd_status compare(wd_ctx *c, const char *a, const char *b, size_t bytes, 
 
 // Tuning cache: a text file named by the environment variable
 // WD_TUNE_CACHE, one line per tuned sweep:
-//   Lx Ly Lz Lt nrhs sp lk dag epi block nr rl remap us
+//   Lx Ly Lz Lt nrhs sp lk dag epi block nr rl remap occ us
+// (lines without the occ field, from older files, read as occ = 0)
 static std::string cache_key(const wd_ctx *c, int nrhs, int sp, int lk, int dag, int epi)
 {
     char b[128];
@@ -193,11 +194,19 @@ static bool cache_lookup(const char *path, const std::string &key, TuneCfg *cfg,
     char line[256];
     bool found = false;
     while (fgets(line, sizeof(line), f)) {
-        int d[9], b, nr, rl, rm;
+        int d[9], b, nr, rl, rm, oc = 0;
         double t;
-        if (sscanf(line, "%d %d %d %d %d %d %d %d %d %d %d %d %d %lf", &d[0], &d[1], &d[2], &d[3], &d[4],
-                   &d[5], &d[6], &d[7], &d[8], &b, &nr, &rl, &rm, &t) != 14)
+        double x[2];
+        const int nf = sscanf(line, "%d %d %d %d %d %d %d %d %d %d %d %d %d %lf %lf", &d[0], &d[1], &d[2],
+                              &d[3], &d[4], &d[5], &d[6], &d[7], &d[8], &b, &nr, &rl, &rm, &x[0], &x[1]);
+        if (nf == 15) {
+            oc = (int)x[0];
+            t = x[1];
+        } else if (nf == 14) {
+            t = x[0];
+        } else {
             continue;
+        }
         char k[128];
         snprintf(k, sizeof(k), "%d %d %d %d %d %d %d %d %d", d[0], d[1], d[2], d[3], d[4], d[5], d[6], d[7], d[8]);
         if (key == k) {  // the last matching line wins
@@ -205,6 +214,7 @@ static bool cache_lookup(const char *path, const std::string &key, TuneCfg *cfg,
             cfg->nr = nr;
             cfg->rl = rl;
             cfg->remap = rm;
+            cfg->occ = oc;
             *us = t;
             found = true;
         }
@@ -217,7 +227,7 @@ static void cache_store(const char *path, const std::string &key, const TuneCfg 
 {
     FILE *f = fopen(path, "a");
     if (!f) return;
-    fprintf(f, "%s %d %d %d %d %.3f\n", key.c_str(), cfg.block, cfg.nr, cfg.rl, cfg.remap, us);
+    fprintf(f, "%s %d %d %d %d %d %.3f\n", key.c_str(), cfg.block, cfg.nr, cfg.rl, cfg.remap, cfg.occ, us);
     fclose(f);
 }
 
@@ -275,13 +285,14 @@ extern "C" wd_status wd_tune(wd_ctx *c, int nrhs, int prec, char *report, size_t
             TuneCfg cc;
             double us = 0;
             if (cache_lookup(cache, cache_key(c, nrhs, sp, lk, k.dag, k.epi), &cc, &us) &&
-                dslash_shape_supported(sp, cc.nr, cc.rl)) {
+                dslash_shape_supported(sp, cc.nr, cc.rl) && (cc.occ == 0 || (cc.occ >= 2 && cc.occ <= kMaxOcc))) {
                 c->tuned[sweep_key(sp, lk, k.dag, k.epi)] = cc;
                 c->tune_gen++;
                 char line[256];
                 snprintf(line, sizeof(line),
-                         "%s;sp=%d;lk=%d;nrhs=%d;block=%d;nr=%d;rl=%d;remap=%d;us=%.2f;GB/s=0.0;candidates=0;rejected=0\n",
-                         k.name, sp, lk, nrhs, cc.block, cc.nr, cc.rl, cc.remap, us);
+                         "%s;sp=%d;lk=%d;nrhs=%d;block=%d;nr=%d;rl=%d;remap=%d;occ=%d;us=%.2f;GB/s=0.0;candidates=0;"
+                         "rejected=0\n",
+                         k.name, sp, lk, nrhs, cc.block, cc.nr, cc.rl, cc.remap, cc.occ, us);
                 rep += line;
                 continue;
             }
@@ -295,8 +306,19 @@ extern "C" wd_status wd_tune(wd_ctx *c, int nrhs, int prec, char *report, size_t
         double best = 1e30;
         TuneCfg bestc = cands[0];
         int rejected = 0;
-        for (size_t q = 0; q < cands.size(); q++) {
-            const TuneCfg &cf = cands[q];
+        // second pass: the best shape of the first, with at most occ
+        // work-groups per CU (fewer waves in flight share each L2 better)
+        std::vector<TuneCfg> list = cands;
+        const size_t nfirst = list.size();
+        for (size_t q = 0;; q++) {
+            if (q == nfirst && best < 1e30)
+                for (int oc = 2; oc <= kMaxOcc; oc++) {
+                    TuneCfg v = bestc;
+                    v.occ = oc;
+                    list.push_back(v);
+                }
+            if (q >= list.size()) break;
+            const TuneCfg cf = list[q];
             // correctness run on fresh inputs, with every output poisoned first
             // so that a shape that skips sites cannot pass on stale results
             if (k.epi == EPI_CGUPD) {
@@ -360,9 +382,10 @@ extern "C" wd_status wd_tune(wd_ctx *c, int nrhs, int prec, char *report, size_t
         const double gbs = sweep_bytes(c, swb) / (best * 1e-3) / 1e9;
         char line[256];
         snprintf(line, sizeof(line),
-                 "%s;sp=%d;lk=%d;nrhs=%d;block=%d;nr=%d;rl=%d;remap=%d;us=%.2f;GB/s=%.1f;candidates=%zu;rejected=%d\n",
-                 k.name, sp, lk, nrhs, bestc.block, bestc.nr, bestc.rl, bestc.remap, best * 1e3, gbs,
-                 cands.size(), rejected);
+                 "%s;sp=%d;lk=%d;nrhs=%d;block=%d;nr=%d;rl=%d;remap=%d;occ=%d;us=%.2f;GB/s=%.1f;candidates=%zu;"
+                 "rejected=%d\n",
+                 k.name, sp, lk, nrhs, bestc.block, bestc.nr, bestc.rl, bestc.remap, bestc.occ, best * 1e3, gbs,
+                 list.size(), rejected);
         rep += line;
     }
     c->timing = was_timing;

@@ -47,6 +47,30 @@ __device__ __forceinline__ uint32_t cvt_pk_f16(float lo, float hi)
 }
 typedef _Float16 half4_t __attribute__((ext_vector_type(4)));
 
+// Load of a T at byte offset off (32 bits: one chunk array is below 4 GiB)
+// from base.  With UNI (base the same in every lane) the base is pinned to
+// scalar registers, so that the load takes the scalar-base form with a
+// 32-bit vector offset; otherwise the compiler folds base + chunk stride
+// into a 64-bit address computed per lane.  The offset must be formed in
+// the same basic block as the load (see pin_v) for that form to be chosen.
+// Opaque copy of a 32-bit value: keeps an offset computed at its use, where
+// the compiler would otherwise hoist it as a 64-bit value.
+__device__ __forceinline__ uint32_t pin_v(uint32_t v)
+{
+    asm("" : "+v"(v));
+    return v;
+}
+
+template <typename T, bool UNI>
+__device__ __forceinline__ T ld_off(const char *base, uint32_t off)
+{
+    typedef const __attribute__((address_space(1))) char gchar;
+    typedef const __attribute__((address_space(1))) T gT;
+    gchar *g = (gchar *)base;
+    if constexpr (UNI) asm("" : "+s"(g));
+    return *(gT *)(g + off);
+}
+
 // Exact division by a runtime constant d for 0 <= n < 2^31 by a multiply and
 // a shift (Granlund & Montgomery, PLDI 1994): with l = ceil(log2 d) and
 // m = ceil(2^(31+l) / d), floor(n/d) = (n * m) >> (31 + l).
@@ -365,10 +389,11 @@ template <> struct LinkIO<LK_F32_12> {
     static constexpr size_t chunk_bytes = 16;
     __device__ static __forceinline__ void load(const char *U, int cs, int blk, int i, float u[18])
     {
-        const float4 *p = reinterpret_cast<const float4 *>(U) + (size_t)blk * 3 * cs;
+        const char *p = U + (size_t)blk * 3 * cs * 16;
+        const uint32_t off = (uint32_t)i * 16u;
 #pragma unroll
         for (int k = 0; k < 3; k++) {
-            float4 w = p[(size_t)k * cs + i];
+            const flt4_t w = ld_off<flt4_t, true>(p + (size_t)k * cs * 16, off);
             u[4 * k] = w.x;
             u[4 * k + 1] = w.y;
             u[4 * k + 2] = w.z;
@@ -627,12 +652,13 @@ typedef _Float16 h2_t __attribute__((ext_vector_type(2)));
 template <bool ADJ>
 __device__ __forceinline__ void link_forms_f16(const char *U, int cs, int blk, int i, h2_t A[9], h2_t B[9])
 {
-    const half4_t *p = reinterpret_cast<const half4_t *>(U) + (size_t)blk * 3 * cs;
+    const char *p = U + (size_t)blk * 3 * cs * 8;
+    const uint32_t off = (uint32_t)i * 8u;
     float u[18];
     _Float16 hv[18];
 #pragma unroll
     for (int k = 0; k < 3; k++) {
-        const half4_t w = p[(size_t)k * cs + i];
+        const half4_t w = ld_off<half4_t, true>(p + (size_t)k * cs * 8, off);
 #pragma unroll
         for (int j = 0; j < 4; j++) {
             hv[4 * k + j] = w[j];
@@ -684,6 +710,16 @@ __device__ __forceinline__ void project_h2(const h2_t v[12], h2_t h[6])
     }
 }
 
+// x.lo * y.lo + x.hi * y.hi + 0 in one instruction: the three-operand form
+// takes the zero as an inline constant, where the builtin's accumulating
+// form would first move a zero into its destination.
+__device__ __forceinline__ float dot2_first(h2_t x, h2_t y)
+{
+    float d;
+    asm("v_dot2_f32_f16 %0, %1, %2, 0" : "=v"(d) : "v"(x), "v"(y));
+    return d;
+}
+
 // w = U h (or U^dag h) for both rows, FP32 results in the float layout of
 // su3_mul_half.
 __device__ __forceinline__ void su3_mul_half_dot2(const h2_t A[9], const h2_t B[9], const h2_t h[6], float w[12])
@@ -692,9 +728,9 @@ __device__ __forceinline__ void su3_mul_half_dot2(const h2_t A[9], const h2_t B[
     for (int r = 0; r < 2; r++)
 #pragma unroll
         for (int a = 0; a < 3; a++) {
-            float re = 0.f, im = 0.f;
+            float re = dot2_first(A[3 * a], h[3 * r]), im = dot2_first(B[3 * a], h[3 * r]);
 #pragma unroll
-            for (int b = 0; b < 3; b++) {
+            for (int b = 1; b < 3; b++) {
                 re = __builtin_amdgcn_fdot2(A[3 * a + b], h[3 * r + b], re, false);
                 im = __builtin_amdgcn_fdot2(B[3 * a + b], h[3 * r + b], im, false);
             }

@@ -73,17 +73,26 @@ struct DslashArgs {
     double *partial;       // partial[rid*pstride + pw_off + site/16] = sum |out|^2 (or |r|^2)
     int pstride;
     int pw_off;
+    unsigned lds;          // dynamic LDS bytes per work-group (unused by the kernel: caps occupancy)
 };
 
 // Launch shape of one stencil sweep: threads per work-group, RHS per lane
 // (nr), lanes per site (rl), tile order (remap: 0 dispatch order,
-// 1 contiguous tile range per XCD, 2 z-slab per XCD walked z-fastest).
+// 1 contiguous tile range per XCD, 2 z-slab per XCD walked z-fastest, ...),
+// and an optional cap on work-groups per CU (occ).
 struct TuneCfg {
     int block = 128;
     int nr = 1;
     int rl = 1;
     int remap = 1;
+    int occ = 0;  // 0, or at most occ work-groups per CU (enforced through dynamic LDS)
 };
+
+// LDS per CU on gfx950, and the dynamic LDS per work-group that lets at most
+// occ work-groups share a CU (occ in 2..kMaxOcc; 0 = no cap).
+constexpr unsigned kLdsPerCU = 160u * 1024u;
+constexpr int kMaxOcc = 8;
+inline unsigned occ_lds_bytes(int occ) { return occ > 0 ? kLdsPerCU / (unsigned)(occ + 1) + 1024u : 0u; }
 
 hipError_t dslash_launch(const DslashArgs &a, int sp, int lk, int nr, int rl, int dag, int epi,
                          int block, int grid, hipStream_t s);

@@ -52,6 +52,10 @@ def test_bad_dims_rejected_without_gpu():
     assert e.value.status == wd.WD_ERR_DIMS
     assert wd.wd_bytes_required((3, 4, 4, 4), 1) == 0
     assert wd.wd_bytes_required((16, 16, 16, 32), 1) > 0
+    # one parity's 16-byte chunk array must stay addressable with 32-bit
+    # byte offsets: 152^4 (Vh = 266887168) fits, 154^4 (Vh = 281224328) not
+    assert wd.wd_bytes_required((152, 152, 152, 152), 1) > 0
+    assert wd.wd_bytes_required((154, 154, 154, 154), 1) == 0
 
 
 def test_solver_defaults():

@@ -24,7 +24,8 @@ def _expected_candidates(dims, code, nrhs):
     y-stripes, t-slab walked t-fastest in two orders, z-slab with the RHS
     groups outermost}, where the z-slab orders need Lz % 8 == 0, the t-slab
     orders Lt % 8 == 0, and all a whole number of tiles per plane and per
-    stripe."""
+    stripe; then the best of these with a cap of 2..8 work-groups per CU
+    (7 more)."""
     f64 = (code & 0xF) == 0
     shapes = [(1, 1), (2, 1), (1, 2), (2, 2), (1, 4), (2, 4)] if f64 else \
         [(nr, rl) for rl in (1, 2, 4) for nr in (1, 2, 3, 4)]
@@ -40,7 +41,7 @@ def _expected_candidates(dims, code, nrhs):
                 if rm >= 2 and not (slab % 8 == 0 and plane % spb == 0 and (plane // spb) % ns == 0):
                     continue
                 n += 1
-    return n
+    return n + 7
 
 
 @pytest.mark.parametrize("prec", ["F64", "F32", "F16", "F16L", "F16R", "I16"])
@@ -63,8 +64,9 @@ def test_tuner_all_shapes_bitwise_and_tuned_solve_identical(wd, oracle, prec, di
     assert all(r["candidates"] == _expected_candidates(dims, code, nrhs) for r in rows)
     for r in rows:
         note(f"{prec} {r['sweep']}: block {r['block']} nr {r['nr']} rl {r['rl']} remap {r['remap']} "
-             f"{r['candidates']} candidates, {r['rejected']} rejected")
+             f"occ {r['occ']} {r['candidates']} candidates, {r['rejected']} rejected")
         assert r["rejected"] == 0 and r["candidates"] > 1
+        assert r["occ"] == 0 or 2 <= r["occ"] <= 8
     if code != wd.WD_F64:
         wd.wd_tune(lat.ctx, nrhs, wd.WD_F64)
     B = li.gaussian_spinor(V // 2, seed=42, nrhs=nrhs)
@@ -91,4 +93,36 @@ def test_bench_dslash_runs(wd):
     for epi in (0, 1, 2):
         ms, by = wd.wd_bench_dslash(lat.ctx, 3, wd.WD_F16, epi=epi, iters=3, tuned=0)
         assert ms > 0 and by > 0
+    lat.close()
+
+
+def test_cached_shapes_with_work_group_cap(wd, tmp_path, monkeypatch):
+    """Shapes read from the tuning cache file, here with a cap of 3 and 5
+    work-groups per CU (and one line in the older format without the cap
+    field), drive a tuned solve that equals the default-shape solve bit for
+    bit."""
+    dims = (8, 8, 8, 8)
+    V = li.volume(dims)
+    U = li.random_su3_field(dims, 0.5, seed=51)
+    lat = wd.Lattice(dims)
+    lat.gauge_load(dev(U), recon=12)
+    key = "8 8 8 8 3 2 2"  # dims, nrhs 3, FP16 spinors, FP32 12-real links
+    cache = tmp_path / "tune.txt"
+    cache.write_text(f"{key} 0 0 128 2 1 1 3 1.0\n"     # D_oe: block 128, nr 2, rl 1, cap 3
+                     f"{key} 0 1 256 1 2 1 5 1.0\n"     # xpay: block 256, nr 1, rl 2, cap 5
+                     f"{key} 1 0 64 3 1 0 1.0\n"        # D_oe^dag: older line, no cap
+                     f"{key} 1 2 128 1 1 1 4 1.0\n")    # CG update: cap 4
+    monkeypatch.setenv("WD_TUNE_CACHE", str(cache))
+    rows = wd.wd_tune(lat.ctx, 3, wd.WD_F16)
+    assert [r["occ"] for r in rows] == [3, 5, 0, 4]
+    assert [r["candidates"] for r in rows] == [0, 0, 0, 0]
+    B = li.gaussian_spinor(V // 2, seed=52, nrhs=3)
+    kap = [0.15, 0.153, 0.156]
+    X0 = empty_like_dev(B)
+    X1 = empty_like_dev(B)
+    s0, st0 = lat.cg_solve(X0, dev(B), kap, wd.solver_params(prec=wd.WD_F16, tuned=0))
+    s1, st1 = lat.cg_solve(X1, dev(B), kap, wd.solver_params(prec=wd.WD_F16, tuned=1))
+    assert s0 == wd.WD_OK and s1 == wd.WD_OK
+    assert [s["iters"] for s in st0] == [s["iters"] for s in st1]
+    assert np.array_equal(host(X0), host(X1))
     lat.close()
