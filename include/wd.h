@@ -345,7 +345,8 @@ wd_status wd_timing_report(wd_ctx *c, char *buf, size_t len);
 /* Autotune the launch shapes of the even-odd solver's four stencil sweeps for
  * nrhs right-hand sides in precision prec (wd_prec, | WD_LINKS_F16).  Every
  * supported shape (threads per work-group, RHS per lane, lanes per site, XCD
- * tile order) is timed with HIP events on synthetic fields; a shape whose
+ * tile order) is timed with HIP events on synthetic fields, then the fastest
+ * with a cap of 2..8 work-groups per compute unit; a shape whose
  * vectors or norm partials are not bitwise identical to the reference shape
  * is rejected.  The fastest shapes are kept in the context and used by
  * solves with wd_solver_params.tuned = 1.  report: HOST buffer of len bytes
@@ -362,6 +363,33 @@ wd_status wd_tune(wd_ctx *c, int nrhs, int prec, char *report, size_t len);
  * time per sweep, *bytes (HOST, may be NULL) its algorithmic bytes. */
 wd_status wd_bench_dslash(wd_ctx *c, int nrhs, int prec, int epi, int iters, int tuned,
                           double *ms, double *bytes);
+
+/* Faces of a lattice cut along t (the paper's next step, Sec. 4 end: running
+ * over several GPUs).  For one sweep of the hopping term with output parity
+ * out_parity (WD_EVEN or WD_ODD; D_eo or D_oe, H^dag if dagger), a GPU that
+ * holds slices 0..Lt-1 of a t-decomposed lattice sends its neighbours
+ *   forward face:  (1 -+ g_t) psi on the input sites of slice 0,
+ *   backward face: U_t^dag (1 +- g_t) psi on the input sites of slice Lt-1,
+ * each as the two independent spin rows of the projection (half a spinor;
+ * the backward one colour-rotated by the sender), and adds the faces it
+ * receives into its output sites on slices Lt-1 and 0.  On one GPU the
+ * lattice wraps onto itself, so the faces packed from psi are the ones
+ * received.  wd_faces_apply packs the faces of in (DEVICE, canonical parity
+ * field [Vh][4][3] complex128 of the input parity, cb order) in the spinor
+ * format of prec (WD_F64, WD_F32 or WD_F16, | WD_LINKS_F16 / _R18), then
+ * writes to out (DEVICE, same layout, output parity) the face terms alone:
+ * the t-neighbour terms across the cut on slices Lt-1 and 0, zero on every
+ * other site.  Needs a loaded gauge field; WD_ERR_ARG for WD_FULL, WD_I16
+ * or a bad code. */
+wd_status wd_faces_apply(wd_ctx *c, double *out, const double *in, int out_parity, int dagger, int prec);
+
+/* Face micro-benchmark on the context's lattice: `iters` packs of both faces,
+ * then `iters` face updates, in the spinor format of prec; *pack_ms and
+ * *apply_ms (HOST) receive the HIP-event time of one, *pack_bytes and
+ * *apply_bytes (HOST, may be NULL) the bytes one must move (spinor slices,
+ * links and faces, each once). */
+wd_status wd_bench_faces(wd_ctx *c, int prec, int iters, double *pack_ms, double *apply_ms,
+                         double *pack_bytes, double *apply_bytes);
 
 /* Message of the last failed call on this thread (never NULL). */
 const char *wd_last_error(void);

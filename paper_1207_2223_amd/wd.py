@@ -78,6 +78,9 @@ _SIGS = {
     "wd_tune": (C.c_int, [_P, C.c_int, C.c_int, C.c_char_p, C.c_size_t]),
     "wd_bench_dslash": (C.c_int, [_P, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int,
                                   C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "wd_faces_apply": (C.c_int, [_P, _P, _P, C.c_int, C.c_int, C.c_int]),
+    "wd_bench_faces": (C.c_int, [_P, C.c_int, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                 C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "wd_session_create": (C.c_int, [_P, C.c_int, C.POINTER(wd_solver_params), C.POINTER(_P)]),
     "wd_session_destroy": (C.c_int, [_P]),
     "wd_session_add": (C.c_int, [_P, _P, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int32)]),
@@ -290,6 +293,20 @@ def wd_bench_dslash(ctx, nrhs, prec, epi=0, iters=20, tuned=1):
     return ms.value, by.value
 
 
+def wd_faces_apply(ctx, out, inp, out_parity, dagger=0, prec=WD_F64):
+    """Face terms across a cut along t of one hopping sweep (include/wd.h)."""
+    _c128(out, (4, 3), "out")
+    _c128(inp, (4, 3), "in")
+    _check(lib().wd_faces_apply(ctx, _ptr(out), _ptr(inp), int(out_parity), int(dagger), int(prec)))
+
+
+def wd_bench_faces(ctx, prec, iters=20):
+    """(pack ms, update ms, pack bytes, update bytes) of the face kernels."""
+    v = [C.c_double() for _ in range(4)]
+    _check(lib().wd_bench_faces(ctx, int(prec), int(iters), *[C.byref(x) for x in v]))
+    return tuple(x.value for x in v)
+
+
 def wd_session_create(ctx, max_rhs, params=None):
     h = C.c_void_p()
     p = params if params is not None else wd_solver_defaults()
@@ -483,6 +500,12 @@ class Lattice:
 
     def mdagm(self, out, inp, kappa, eo=1):
         wd_mdagm(self.ctx, out, inp, kappa, eo)
+
+    def faces_apply(self, out, inp, out_parity, dagger=0, prec=WD_F64):
+        for name, t in (("out", out), ("in", inp)):
+            if tuple(t.shape) != (self.V // 2, 4, 3):
+                raise ValueError(f"{name} has shape {tuple(t.shape)}, expected ({self.V // 2}, 4, 3)")
+        wd_faces_apply(self.ctx, out, inp, out_parity, dagger, prec)
 
     def cg_solve(self, x, phi, kappa, params=None, check=True):
         return wd_cg_solve(self.ctx, x, phi, kappa, params, check)

@@ -37,3 +37,22 @@ def test_more_than_one_gpu_is_refused():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
                        capture_output=True, text=True, timeout=60)
     assert r.returncode == 2 and "one GPU" in r.stderr
+
+
+def test_shape_table_lines_are_valid_launch_shapes():
+    """The MI355X launch-shape table bench.py reuses: one line per sweep,
+    dims nrhs sp lk dag epi block nr rl remap occ us, every field in range."""
+    import bench
+    seen = set()
+    for line in open(bench.SHAPE_TABLE):
+        f = line.split()
+        assert len(f) == 15, line
+        d = [int(x) for x in f[:14]]
+        lx, ly, lz, lt, nrhs, sp, lk, dag, epi, block, nr, rl, remap, occ = d
+        assert all(L % 2 == 0 for L in (lx, ly, lz, lt)) and 1 <= nrhs <= 64
+        assert sp in (0, 1, 2, 3) and lk in (0, 1, 2, 3, 4) and dag in (0, 1) and epi in (0, 1, 2)
+        assert block in (64, 128, 256) and nr in (1, 2, 3, 4) and rl in (1, 2, 4)
+        assert 0 <= remap < 8 and (occ == 0 or 2 <= occ <= 8) and float(f[14]) > 0
+        seen.add(tuple(d[:9]))
+    # the four sweeps of the c3 workload's FP16 solve are all there
+    assert all((32, 32, 32, 64, 12, 2, 2, dag, epi) in seen for dag, epi in ((0, 0), (0, 1), (1, 0), (1, 2)))
