@@ -185,7 +185,7 @@ def test_exp_minus_dh_averages_to_one(wd, prec, chrono):
     code = {"F64": wd.WD_F64, "F16": wd.WD_F16}[prec]
     vals, acc = [], 0
     for traj in range(200):
-        hp = wd.hmc_params(5.6, 0.12, 0.5, 8, seed=73, traj=traj,
+        hp = wd.hmc_params(5.6, 0.12, 0.5, 20, seed=73, traj=traj,
                            force=wd.solver_params(tol=1e-10, prec=code),
                            h=wd.solver_params(tol=1e-12), chrono=chrono)
         r = wd.hmc_trajectory(lat.ctx, U, hp)
