@@ -124,6 +124,8 @@ def parse():
                     help="reliable-update threshold of the mixed solves (c1-c3, c6)")
     ap.add_argument("--chrono", type=int, default=1, choices=(0, 1, 2),
                     help="c5: force-solve starting vectors (0 zero, 1 previous, 2 extrapolated)")
+    ap.add_argument("--poll", type=int, default=8,
+                    help="CG iterations between the host's residual checks (c5 force solves)")
     ap.add_argument("--retune", action="store_true",
                     help="time every launch shape again instead of reusing the MI355X shape table")
     ap.add_argument("--tune-only", action="store_true",
@@ -570,7 +572,7 @@ def bench_hmc(args, wd, torch):
     Ud = torch.from_numpy(U).to(dev)
     lat = wd.Lattice(dims)
     lat.gauge_load(Ud, recon=12)
-    force = wd.solver_params(prec=PRECS[args.prec], tol=1e-8, maxiter=20000, tuned=args.tuned)
+    force = wd.solver_params(prec=PRECS[args.prec], tol=1e-8, maxiter=20000, tuned=args.tuned, poll=args.poll)
     hsol = wd.solver_params(prec=0, tol=1e-10, maxiter=20000, tuned=args.tuned)
     if args.tuned:
         for code in {PRECS[args.prec], 0}:
