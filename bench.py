@@ -284,10 +284,10 @@ def bench_solve(args, wd, torch):
     dom, roof, sten = kernel_roofline(report, t_inst)
     roof["traffic"] = counter_traffic(args.workload, args.prec, dom["name"])
 
-    stream = dsl = shard = None
+    stream = dsl = dsl_err = shard = None
     if not args.no_dslash:
         stream = copy_bandwidth(torch)
-        dsl = dslash_section(wd, Ud, dims, stream, PRECS[args.prec], nrhs, tuned=args.tuned)
+        dsl, dsl_err = dslash_section(wd, Ud, dims, stream, PRECS[args.prec], nrhs, tuned=args.tuned)
         shard = shard_section(wd, Ud, dims, tuned=args.tuned)
 
     fp64 = None
@@ -329,6 +329,7 @@ def bench_solve(args, wd, torch):
         "mixed_vs_fp64": (value / fp64["solves_per_s"]) if fp64 else None,
         "stream_copy_GB_s": stream,
         "dslash": dsl,
+        "stencil_rel_err_vs_fp64": dsl_err,
         "shard_t8": shard,
         "cpu_baseline": cpu,
     })
@@ -361,9 +362,24 @@ def dslash_section(wd, Ud, dims, stream_gbs, prec, nrhs, tuned=1):
     and FP16 with FP16 links, and the workload's RHS count in its precision.
     Algorithmic GB/s, its fraction of the 8 TB/s peak and of the measured copy
     bandwidth, GFLOP/s at 1320 flop per site and RHS; autotuned shapes."""
+    import torch
     Vh = int(np.prod(dims)) // 2
     lat = wd.Lattice(dims)
     lat.gauge_load(Ud, recon=12)
+    # the error of each format against the FP64 stencil (itself equal to the
+    # oracle's to 1e-12) on one Gaussian source: relative 2-norm of D_oe psi
+    g = torch.Generator(device="cuda").manual_seed(5)
+    psi = torch.complex(torch.randn((Vh, 4, 3), dtype=torch.float64, device="cuda", generator=g),
+                        torch.randn((Vh, 4, 3), dtype=torch.float64, device="cuda", generator=g))
+    ref = torch.empty_like(psi)
+    out = torch.empty_like(psi)
+    lat.dslash(ref, psi, wd.WD_ODD, 0, wd.WD_F64)
+    err = {}
+    for name, code in PRECS.items():
+        lat.dslash(out, psi, wd.WD_ODD, 0, code)
+        err[name] = float(torch.linalg.vector_norm(out - ref) / torch.linalg.vector_norm(ref))
+    log("[bench] stencil error vs FP64: " + ", ".join(f"{k} {v:.2e}" for k, v in err.items()))
+    del psi, ref, out
     rows = []
     cases = [("f64", 0, 1), ("f32", 1, 1), ("f16", 2, 1), ("f16l16", 2 | 0x10, 1)]
     cases.append((next(k for k, v in PRECS.items() if v == prec), prec, nrhs))
@@ -374,12 +390,13 @@ def dslash_section(wd, Ud, dims, stream_gbs, prec, nrhs, tuned=1):
             ms, by = wd.wd_bench_dslash(lat.ctx, n, code, epi=epi, iters=20, tuned=tuned)
             gbs = by / (ms * 1e-3) / 1e9
             rows.append({"prec": name, "nrhs": n, "sweep": ename, "us": ms * 1e3, "bytes": by,
+                         "rel_err_vs_fp64": err[name],
                          "GB_s": gbs, "frac_peak": gbs / HBM_PEAK_GBS, "frac_copy": gbs / stream_gbs,
                          "GFLOP_s": FLOP_SITE * Vh * n / (ms * 1e-3) / 1e9})
             log(f"[bench] dslash {name} nrhs {n} {ename}: {ms * 1e3:.1f} us {gbs:.0f} GB/s "
                 f"({gbs / HBM_PEAK_GBS * 100:.1f} % of peak, {gbs / stream_gbs * 100:.1f} % of copy)")
     lat.close()
-    return rows
+    return rows, err
 
 
 def shard_section(wd, Ud, dims, lt=8, tuned=1):
