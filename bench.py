@@ -64,7 +64,7 @@ PRECS = {"f64": 0, "f32": 1, "f16": 2, "f16l16": 2 | 0x10, "f32l16": 1 | 0x10,
 DTYPE = {"f64": "f64", "f32": "f32", "f16": "f16+norm/f32", "f16l16": "f16+norm/f32",
          "f32l16": "f32", "f16r18": "f16+norm/f32", "f32r18": "f32", "i16": "i16+norm/f32",
          "i16l16": "i16+norm/f32"}
-DEFAULT_STEPS = {"c4_serving": (1, 1), "c5_hmc": (20, 30)}
+DEFAULT_STEPS = {"c4_serving": (1, 1), "c5_hmc": (40, 60)}
 
 
 def log(msg):
