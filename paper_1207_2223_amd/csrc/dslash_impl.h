@@ -71,6 +71,21 @@ __device__ __forceinline__ float load_nb_half(const char *f, int cs, int j, _Flo
     return ld_off<float, UNI>(f + (size_t)48 * cs, UNI ? pin_v((uint32_t)j * 4u) : (uint32_t)j * 4u);
 }
 
+// int16 neighbour spinor as stored (widened to int), and its quantisation
+// step (norm / 32767).
+template <bool UNI>
+__device__ __forceinline__ float load_nb_i16(const char *f, int cs, int j, int v[24])
+{
+    const uint32_t off = UNI ? pin_v((uint32_t)j * 16u) : (uint32_t)j * 16u;
+#pragma unroll
+    for (int k = 0; k < 3; k++) {
+        const short8_t w = ld_off<short8_t, UNI>(f + (size_t)k * cs * 16, off);
+#pragma unroll
+        for (int q = 0; q < 8; q++) v[8 * k + q] = w[q];
+    }
+    return SpinorIO<SP_I16>::step(ld_off<float, UNI>(f + (size_t)48 * cs, UNI ? pin_v((uint32_t)j * 4u) : (uint32_t)j * 4u));
+}
+
 // FP16 neighbour spinor as 12 (re, im) half2 pairs, and its per-site norm.
 template <bool UNI>
 __device__ __forceinline__ float load_nb_h2(const char *f, int cs, int j, h2_t v[12])
@@ -145,6 +160,10 @@ __device__ __forceinline__ void hop_dir(const DslashArgs &a, int i, const int c[
                 _Float16 v[24];
                 sc = load_nb_half<UNI>(a.in + rid[r] * a.in_rs, cs, j, v);
                 project_mix<MU, SF>(v, h);
+            } else if constexpr (SP == SP_I16) {
+                int v[24];
+                sc = load_nb_i16<UNI>(a.in + rid[r] * a.in_rs, cs, j, v);
+                project_int<MU, SF>(v, h);
             } else {
                 real v[24];
                 sc = load_nb<SP>(a.in + rid[r] * a.in_rs, cs, j, v);
@@ -167,6 +186,10 @@ __device__ __forceinline__ void hop_dir(const DslashArgs &a, int i, const int c[
                 _Float16 v[24];
                 sc = load_nb_half<UNI>(a.in + rid[r] * a.in_rs, cs, j, v);
                 project_mix<MU, SB>(v, h);
+            } else if constexpr (SP == SP_I16) {
+                int v[24];
+                sc = load_nb_i16<UNI>(a.in + rid[r] * a.in_rs, cs, j, v);
+                project_int<MU, SB>(v, h);
             } else {
                 real v[24];
                 sc = load_nb<SP>(a.in + rid[r] * a.in_rs, cs, j, v);

@@ -536,6 +536,44 @@ __device__ __forceinline__ void project_mix(const _Float16 v[24], float h[12])
     }
 }
 
+// project() on int16 inputs: each component is an integer sum or difference
+// converted once (|a +- b| < 2^16, so both steps are exact and the value is
+// that of converting first and adding in FP32), one add and one convert
+// instead of two converts and an add.
+template <int MU, int S>
+__device__ __forceinline__ void project_int(const int v[24], float h[12])
+{
+    auto pm = [](int a, int b, int sgn) { return (float)(sgn > 0 ? a + b : a - b); };
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        const int p0r = v[2 * c], p0i = v[2 * c + 1];
+        const int p1r = v[6 + 2 * c], p1i = v[6 + 2 * c + 1];
+        const int p2r = v[12 + 2 * c], p2i = v[12 + 2 * c + 1];
+        const int p3r = v[18 + 2 * c], p3i = v[18 + 2 * c + 1];
+        if (MU == 0) {
+            h[2 * c] = pm(p0r, p3i, -S);
+            h[2 * c + 1] = pm(p0i, p3r, S);
+            h[6 + 2 * c] = pm(p1r, p2i, -S);
+            h[6 + 2 * c + 1] = pm(p1i, p2r, S);
+        } else if (MU == 1) {
+            h[2 * c] = pm(p0r, p3r, -S);
+            h[2 * c + 1] = pm(p0i, p3i, -S);
+            h[6 + 2 * c] = pm(p1r, p2r, S);
+            h[6 + 2 * c + 1] = pm(p1i, p2i, S);
+        } else if (MU == 2) {
+            h[2 * c] = pm(p0r, p2i, -S);
+            h[2 * c + 1] = pm(p0i, p2r, S);
+            h[6 + 2 * c] = pm(p1r, p3i, S);
+            h[6 + 2 * c + 1] = pm(p1i, p3r, -S);
+        } else {
+            h[2 * c] = pm(p0r, p2r, S);
+            h[2 * c + 1] = pm(p0i, p2i, S);
+            h[6 + 2 * c] = pm(p1r, p3r, S);
+            h[6 + 2 * c + 1] = pm(p1i, p3i, S);
+        }
+    }
+}
+
 // acc += full 4-spinor rebuilt from the colour-rotated half spinor w.
 template <int MU, int S, typename T>
 __device__ __forceinline__ void accumulate(T acc[24], const T w[12])
