@@ -120,7 +120,7 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--tuned", type=int, default=1, help="autotune launch shapes before timing")
     ap.add_argument("--requests", type=int, default=None, help="c4: requests per pass")
-    ap.add_argument("--delta", type=float, default=0.02,
+    ap.add_argument("--delta", type=float, default=0.01,
                     help="reliable-update threshold of the mixed solves (c1-c3, c6)")
     ap.add_argument("--chrono", type=int, default=1, choices=(0, 1, 2),
                     help="c5: force-solve starting vectors (0 zero, 1 previous, 2 extrapolated)")
