@@ -56,3 +56,24 @@ def test_shape_table_lines_are_valid_launch_shapes():
         seen.add(tuple(d[:9]))
     # the four sweeps of the c3 workload's FP16 solve are all there
     assert all((32, 32, 32, 64, 12, 2, 2, dag, epi) in seen for dag, epi in ((0, 0), (0, 1), (1, 0), (1, 2)))
+
+
+def test_shape_table_is_used_through_a_private_copy(monkeypatch):
+    """bench.py points WD_TUNE_CACHE at a private copy of the table (the
+    library appends to it), and leaves an explicit WD_TUNE_CACHE or
+    --retune alone."""
+    import os
+    import sys
+    import bench
+    monkeypatch.setattr(sys, "argv", ["bench.py"])
+    monkeypatch.delenv("WD_TUNE_CACHE", raising=False)
+    bench.use_shape_table(bench.parse())
+    dst = os.environ["WD_TUNE_CACHE"]
+    assert dst != bench.SHAPE_TABLE and open(dst).read() == open(bench.SHAPE_TABLE).read()
+    monkeypatch.setenv("WD_TUNE_CACHE", "/nonexistent/keep")
+    bench.use_shape_table(bench.parse())
+    assert os.environ["WD_TUNE_CACHE"] == "/nonexistent/keep"
+    monkeypatch.delenv("WD_TUNE_CACHE")
+    monkeypatch.setattr(sys, "argv", ["bench.py", "--retune"])
+    bench.use_shape_table(bench.parse())
+    assert "WD_TUNE_CACHE" not in os.environ
