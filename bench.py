@@ -128,6 +128,9 @@ def parse():
                     help="CG iterations between the host's residual checks (c5 force solves)")
     ap.add_argument("--retune", action="store_true",
                     help="time every launch shape again instead of reusing the MI355X shape table")
+    ap.add_argument("--dslash-only", action="store_true",
+                    help="only the stencil-alone section of the workload's lattice (for profiling); "
+                         "prints its rows as one JSON line")
     ap.add_argument("--tune-only", action="store_true",
                     help="autotune (filling WD_TUNE_CACHE when set) and exit")
     ap.add_argument("--copy-probe", action="store_true",
@@ -258,6 +261,11 @@ def bench_solve(args, wd, torch):
         torch.cuda.synchronize()
         log("[bench] copy probe: 1 GiB read + 1 GiB written by one copy kernel")
         del a, b
+    if args.dslash_only:
+        lat.close()
+        rows, err = dslash_section(wd, Ud, dims, copy_bandwidth(torch), PRECS[args.prec], nrhs, tuned=args.tuned)
+        print(json.dumps({"workload": args.workload, "dslash": rows, "stencil_rel_err_vs_fp64": err}), flush=True)
+        return None
     for k in range(args.warmup):
         st, stats = solve(params)
         log(f"[bench] warmup {k}: status {st} iters {[s['iters'] for s in stats][:4]}...")
