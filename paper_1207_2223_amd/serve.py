@@ -14,7 +14,10 @@ slots are allocated when a request needs them (the session grows) and given
 back when its lattice's queue drains (it shrinks, or is freed when idle), so
 the bytes charged against the global budget -- session slots plus each
 request's input/output buffers -- are bytes actually held on the device; each
-admission is also checked against the device's free memory.
+admission is also checked against the device's free memory.  A lattice with
+nothing running whose queue head does not fit gives back its idle slots
+before it waits, so idle sessions never hold bytes another lattice's request
+needs.
 
 The scheduler core (Admission, Server) is independent of the device: the
 executor interface is `max_slots`, `slot_bytes`, `io_bytes(nrhs)`,
@@ -148,6 +151,16 @@ class Server:
                         if self.closed and not self.queues[name]:
                             self.adm.give(ex.shrink())
                             return
+                        if self.queues[name]:
+                            # idle, and the queue head does not fit: give back
+                            # the idle slots before waiting, or two lattices
+                            # that each hold idle slots could wait for each
+                            # other's bytes forever
+                            freed = ex.shrink()
+                            if freed:
+                                self.adm.give(freed)
+                                self.cv.notify_all()
+                                continue
                         self.cv.wait(timeout=0.05)
                 self.max_batch[name] = max(self.max_batch[name], sum(r.nrhs for r in running))
                 ex.step(self.k)

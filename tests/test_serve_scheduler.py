@@ -186,3 +186,27 @@ def test_latency_accounting_with_arrivals():
         assert r.admitted >= r.arrival - 1e-3
     lat = sorted(r.latency for r in reqs)
     assert abs(summ["latency_p50_s"] - float(np.percentile(lat, 50))) < 1e-12
+
+
+def test_idle_slots_are_released_when_two_lattices_block_each_other():
+    # Two lattices each finish a 2-RHS request and keep 2 idle slots while
+    # their next requests (3 RHS each) wait.  The budget (4 slots plus io)
+    # fits one 3-RHS request at a time only if the other lattice's idle slots
+    # are given back; otherwise both heads would wait for each other forever.
+    ex = {"a": FakeExecutor(4, step_time=0.002), "b": FakeExecutor(4, step_time=0.002)}
+    adm = Admission(4 * 100 + 4 * 10)
+    srv = Server(ex, adm, k_iters=8)
+    phi2, phi3 = np.ones((2, 4, 4, 3), complex), np.ones((3, 4, 4, 3), complex)
+    reqs = [Request(0, "a", phi2, [0.15, 0.15], arrival=0.0),
+            Request(1, "b", phi2, [0.15, 0.15], arrival=0.0),
+            Request(2, "a", 2 * phi3, [0.15] * 3, arrival=0.001),
+            Request(3, "b", 3 * phi3, [0.15] * 3, arrival=0.001)]
+    out = {}
+    th = threading.Thread(target=lambda: out.update(summ=srv.run(reqs)), daemon=True)
+    th.start()
+    th.join(timeout=20)
+    assert not th.is_alive(), "scheduler deadlocked"
+    assert out["summ"]["completed"] == 4
+    for r in reqs:
+        assert np.array_equal(r.x, 2 * r.phi)
+    assert adm.peak <= 440 and adm.in_use == 0
