@@ -138,14 +138,17 @@ def _dims(dims):
     return _I32x4(*[int(v) for v in dims])
 
 
-def _ptr(t):
-    """Device pointer of a contiguous CUDA tensor."""
+def _ptr(t, info=None, name="tensor"):
+    """Device pointer of a contiguous CUDA tensor (on the context's device when
+    info is given)."""
     if t is None:
         return None
+    if info is not None:
+        _on_device(t, info, name)
     if not t.is_cuda:
-        raise ValueError("expected a CUDA (HIP) tensor")
+        raise ValueError(f"{name} must be a CUDA (HIP) tensor")
     if not t.is_contiguous():
-        raise ValueError("expected a contiguous tensor")
+        raise ValueError(f"{name} must be contiguous")
     return C.c_void_p(t.data_ptr())
 
 
@@ -165,6 +168,58 @@ def _c128(t, shape_tail, name):
     return t
 
 
+# Lattice and device of every live context and session, recorded at creation:
+# the library takes raw device pointers, so a tensor with too few sites, or on
+# another device, must be refused here before its pointer reaches a kernel.
+class _CtxInfo:
+    def __init__(self, dims, device):
+        self.dims = tuple(int(d) for d in dims)
+        self.V = int(np.prod(self.dims))
+        self.Vh = self.V // 2
+        self.device = int(device)
+
+
+_CTX = {}   # context handle value -> _CtxInfo
+_SESS = {}  # session handle value -> (_CtxInfo, eo)
+
+
+def _key(h):
+    return h.value if isinstance(h, C.c_void_p) else int(h)
+
+
+def _ctx_info(ctx):
+    info = _CTX.get(_key(ctx))
+    if info is None:
+        raise ValueError("unknown context handle (not from wd_create, or destroyed)")
+    return info
+
+
+def _sites(info, parity_or_eo, full_code):
+    """Sites of a field: V when parity_or_eo == full_code, else Vh."""
+    return info.V if parity_or_eo == full_code else info.Vh
+
+
+def _field(t, info, sites, tail, name, nrhs=None):
+    """complex128 tensor holding exactly (nrhs x) sites x tail (the device is
+    checked when its pointer is taken, after every size check)."""
+    _c128(t, tail, name)
+    per = sites * int(np.prod(tail))
+    want = per if nrhs is None else int(nrhs) * per
+    if t.numel() != want:
+        lead = f"{nrhs} x " if nrhs is not None else ""
+        raise ValueError(f"{name} has shape {tuple(t.shape)} ({t.numel()} elements), expected "
+                         f"{lead}{sites} sites x {tuple(tail)} ({want} elements)")
+    return t
+
+
+def _on_device(t, info, name):
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a CUDA (HIP) tensor")
+    idx = t.device.index if t.device.index is not None else 0
+    if idx != info.device:
+        raise ValueError(f"{name} is on device {idx}, the context on device {info.device}")
+
+
 # ---------------------------------------------------------------------------
 # C-ABI calls under their C names
 # ---------------------------------------------------------------------------
@@ -178,11 +233,13 @@ def wd_solver_defaults():
 def wd_create(dims, device=0, stream=None):
     h = C.c_void_p()
     _check(lib().wd_create(C.byref(h), _dims(dims), int(device), _stream_handle(stream)))
+    _CTX[_key(h)] = _CtxInfo(dims, device)
     return h
 
 
 def wd_destroy(ctx):
     _check(lib().wd_destroy(ctx))
+    _CTX.pop(_key(ctx), None)
 
 
 def wd_set_stream(ctx, stream=None):
@@ -190,35 +247,45 @@ def wd_set_stream(ctx, stream=None):
 
 
 def wd_gauge_load(ctx, U, flags=WD_RECON_18):
-    _c128(U, (4, 3, 3), "U")
-    _check(lib().wd_gauge_load(ctx, _ptr(U), int(flags)))
+    info = _ctx_info(ctx)
+    _field(U, info, info.V, (4, 3, 3), "U")
+    _check(lib().wd_gauge_load(ctx, _ptr(U, info, "U"), int(flags)))
 
 
 def wd_dslash(ctx, out, inp, out_parity, dagger=0, prec=WD_F64):
-    _c128(out, (4, 3), "out")
-    _c128(inp, (4, 3), "in")
-    _check(lib().wd_dslash(ctx, _ptr(out), _ptr(inp), int(out_parity), int(dagger), int(prec)))
+    info = _ctx_info(ctx)
+    n = _sites(info, int(out_parity), WD_FULL)
+    _field(out, info, n, (4, 3), "out")
+    _field(inp, info, n, (4, 3), "in")
+    _check(lib().wd_dslash(ctx, _ptr(out, info, "out"), _ptr(inp, info, "in"), int(out_parity),
+                           int(dagger), int(prec)))
 
 
 def wd_mdagm(ctx, out, inp, kappa, eo=1):
-    _c128(out, (4, 3), "out")
-    _c128(inp, (4, 3), "in")
-    _check(lib().wd_mdagm(ctx, _ptr(out), _ptr(inp), float(kappa), int(eo)))
+    info = _ctx_info(ctx)
+    n = info.Vh if eo else info.V
+    _field(out, info, n, (4, 3), "out")
+    _field(inp, info, n, (4, 3), "in")
+    _check(lib().wd_mdagm(ctx, _ptr(out, info, "out"), _ptr(inp, info, "in"), float(kappa), int(eo)))
 
 
 def wd_cg_solve(ctx, x, phi, kappa, params=None, check=True):
     """x, phi: complex128 [nrhs, sites, 4, 3] (or [sites, 4, 3]); kappa: float
     or sequence of nrhs floats.  Returns (status, list of stats dicts)."""
-    _c128(x, (4, 3), "x")
-    _c128(phi, (4, 3), "phi")
+    info = _ctx_info(ctx)
+    p = params if params is not None else wd_solver_defaults()
     nrhs = 1 if phi.dim() == 3 else phi.shape[0]
+    if tuple(x.shape) != tuple(phi.shape):
+        raise ValueError(f"x has shape {tuple(x.shape)}, phi {tuple(phi.shape)}: they must match")
+    n = info.Vh if p.eo else info.V
+    _field(phi, info, n, (4, 3), "phi", nrhs)
+    _field(x, info, n, (4, 3), "x", nrhs)
     ks = [float(kappa)] * nrhs if np.isscalar(kappa) else [float(k) for k in kappa]
     if len(ks) != nrhs:
         raise ValueError("one kappa per right-hand side")
     karr = (C.c_double * nrhs)(*ks)
-    p = params if params is not None else wd_solver_defaults()
     st = (wd_solver_stats * nrhs)()
-    status = lib().wd_cg_solve(ctx, _ptr(x), _ptr(phi), nrhs, karr, C.byref(p), st)
+    status = lib().wd_cg_solve(ctx, _ptr(x, info, "x"), _ptr(phi, info, "phi"), nrhs, karr, C.byref(p), st)
     if check and status not in (WD_OK, WD_ERR_NOCONV, WD_ERR_NAN):
         _check(status)
     stats = [dict(iters=s.iters, iters_fp64=s.iters_fp64, reliable_updates=s.reliable_updates, true_resid=s.true_resid,
@@ -237,7 +304,14 @@ def wd_index_tables(dims):
 
 
 def wd_debug_device_tables(ctx, nb, cb, par):
-    _check(lib().wd_debug_device_tables(ctx, _ptr(nb), _ptr(cb), _ptr(par)))
+    import torch
+    info = _ctx_info(ctx)
+    for name, t, n, dt in (("nb", nb, 8 * info.V, torch.int32), ("cb", cb, info.V, torch.int32),
+                           ("par", par, info.V, torch.uint8)):
+        if t.dtype != dt or t.numel() != n:
+            raise ValueError(f"{name} must be {n} elements of {dt}, got {t.numel()} of {t.dtype}")
+    _check(lib().wd_debug_device_tables(ctx, _ptr(nb, info, "nb"), _ptr(cb, info, "cb"),
+                                        _ptr(par, info, "par")))
 
 
 def wd_bytes_required(dims, nrhs, params=None):
@@ -295,9 +369,11 @@ def wd_bench_dslash(ctx, nrhs, prec, epi=0, iters=20, tuned=1):
 
 def wd_faces_apply(ctx, out, inp, out_parity, dagger=0, prec=WD_F64):
     """Face terms across a cut along t of one hopping sweep (include/wd.h)."""
-    _c128(out, (4, 3), "out")
-    _c128(inp, (4, 3), "in")
-    _check(lib().wd_faces_apply(ctx, _ptr(out), _ptr(inp), int(out_parity), int(dagger), int(prec)))
+    info = _ctx_info(ctx)
+    _field(out, info, info.Vh, (4, 3), "out")
+    _field(inp, info, info.Vh, (4, 3), "in")
+    _check(lib().wd_faces_apply(ctx, _ptr(out, info, "out"), _ptr(inp, info, "in"), int(out_parity),
+                                int(dagger), int(prec)))
 
 
 def wd_bench_faces(ctx, prec, iters=20):
@@ -308,25 +384,37 @@ def wd_bench_faces(ctx, prec, iters=20):
 
 
 def wd_session_create(ctx, max_rhs, params=None):
+    info = _ctx_info(ctx)
     h = C.c_void_p()
     p = params if params is not None else wd_solver_defaults()
     _check(lib().wd_session_create(ctx, int(max_rhs), C.byref(p), C.byref(h)))
+    _SESS[_key(h)] = (info, int(p.eo))
     return h
 
 
 def wd_session_destroy(sess):
     _check(lib().wd_session_destroy(sess))
+    _SESS.pop(_key(sess), None)
+
+
+def _sess_info(sess):
+    s = _SESS.get(_key(sess))
+    if s is None:
+        raise ValueError("unknown session handle (not from wd_session_create, or destroyed)")
+    info, eo = s
+    return info, (info.Vh if eo else info.V)
 
 
 def wd_session_add(sess, phi, kappa):
     """phi: complex128 [nrhs, sites, 4, 3] device tensor; returns the slots."""
-    _c128(phi, (4, 3), "phi")
+    info, n = _sess_info(sess)
     nrhs = 1 if phi.dim() == 3 else phi.shape[0]
+    _field(phi, info, n, (4, 3), "phi", nrhs)
     ks = [float(kappa)] * nrhs if np.isscalar(kappa) else [float(k) for k in kappa]
     if len(ks) != nrhs:
         raise ValueError("one kappa per right-hand side")
     slots = (C.c_int32 * nrhs)()
-    _check(lib().wd_session_add(sess, _ptr(phi), nrhs, (C.c_double * nrhs)(*ks), slots))
+    _check(lib().wd_session_add(sess, _ptr(phi, info, "phi"), nrhs, (C.c_double * nrhs)(*ks), slots))
     return list(slots)
 
 
@@ -357,8 +445,9 @@ def wd_session_poll(sess, max_rhs=None):
 
 
 def wd_session_take(sess, slot, x):
-    _c128(x, (4, 3), "x")
-    _check(lib().wd_session_take(sess, int(slot), _ptr(x)))
+    info, n = _sess_info(sess)
+    _field(x, info, n, (4, 3), "x")
+    _check(lib().wd_session_take(sess, int(slot), _ptr(x, info, "x")))
 
 
 def wd_session_bytes(dims, max_rhs, params=None):
@@ -373,28 +462,32 @@ def wd_hmc_defaults():
 
 
 def wd_hmc_draw(ctx, P, chi, seed, traj):
-    _c128(P, (4, 3, 3), "P")
-    _c128(chi, (4, 3), "chi")
-    _check(lib().wd_hmc_draw(ctx, _ptr(P), _ptr(chi), int(seed), int(traj)))
+    info = _ctx_info(ctx)
+    _field(P, info, info.V, (4, 3, 3), "P")
+    _field(chi, info, info.Vh, (4, 3), "chi")
+    _check(lib().wd_hmc_draw(ctx, _ptr(P, info, "P"), _ptr(chi, info, "chi"), int(seed), int(traj)))
 
 
 def wd_md_force(ctx, F, U, phi, kappa, beta, params=None):
     """F = F_g + F_f (even-odd action); returns the solve's iteration count."""
-    _c128(F, (4, 3, 3), "F")
-    _c128(U, (4, 3, 3), "U")
-    _c128(phi, (4, 3), "phi")
+    info = _ctx_info(ctx)
+    _field(F, info, info.V, (4, 3, 3), "F")
+    _field(U, info, info.V, (4, 3, 3), "U")
+    _field(phi, info, info.Vh, (4, 3), "phi")
     it = C.c_int(0)
     p = params if params is not None else wd_solver_defaults()
-    _check(lib().wd_md_force(ctx, _ptr(F), _ptr(U), _ptr(phi), float(kappa), float(beta),
+    _check(lib().wd_md_force(ctx, _ptr(F, info, "F"), _ptr(U, info, "U"), _ptr(phi, info, "phi"),
+                             float(kappa), float(beta),
                              C.byref(p), C.byref(it)))
     return it.value
 
 
 def hmc_trajectory(ctx, U, params, check=True):
     """One trajectory; U is updated in place when accepted.  Returns a dict."""
-    _c128(U, (4, 3, 3), "U")
+    info = _ctx_info(ctx)
+    _field(U, info, info.V, (4, 3, 3), "U")
     r = wd_hmc_result()
-    st = lib().hmc_trajectory(ctx, _ptr(U), C.byref(params), C.byref(r))
+    st = lib().hmc_trajectory(ctx, _ptr(U, info, "U"), C.byref(params), C.byref(r))
     if check and st not in (WD_OK, WD_ERR_NOCONV, WD_ERR_NAN):
         _check(st)
     return {k: getattr(r, k) for k, _ in wd_hmc_result._fields_}
@@ -415,29 +508,33 @@ def hmc_params(beta=5.6, kappa=0.156, tau=1.0, nsteps=50, seed=1, traj=0, force=
 
 
 def wd_plaquette(ctx, U):
-    _c128(U, (4, 3, 3), "U")
+    info = _ctx_info(ctx)
+    _field(U, info, info.V, (4, 3, 3), "U")
     out = C.c_double(0)
-    _check(lib().wd_plaquette(ctx, _ptr(U), C.byref(out)))
+    _check(lib().wd_plaquette(ctx, _ptr(U, info, "U"), C.byref(out)))
     return out.value
 
 
 def wd_polyakov(ctx, U):
     """Complex Polyakov loop of U ([V][4][3][3] complex128 device tensor)."""
-    _c128(U, (4, 3, 3), "U")
+    info = _ctx_info(ctx)
+    _field(U, info, info.V, (4, 3, 3), "U")
     out = (C.c_double * 2)()
-    _check(lib().wd_polyakov(ctx, _ptr(U), out))
+    _check(lib().wd_polyakov(ctx, _ptr(U, info, "U"), out))
     return complex(out[0], out[1])
 
 
 def wd_point_propagator(ctx, psi, src, kappa, params=None, check=True):
     """psi: complex128 [12, V, 4, 3] device tensor (written); returns
     (status, stats list)."""
-    _c128(psi, (4, 3), "psi")
+    info = _ctx_info(ctx)
     if psi.dim() != 4 or psi.shape[0] != 12:
         raise ValueError("psi must be [12, V, 4, 3]")
+    _field(psi, info, info.V, (4, 3), "psi", 12)
     p = params if params is not None else wd_solver_defaults()
     st = (wd_solver_stats * 12)()
-    status = lib().wd_point_propagator(ctx, _ptr(psi), _dims(src), float(kappa), C.byref(p), st)
+    status = lib().wd_point_propagator(ctx, _ptr(psi, info, "psi"), _dims(src), float(kappa),
+                                       C.byref(p), st)
     if check and status not in (WD_OK, WD_ERR_NOCONV, WD_ERR_NAN):
         _check(status)
     stats = [dict(iters=s.iters, iters_fp64=s.iters_fp64, reliable_updates=s.reliable_updates,
@@ -446,11 +543,12 @@ def wd_point_propagator(ctx, psi, src, kappa, params=None, check=True):
 
 
 def wd_pion_correlator(ctx, psi, src, Lt):
-    _c128(psi, (4, 3), "psi")
+    info = _ctx_info(ctx)
     if psi.dim() != 4 or psi.shape[0] != 12:
         raise ValueError("psi must be [12, V, 4, 3]")
+    _field(psi, info, info.V, (4, 3), "psi", 12)
     corr = (C.c_double * int(Lt))()
-    _check(lib().wd_pion_correlator(ctx, corr, _ptr(psi), _dims(src)))
+    _check(lib().wd_pion_correlator(ctx, corr, _ptr(psi, info, "psi"), _dims(src)))
     return np.array(corr[:])
 
 
