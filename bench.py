@@ -55,7 +55,7 @@ WORKLOADS = {
     "c4_serving": dict(lattices={"8^4": (8, 8, 8, 8), "12^3x24": (12, 12, 12, 24),
                                  "16^3x32": (16, 16, 16, 32), "24^3x48": (24, 24, 24, 48)},
                        eps=0.5, kappa=(0.14, 0.157), nrhs=(1, 8), cfg=3, max_slots=8,
-                       budget_gib=6.0, requests=100, loads=(0.5, 0.8, 1.0)),
+                       budget_gib=6.0, requests=500, warmup_requests=50, loads=(0.5, 0.8, 1.0)),
     "c5_hmc": dict(dims=(16, 16, 16, 32), beta=5.6, kappa=0.156, tau=1.0, nsteps=50, cfg=4),
     "c6_measure": dict(dims=(32, 32, 32, 64), eps=0.5, kappa=0.156, cfg=2, src=(0, 0, 0, 0)),
 }
@@ -153,11 +153,11 @@ def make_inputs(w):
 
 
 def oracle_apply_seconds(U, dims, kappa, budget_s, max_n=50):
-    """Seconds per oracle application of Mhat^dag Mhat on one RHS, and the
-    number of applications timed (within budget_s)."""
-    from oracle import wdref
+    """Seconds per oracle application of Mhat^dag Mhat on one RHS on all
+    host threads, the number of applications timed (within budget_s), the
+    seconds of one application on one thread, and the thread count."""
     import lattice_inputs as li
-    wdref.lib()
+    wdref, _ = oracle_host()
     b = li.gaussian_spinor(li.volume(dims) // 2, seed=77)
     t0 = time.time()
     n = 0
@@ -166,11 +166,77 @@ def oracle_apply_seconds(U, dims, kappa, budget_s, max_n=50):
         n += 1
         if time.time() - t0 > budget_s or n >= max_n:
             break
-    return (time.time() - t0) / n, n
+    t_all = (time.time() - t0) / n
+    cores = omp_threads(1)
+    t = time.time()
+    wdref.mhatdag_mhat(dims, U, kappa, b)
+    t_one = time.time() - t
+    omp_threads(cores)
+    return t_all, n, t_one, cores
 
 
-def oracle_cores():
-    return int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+_ORACLE_BUILD = None
+
+
+def oracle_host():
+    """The oracle compiled for the host the benchmark runs on (gcc -O3
+    -march=native into a temporary directory), else the in-tree portable
+    build; returns (the wdref module, a label of the build)."""
+    global _ORACLE_BUILD
+    from oracle import build, wdref
+    if _ORACLE_BUILD is None:
+        import atexit
+        import shutil
+        import tempfile
+        d = tempfile.mkdtemp(prefix="wd_oracle_")
+        atexit.register(shutil.rmtree, d, True)
+        try:
+            wdref.use_library(build.build(out=os.path.join(d, "liboracle_wd.so"), native=True))
+            _ORACLE_BUILD = "gcc -O3 -march=native -fopenmp, built on this host"
+        except Exception as e:  # no compiler here: the portable in-tree build
+            log(f"[bench] native oracle build failed ({e}); using the in-tree build")
+            wdref.lib()
+            _ORACLE_BUILD = "gcc -O3 -march=x86-64-v2 -fopenmp (in-tree build)"
+    return wdref, _ORACLE_BUILD
+
+
+def omp_threads(n=None):
+    """OpenMP threads of the oracle's parallel regions (libgomp, the runtime
+    gcc -fopenmp links): returns the current count, then sets n if given."""
+    import ctypes
+    g = ctypes.CDLL("libgomp.so.1")
+    cur = int(g.omp_get_max_threads())
+    if n is not None:
+        g.omp_set_num_threads(int(n))
+    return cur
+
+
+def oracle_check_solutions(dims, U, kappa, B, X, label="Mhat^dag Mhat"):
+    """The oracle's true residual |b_j - A x_j| / |b_j| of every GPU solution
+    (A = Mhat^dag Mhat, FP64 on the host), the seconds of one application on
+    all host threads (median over the RHS) and on one thread, and the thread
+    count.  B, X: host arrays [nrhs][Vh][4][3]."""
+    wdref, build = oracle_host()
+    cores = omp_threads()
+    res, ts = [], []
+    for j in range(B.shape[0]):
+        t = time.time()
+        AX = wdref.mhatdag_mhat(dims, U, kappa[j], X[j])
+        ts.append(time.time() - t)
+        res.append(float(np.linalg.norm(B[j] - AX) / np.linalg.norm(B[j])))
+    omp_threads(1)
+    t = time.time()
+    wdref.mhatdag_mhat(dims, U, kappa[0], X[0])
+    t1 = time.time() - t
+    omp_threads(cores)
+    log(f"[bench] oracle residuals of the GPU solutions: max {max(res):.3e}; one {label} application "
+        f"{float(np.median(ts)):.3f} s on {cores} threads, {t1:.3f} s on 1 thread ({build})")
+    return res, float(np.median(ts)), t1, cores, build
+
+
+def cpu_record(rate_all, rate_one, cores, build, sample):
+    return {"value": rate_all, "unit": "solves/s", "cores": cores, "kind": "oracle", "sample": sample,
+            "single_thread": {"value": rate_one, "cores": 1}, "build": build}
 
 
 def kernel_roofline(report, wall_s=None):
@@ -237,12 +303,16 @@ def bench_solve(args, wd, torch):
     lat = wd.Lattice(dims)
     lat.gauge_load(Ud, recon=12)
     params = wd.solver_params(prec=PRECS[args.prec], eo=1, tuned=args.tuned, delta=args.delta)
+    tune_rows = []
     if args.tuned:
         t = time.time()
         for code in {PRECS[args.prec], 0}:
             for row in wd.wd_tune(lat.ctx, nrhs, code):
+                tune_rows.append({k: row[k] for k in ("sweep", "sp", "block", "nr", "rl", "remap", "occ", "us",
+                                                      "candidates", "rejected", "source")})
                 log(f"[bench] tuned {code:#x} {row['sweep']}: block {row['block']} nr {row['nr']} "
-                    f"rl {row['rl']} remap {row['remap']} occ {row['occ']} {row['us']:.1f} us")
+                    f"rl {row['rl']} remap {row['remap']} occ {row['occ']} {row['us']:.1f} us "
+                    f"({row['source']}, {row['candidates']} candidates, {row['rejected']} rejected)")
         log(f"[bench] autotune {time.time() - t:.1f}s")
     if args.tune_only:
         lat.close()
@@ -298,27 +368,38 @@ def bench_solve(args, wd, torch):
         dsl, dsl_err = dslash_section(wd, Ud, dims, stream, PRECS[args.prec], nrhs, tuned=args.tuned)
         shard = shard_section(wd, Ud, dims, tuned=args.tuned)
 
+    # the mixed solutions of the last timed step, for the oracle's check
+    Xmixed = Xd.cpu().numpy() if not args.no_cpu else None
+
     fp64 = None
     if not args.no_fp64 and args.prec != "f64":
         p64 = wd.solver_params(prec=0, eo=1, tuned=args.tuned)
-        torch.cuda.synchronize()
-        ts = time.perf_counter()
-        st64, s64 = solve(p64)
-        torch.cuda.synchronize()
-        t64 = time.perf_counter() - ts
+        st64, s64 = solve(p64)  # warm-up: graph capture and first-use allocations
+        t64s = []
+        for k in range(3):
+            torch.cuda.synchronize()
+            ts = time.perf_counter()
+            st64, s64 = solve(p64)
+            torch.cuda.synchronize()
+            t64s.append(time.perf_counter() - ts)
+            log(f"[bench] fp64 solve {k}: {t64s[-1] * 1e3:.1f} ms, iters {max(s['iters'] for s in s64)}")
+        t64 = float(np.median(t64s))
         fp64 = {"solves_per_s": nrhs / t64, "iters": max(s["iters"] for s in s64),
-                "status": st64, "max_true_resid": max(s["true_resid"] for s in s64)}
-        log(f"[bench] fp64 solve: {t64 * 1e3:.1f} ms, iters {fp64['iters']}")
+                "status": st64, "max_true_resid": max(s["true_resid"] for s in s64),
+                "ms_per_solve_runs": [t * 1e3 for t in t64s], "timing": "median of 3 after one warm-up solve"}
     iters64 = fp64["iters"] if fp64 else iters[-1]
 
-    cpu = None
+    cpu = oracle_res = None
     if not args.no_cpu:
-        t_apply, n = oracle_apply_seconds(U, dims, kappa, args.cpu_seconds)
-        cpu = {"value": 1.0 / (t_apply * iters64), "unit": "solves/s", "cores": oracle_cores(),
-               "kind": "oracle",
-               "sample": (f"{n} oracle applications of Mhat^dag Mhat on one {dims} right-hand side "
-                          f"({t_apply:.3f} s each), times {iters64} CG iterations per solve")}
-        log(f"[bench] cpu oracle: {cpu['value']:.4g} solves/s ({cpu['sample']})")
+        oracle_res, t_apply, t_one, cores, build = oracle_check_solutions(dims, U, [kappa] * nrhs, B, Xmixed)
+        del Xmixed
+        ok &= max(oracle_res) <= 1e-10
+        cpu = cpu_record(1.0 / (t_apply * iters64), 1.0 / (t_one * iters64), cores, build,
+                         f"{nrhs} oracle applications of Mhat^dag Mhat on {dims} (median {t_apply:.3f} s on "
+                         f"{cores} threads; one more on 1 thread: {t_one:.3f} s), each applied to one GPU "
+                         f"solution to check it, times {iters64} CG iterations per solve (the FP64 CG's count)")
+        log(f"[bench] cpu oracle: {cpu['value']:.4g} solves/s on {cores} threads, "
+            f"{cpu['single_thread']['value']:.4g} on 1")
     lat.close()
 
     out = base_record(args, value, "solves/s", elapsed / args.steps * 1e3, DTYPE[args.prec],
@@ -329,10 +410,13 @@ def bench_solve(args, wd, torch):
         "converged": bool(ok),
         "iters": iters[-1],
         "max_true_resid": max(resid),
+        "oracle_true_resid": oracle_res,
+        "oracle_max_true_resid": max(oracle_res) if oracle_res else None,
         "latency_ms": {"p50": float(np.percentile(step_ms, 50)), "p99": float(np.percentile(step_ms, 99))},
         "stencil": sten,
         "dominant_kernel": dom,
         "roofline": roof,
+        "tune": tune_rows,
         "fp64": fp64,
         "mixed_vs_fp64": (value / fp64["solves_per_s"]) if fp64 else None,
         "stream_copy_GB_s": stream,
@@ -502,7 +586,7 @@ def bench_serving(args, wd, torch):
     prec = PRECS[args.prec]
     ex = executors(prec)
     for k in range(args.warmup):
-        summ, _ = one_pass(ex, requests(8, seed=900 + k))
+        summ, _ = one_pass(ex, requests(w["warmup_requests"], seed=900 + k))
         log(f"[bench] serving warmup {k}: {summ['completed']} requests in {summ['makespan_s']:.2f}s")
     reqs = requests(nreq, seed=1)
     sat = []
@@ -545,16 +629,18 @@ def bench_serving(args, wd, torch):
     if not args.no_cpu:
         # oracle seconds per application on each lattice, times the CG
         # iterations every RHS of the saturation pass took
-        per = {}
+        per, per1 = {}, {}
         budget_each = args.cpu_seconds / len(names)
         for n in names:
-            per[n], cnt = oracle_apply_seconds(fields[n], w["lattices"][n], 0.15, budget_each, max_n=20)
+            per[n], cnt, per1[n], cores = oracle_apply_seconds(fields[n], w["lattices"][n], 0.15, budget_each,
+                                                               max_n=20)
         t_est = sum(per[r.lattice] * s["iters"] for r in reqs for s in r.stats)
+        t_est1 = sum(per1[r.lattice] * s["iters"] for r in reqs for s in r.stats)
         nrhs_all = sum(r.nrhs for r in reqs)
-        cpu = {"value": nrhs_all / t_est, "unit": "solves/s", "cores": oracle_cores(), "kind": "oracle",
-               "sample": ("oracle Mhat^dag Mhat applications timed on each lattice ("
-                          + ", ".join(f"{n} {per[n] * 1e3:.1f} ms" for n in names)
-                          + f"), times the CG iterations of each of the {nrhs_all} RHS of the saturation pass")}
+        cpu = cpu_record(nrhs_all / t_est, nrhs_all / t_est1, cores, oracle_host()[1],
+                         "oracle Mhat^dag Mhat applications timed on each lattice ("
+                         + ", ".join(f"{n} {per[n] * 1e3:.1f} ms ({per1[n] * 1e3:.1f} ms on 1 thread)" for n in names)
+                         + f"), times the CG iterations of each of the {nrhs_all} RHS of the saturation pass")
         log(f"[bench] cpu oracle: {cpu['value']:.4g} solves/s")
 
     dom, roof, sten = kernel_roofline(report)
@@ -649,17 +735,25 @@ def bench_hmc(args, wd, torch):
 
     cpu = None
     if not args.no_cpu:
-        from oracle import wdref
-        t_apply, n = oracle_apply_seconds(U, dims, w["kappa"], args.cpu_seconds * 0.7)
+        t_apply, n, t_one, cores = oracle_apply_seconds(U, dims, w["kappa"], args.cpu_seconds * 0.7)
+        wdref, build = oracle_host()
         t = time.time()
         wdref.gauge_force(dims, U, w["beta"])
         t_gf = time.time() - t
+        omp_threads(1)
+        t = time.time()
+        wdref.gauge_force(dims, U, w["beta"])
+        t_gf1 = time.time() - t
+        omp_threads(cores)
         h_iters = 2 * cg_per_step  # two H solves at about a force solve's count each, FP64 (labelled)
         t_traj = w["nsteps"] * (cg_per_step * t_apply + t_gf) + h_iters * t_apply
-        cpu = {"value": 3600.0 / t_traj, "unit": "traj/h", "cores": oracle_cores(), "kind": "oracle",
-               "sample": (f"extrapolated: {n} oracle Mhat^dag Mhat applications on {dims} ({t_apply:.3f} s each) "
-                          f"times the GPU's {cg_per_step:.0f} CG iterations per MD step, plus one oracle gauge force "
-                          f"({t_gf:.3f} s), times {w['nsteps']} steps, plus two Hamiltonian solves")}
+        t_traj1 = w["nsteps"] * (cg_per_step * t_one + t_gf1) + h_iters * t_one
+        cpu = cpu_record(3600.0 / t_traj, 3600.0 / t_traj1, cores, build,
+                         f"extrapolated: {n} oracle Mhat^dag Mhat applications on {dims} ({t_apply:.3f} s each on "
+                         f"{cores} threads, {t_one:.3f} s on 1) times the GPU's {cg_per_step:.0f} CG iterations per "
+                         f"MD step, plus one oracle gauge force ({t_gf:.3f} s), times {w['nsteps']} steps, plus two "
+                         f"Hamiltonian solves")
+        cpu["unit"] = "traj/h"
         log(f"[bench] cpu oracle: {cpu['value']:.4g} traj/h")
     lat.close()
 
@@ -735,25 +829,52 @@ def bench_measure(args, wd, torch):
     roof["traffic"] = counter_traffic("c3_32c64_12rhs", args.prec, dom["name"])  # the same solve's kernels
     meff = [float(np.log(corr[i] / corr[i + 1])) for i in range(min(12, len(corr) - 1))]
 
+    # the even-site part of the 12 mixed-precision columns, for the oracle's check
+    psi_e = None
+    if not args.no_cpu:
+        from oracle import wdref
+        wdref.lib()
+        eo = wdref.index_tables(dims)[3]
+        psi_e = psi.cpu().numpy()[:, eo[0]]
+
     fp64 = None
     if not args.no_fp64 and args.prec != "f64":
-        torch.cuda.synchronize()
-        ts = time.perf_counter()
-        st64, s64, c64, _, _ = measure(wd.solver_params(prec=0, eo=1, tol=1e-10, tuned=args.tuned))
-        torch.cuda.synchronize()
-        t64 = time.perf_counter() - ts
+        p64 = wd.solver_params(prec=0, eo=1, tol=1e-10, tuned=args.tuned)
+        measure(p64)  # warm-up
+        t64s = []
+        for k in range(3):
+            torch.cuda.synchronize()
+            ts = time.perf_counter()
+            st64, s64, c64, _, _ = measure(p64)
+            torch.cuda.synchronize()
+            t64s.append(time.perf_counter() - ts)
+        t64 = float(np.median(t64s))
         fp64 = {"solves_per_s": 12 / t64, "iters": max(s["iters"] for s in s64),
-                "corr_max_rel_diff": float(np.max(np.abs(corr / c64 - 1)))}
+                "corr_max_rel_diff": float(np.max(np.abs(corr / c64 - 1))),
+                "ms_per_config_runs": [t * 1e3 for t in t64s], "timing": "median of 3 after one warm-up"}
         log(f"[bench] fp64 measurement: {t64 * 1e3:.1f} ms, correlators differ by {fp64['corr_max_rel_diff']:.1e}")
 
-    cpu = None
+    cpu = oracle_res = None
     if not args.no_cpu:
+        # the normal equation each column solved: Mhat^dag Mhat psi_e =
+        # Mhat^dag (b_e + kappa D_eo b_o) for the point source b of column j
+        wdref, build = oracle_host()
+        eo = wdref.index_tables(dims)[3]
+        lex0 = src[0] + dims[0] * (src[1] + dims[1] * (src[2] + dims[2] * src[3]))
+        B = np.zeros((12, V // 2, 4, 3), np.complex128)
+        for j in range(12):
+            b = np.zeros((V, 4, 3), np.complex128)
+            b[lex0, j // 3, j % 3] = 1.0
+            bh = b[eo[0]] + kappa * wdref.hop_eo(dims, U, b[eo[1]], 0)
+            B[j] = wdref.mhat(dims, U, kappa, bh, dagger=True)
+        oracle_res, t_apply, t_one, cores, build = oracle_check_solutions(dims, U, [kappa] * 12, B, psi_e)
+        ok &= max(oracle_res) <= 1e-10
         iters = fp64["iters"] if fp64 else max(s["iters"] for s in stats)
-        t_apply, n = oracle_apply_seconds(U, dims, kappa, args.cpu_seconds)
-        cpu = {"value": 1.0 / (t_apply * iters), "unit": "solves/s", "cores": oracle_cores(), "kind": "oracle",
-               "sample": (f"extrapolated: {n} oracle Mhat^dag Mhat applications on {dims} ({t_apply:.3f} s each) "
-                          f"times {iters} CG iterations per column (the oracle's own propagator runs CG on the "
-                          f"full normal equations, slower still)")}
+        cpu = cpu_record(1.0 / (t_apply * iters), 1.0 / (t_one * iters), cores, build,
+                         f"extrapolated: 12 oracle Mhat^dag Mhat applications on {dims} (median {t_apply:.3f} s "
+                         f"on {cores} threads, {t_one:.3f} s on 1 thread), each checking one GPU column, times "
+                         f"{iters} CG iterations per column (the oracle's own propagator runs CG on the full "
+                         f"normal equations, slower still)")
     lat.close()
     out = base_record(args, value, "solves/s", elapsed / args.steps * 1e3, DTYPE[args.prec],
                       {"workload": (f"c6_measure: {'x'.join(map(str, dims))} lattice (eps {w['eps']}), kappa {kappa}, "
@@ -762,6 +883,8 @@ def bench_measure(args, wd, torch):
                        "prec_sloppy": args.prec, "lattice": list(dims), "delta": args.delta})
     out.update({
         "converged": bool(ok),
+        "oracle_true_resid": oracle_res,
+        "oracle_max_true_resid": max(oracle_res) if oracle_res else None,
         "configs_per_hour": 3600.0 * args.steps / elapsed,
         "plaquette": plaq,
         "polyakov": [poly.real, poly.imag],

@@ -140,6 +140,18 @@ wd_status wd_gauge_load(wd_ctx *c, const double *U, uint32_t flags);
 wd_status wd_dslash(wd_ctx *c, double *out, const double *in, int out_parity, int dagger,
                     int prec);
 
+/* The parity blocks of the hopping term (as wd_dslash with WD_EVEN / WD_ODD)
+ * on nrhs right-hand sides at once (in, out: [nrhs][Vh][4][3], 1..64) with an
+ * explicit launch shape of the stencil kernel: shape (HOST int32[5]) =
+ * {threads per work-group (64, 128, 192 or 256), RHS per lane, lanes per
+ * site, tile order (0..7, as the autotuner's), work-groups per CU cap (0 or
+ * 2..8)}, or NULL for the default shape.  Every supported shape gives the
+ * same bits; WD_ERR_ARG for a shape this lattice or precision does not
+ * support (e.g. a slab tile order when the slab extent is not a multiple of
+ * 8).  For checking launch shapes against a reference operator. */
+wd_status wd_dslash_shaped(wd_ctx *c, double *out, const double *in, int nrhs, int out_parity, int dagger,
+                           int prec, const int32_t shape[5]);
+
 /* Normal operator: eo = 0: out = M^dag M in (full [V][4][3]);
  * eo = 1: out = Mhat^dag Mhat in (even [Vh][4][3]).  FP64 arithmetic. */
 wd_status wd_mdagm(wd_ctx *c, double *out, const double *in, double kappa, int eo);
@@ -351,9 +363,13 @@ wd_status wd_timing_report(wd_ctx *c, char *buf, size_t len);
  * is rejected.  The fastest shapes are kept in the context and used by
  * solves with wd_solver_params.tuned = 1.  report: HOST buffer of len bytes
  * receiving one line per sweep (may be NULL).  Needs a loaded gauge field.
- * If the environment variable WD_TUNE_CACHE names a file, shapes found there
- * for the same lattice, nrhs and formats are reused without timing, and new
- * results are appended to it. */
+ * If the environment variable WD_TUNE_CACHE names a file, a shape found there
+ * for the same lattice, nrhs and formats is run once against the reference
+ * shape on the same synthetic inputs and adopted without a search only if its
+ * vectors and norm partials agree bit for bit (report source=cache-verified,
+ * candidates=1); otherwise it is reported as source=cache-rejected and the
+ * sweep is tuned from scratch (source=timed).  New results are appended to
+ * the file. */
 wd_status wd_tune(wd_ctx *c, int nrhs, int prec, char *report, size_t len);
 
 /* Stencil micro-benchmark: `iters` back-to-back sweeps of the stencil with

@@ -11,12 +11,22 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB = None
+_PATH = None  # another build of the same source (use_library), else the in-tree one
+
+
+def use_library(path):
+    """Load the oracle from `path` (another build of wdref.c, e.g. one
+    compiled for the host it runs on) for every later call."""
+    global _LIB, _PATH
+    _PATH = path
+    _LIB = None
+    return lib()
 
 
 def lib():
     global _LIB
     if _LIB is None:
-        path = os.path.join(_HERE, "liboracle_wd.so")
+        path = _PATH or os.path.join(_HERE, "liboracle_wd.so")
         if not os.path.exists(path):
             from oracle import build
             build.build()

@@ -432,6 +432,70 @@ wd_status wd_dslash(wd_ctx *c, double *out, const double *in, int out_parity, in
     return WD_OK;
 }
 
+namespace {
+__global__ void __launch_bounds__(256) k_fill_ones(unsigned *p, long long n)
+{
+    const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) p[i] = 0xffffffffu;
+}
+
+hipError_t fill_ones(void *p, size_t bytes, hipStream_t s)
+{
+    const long long n = (long long)(bytes / 4);
+    if (n > 0)
+        hipLaunchKernelGGL(k_fill_ones, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, (unsigned *)p, n);
+    return hipGetLastError();
+}
+}  // namespace
+
+wd_status wd_dslash_shaped(wd_ctx *c, double *out, const double *in, int nrhs, int out_parity, int dagger,
+                           int prec, const int32_t shape[5])
+{
+    if (!c || !out || !in) return set_error(WD_ERR_ARG, "NULL argument");
+    if (!c->have_gauge) return set_error(WD_ERR_STATE, "no gauge field loaded");
+    if (out_parity != WD_EVEN && out_parity != WD_ODD)
+        return set_error(WD_ERR_ARG, "bad parity %d (WD_EVEN or WD_ODD)", out_parity);
+    if (nrhs < 1 || nrhs > 64) return set_error(WD_ERR_ARG, "nrhs %d out of range 1..64", nrhs);
+    int sp, lk, xp;
+    WD_TRY(decode_prec(c, prec, &sp, &lk, &xp));
+    TuneCfg t = default_cfg(sp);
+    if (shape) {
+        t.block = shape[0];
+        t.nr = shape[1];
+        t.rl = shape[2];
+        t.remap = shape[3];
+        t.occ = shape[4];
+    }
+    if (!dslash_shape_supported(sp, t.nr, t.rl) || t.block < 64 || t.block > 256 || (t.block & 63) ||
+        t.remap < 0 || t.remap >= kTileOrders || (t.occ != 0 && (t.occ < 2 || t.occ > kMaxOcc)) ||
+        (t.remap >= 2 && !slab_order_ok(c->g, t.block / t.rl, t.remap)))
+        return set_error(WD_ERR_ARG, "launch shape block %d nr %d rl %d order %d cap %d not supported here",
+                         t.block, t.nr, t.rl, t.remap, t.occ);
+    WD_HIP(hipSetDevice(c->device));
+    Field fi, fo;
+    WD_TRY(alloc_field(c, "dsh_in", sp, 1, nrhs, &fi));
+    WD_TRY(alloc_field(c, "dsh_out", sp, 1, nrhs, &fo));
+    std::vector<int> ids(nrhs);
+    for (int j = 0; j < nrhs; j++) ids[j] = j;
+    int *act;
+    WD_TRY(upload_ints(c, "dsh_act", ids.data(), nrhs, &act));
+    hipError_t e;
+    if ((e = pack_spinor(in, fi, nrhs, 0, c->g, c->stream)) != hipSuccess)
+        return set_error(WD_ERR_HIP, "pack: %s", hipGetErrorString(e));
+    // poison the internal output (all-ones bytes: NaN in every format), so
+    // that sites a launch shape failed to write show up as NaN
+    if ((e = fill_ones(fo.base, (size_t)fo.rs * nrhs, c->stream)) != hipSuccess)
+        return set_error(WD_ERR_HIP, "fill: %s", hipGetErrorString(e));
+    Sweep sw;
+    sw.sp = sp; sw.lk = lk; sw.dag = dagger ? 1 : 0; sw.epi = EPI_PLAIN;
+    sw.P = (out_parity == WD_EVEN) ? 0 : 1;
+    sw.in = fi; sw.out = fo; sw.active = act; sw.nact = nrhs;
+    WD_TRY(run_sweep(c, sw, &t));
+    if ((e = unpack_spinor(fo, out, nrhs, 0, c->g, c->stream)) != hipSuccess)
+        return set_error(WD_ERR_HIP, "unpack: %s", hipGetErrorString(e));
+    return WD_OK;
+}
+
 wd_status wd_mdagm(wd_ctx *c, double *out, const double *in, double kappa, int eo)
 {
     if (!c || !out || !in) return set_error(WD_ERR_ARG, "NULL argument");

@@ -281,112 +281,138 @@ extern "C" wd_status wd_tune(wd_ctx *c, int nrhs, int prec, char *report, size_t
     wd_status st = WD_OK;
     const char *cache = getenv("WD_TUNE_CACHE");
     for (const Kind &k : kinds) {
-        if (cache && cache[0]) {
-            TuneCfg cc;
-            double us = 0;
-            if (cache_lookup(cache, cache_key(c, nrhs, sp, lk, k.dag, k.epi), &cc, &us) &&
-                dslash_shape_supported(sp, cc.nr, cc.rl) && (cc.occ == 0 || (cc.occ >= 2 && cc.occ <= kMaxOcc))) {
-                c->tuned[sweep_key(sp, lk, k.dag, k.epi)] = cc;
-                c->tune_gen++;
-                char line[256];
-                snprintf(line, sizeof(line),
-                         "%s;sp=%d;lk=%d;nrhs=%d;block=%d;nr=%d;rl=%d;remap=%d;occ=%d;us=%.2f;GB/s=0.0;candidates=0;"
-                         "rejected=0\n",
-                         k.name, sp, lk, nrhs, cc.block, cc.nr, cc.rl, cc.remap, cc.occ, us);
-                rep += line;
-                continue;
-            }
-        }
         Sweep sw;
         sw.sp = sp; sw.lk = lk; sw.xp = xp; sw.dag = k.dag; sw.epi = k.epi; sw.P = k.P;
         sw.in = t.in; sw.out = t.out; sw.x = t.x; sw.p = t.p; sw.xs = t.xs; sw.r = t.r;
         sw.coef = t.coef; sw.alpha = t.alpha; sw.active = t.act; sw.nact = nrhs;
         sw.partial = (k.epi == EPI_PLAIN) ? nullptr : t.partial;
         sw.pstride = t.pstride;
-        double best = 1e30;
-        TuneCfg bestc = cands[0];
-        int rejected = 0;
-        // second pass: the best shape of the first, with at most occ
-        // work-groups per CU (fewer waves in flight share each L2 better)
-        std::vector<TuneCfg> list = cands;
-        const size_t nfirst = list.size();
-        for (size_t q = 0;; q++) {
-            if (q == nfirst && best < 1e30)
-                for (int oc = 2; oc <= kMaxOcc; oc++) {
-                    TuneCfg v = bestc;
-                    v.occ = oc;
-                    list.push_back(v);
-                }
-            if (q >= list.size()) break;
-            const TuneCfg cf = list[q];
-            // correctness run on fresh inputs, with every output poisoned first
-            // so that a shape that skips sites cannot pass on stale results
-            if (k.epi == EPI_CGUPD) {
-                HIPCHK(hipMemcpyAsync(t.r.base, t.r0.base, sb * nrhs, hipMemcpyDeviceToDevice, s));
-                HIPCHK(hipMemcpyAsync(t.xs.base, t.xs0.base, xb * nrhs, hipMemcpyDeviceToDevice, s));
-            } else {
-                HIPCHK(fill(t.out, Vh, nrhs, 1000 + (unsigned)q, s));
-            }
-            // (the same poison every time: slots no shape writes stay equal)
-            if (t.partial) HIPCHK(fill_bytes(t.partial, sizeof(double) * t.pstride * nrhs, 0xA5u, s));
-            if ((st = run_sweep(c, sw, &cf)) != WD_OK) break;
-            if (q == 0) {
-                HIPCHK(hipMemcpyAsync(t.outref.base, t.out.base, sb * nrhs, hipMemcpyDeviceToDevice, s));
-                HIPCHK(hipMemcpyAsync(t.rref.base, t.r.base, sb * nrhs, hipMemcpyDeviceToDevice, s));
-                HIPCHK(hipMemcpyAsync(t.xsref.base, t.xs.base, xb * nrhs, hipMemcpyDeviceToDevice, s));
-                HIPCHK(hipMemcpyAsync(t.pref, t.partial, sizeof(double) * t.pstride * nrhs, hipMemcpyDeviceToDevice, s));
-            } else {
-                unsigned bad = 0;
+
+        // Runs list[0] (the reference shape) and then every other entry on
+        // identical inputs, with every output poisoned first so that a shape
+        // that skips sites cannot pass on stale results; a shape whose vectors
+        // or norm partials differ in any bit from the reference is rejected
+        // (ok[q] = false).  The accepted ones are timed (best of 3 batches of
+        // 4 launches).  With occ_pass, the fastest shape of the list is then
+        // retried with a cap of 2..kMaxOcc work-groups per CU.
+        auto evaluate = [&](std::vector<TuneCfg> &list, bool occ_pass, std::vector<char> &ok,
+                            std::vector<double> &us, TuneCfg &bestc, double &best) -> wd_status {
+            best = 1e30;
+            bestc = list[0];
+            const size_t nfirst = list.size();
+            for (size_t q = 0;; q++) {
+                if (occ_pass && q == nfirst && best < 1e30)
+                    for (int oc = 2; oc <= kMaxOcc; oc++) {
+                        TuneCfg v = bestc;
+                        v.occ = oc;
+                        list.push_back(v);
+                    }
+                if (q >= list.size()) break;
+                ok.resize(list.size(), 0);
+                us.resize(list.size(), 0.0);
+                const TuneCfg cf = list[q];
                 if (k.epi == EPI_CGUPD) {
-                    WD_TRY(compare(c, t.r.base, t.rref.base, sb * nrhs, dcount, nd));
-                    bad += *nd;
-                    WD_TRY(compare(c, t.xs.base, t.xsref.base, xb * nrhs, dcount, nd));
-                    bad += *nd;
+                    HIPCHK(hipMemcpyAsync(t.r.base, t.r0.base, sb * nrhs, hipMemcpyDeviceToDevice, s));
+                    HIPCHK(hipMemcpyAsync(t.xs.base, t.xs0.base, xb * nrhs, hipMemcpyDeviceToDevice, s));
                 } else {
-                    WD_TRY(compare(c, t.out.base, t.outref.base, sb * nrhs, dcount, nd));
-                    bad += *nd;
+                    HIPCHK(fill(t.out, Vh, nrhs, 1000 + (unsigned)q, s));
                 }
-                if (k.epi != EPI_PLAIN) {
-                    WD_TRY(compare(c, (const char *)t.partial, (const char *)t.pref,
-                                   sizeof(double) * t.pstride * nrhs, dcount, nd));
-                    bad += *nd;
+                // (the same poison every time: slots no shape writes stay equal)
+                if (t.partial) HIPCHK(fill_bytes(t.partial, sizeof(double) * t.pstride * nrhs, 0xA5u, s));
+                WD_TRY(run_sweep(c, sw, &cf));
+                if (q == 0) {
+                    HIPCHK(hipMemcpyAsync(t.outref.base, t.out.base, sb * nrhs, hipMemcpyDeviceToDevice, s));
+                    HIPCHK(hipMemcpyAsync(t.rref.base, t.r.base, sb * nrhs, hipMemcpyDeviceToDevice, s));
+                    HIPCHK(hipMemcpyAsync(t.xsref.base, t.xs.base, xb * nrhs, hipMemcpyDeviceToDevice, s));
+                    HIPCHK(hipMemcpyAsync(t.pref, t.partial, sizeof(double) * t.pstride * nrhs,
+                                          hipMemcpyDeviceToDevice, s));
+                } else {
+                    unsigned bad = 0;
+                    if (k.epi == EPI_CGUPD) {
+                        WD_TRY(compare(c, t.r.base, t.rref.base, sb * nrhs, dcount, nd));
+                        bad += *nd;
+                        WD_TRY(compare(c, t.xs.base, t.xsref.base, xb * nrhs, dcount, nd));
+                        bad += *nd;
+                    } else {
+                        WD_TRY(compare(c, t.out.base, t.outref.base, sb * nrhs, dcount, nd));
+                        bad += *nd;
+                    }
+                    if (k.epi != EPI_PLAIN) {
+                        WD_TRY(compare(c, (const char *)t.partial, (const char *)t.pref,
+                                       sizeof(double) * t.pstride * nrhs, dcount, nd));
+                        bad += *nd;
+                    }
+                    if (bad) continue;
                 }
-                if (bad) {
-                    rejected++;
+                ok[q] = 1;
+                double tbest = 1e30;
+                for (int rep3 = 0; rep3 < 3; rep3++) {
+                    HIPCHK(hipEventRecord(e0, s));
+                    for (int it = 0; it < 4; it++) WD_TRY(run_sweep(c, sw, &cf));
+                    HIPCHK(hipEventRecord(e1, s));
+                    HIPCHK(hipEventSynchronize(e1));
+                    float ms = 0;
+                    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+                    tbest = std::min(tbest, (double)ms / 4);
+                }
+                us[q] = tbest * 1e3;
+                if (tbest < best) {
+                    best = tbest;
+                    bestc = cf;
+                }
+            }
+            return WD_OK;
+        };
+        auto rejected_of = [](const std::vector<char> &ok) {
+            int r = 0;
+            for (size_t q = 1; q < ok.size(); q++) r += ok[q] ? 0 : 1;
+            return r;
+        };
+        auto report_line = [&](const TuneCfg &b, double us, double gbs, size_t ncand, int nrej, const char *src) {
+            char line[320];
+            snprintf(line, sizeof(line),
+                     "%s;sp=%d;lk=%d;nrhs=%d;block=%d;nr=%d;rl=%d;remap=%d;occ=%d;us=%.2f;GB/s=%.1f;"
+                     "candidates=%zu;rejected=%d;source=%s\n",
+                     k.name, sp, lk, nrhs, b.block, b.nr, b.rl, b.remap, b.occ, us, gbs, ncand, nrej, src);
+            rep += line;
+        };
+
+        // A shape found in the cache is adopted only after it has given the
+        // reference shape's results bit for bit on this lattice.
+        if (cache && cache[0]) {
+            TuneCfg cc;
+            double us_cached = 0;
+            if (cache_lookup(cache, cache_key(c, nrhs, sp, lk, k.dag, k.epi), &cc, &us_cached) &&
+                dslash_shape_supported(sp, cc.nr, cc.rl) && (cc.occ == 0 || (cc.occ >= 2 && cc.occ <= kMaxOcc)) &&
+                (cc.remap < 2 || slab_order_ok(c->g, cc.block / cc.rl, cc.remap))) {
+                std::vector<TuneCfg> vl = {cands[0], cc};
+                std::vector<char> ok;
+                std::vector<double> us;
+                TuneCfg bc;
+                double bt;
+                if ((st = evaluate(vl, false, ok, us, bc, bt)) != WD_OK) break;
+                if (ok[1]) {
+                    c->tuned[sweep_key(sp, lk, k.dag, k.epi)] = cc;
+                    c->tune_gen++;
+                    report_line(cc, us[1], sweep_bytes(c, sw) / (us[1] * 1e-6) / 1e9, 1, 0, "cache-verified");
                     continue;
                 }
-            }
-            // timing: best of 3 batches of 4 launches
-            double tbest = 1e30;
-            for (int rep3 = 0; rep3 < 3; rep3++) {
-                HIPCHK(hipEventRecord(e0, s));
-                for (int it = 0; it < 4; it++)
-                    if ((st = run_sweep(c, sw, &cf)) != WD_OK) break;
-                HIPCHK(hipEventRecord(e1, s));
-                HIPCHK(hipEventSynchronize(e1));
-                float ms = 0;
-                HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-                tbest = std::min(tbest, (double)ms / 4);
-            }
-            if (st != WD_OK) break;
-            if (tbest < best) {
-                best = tbest;
-                bestc = cf;
+                // a cached shape that does not reproduce the reference is
+                // discarded, and the sweep is tuned from scratch
+                report_line(cc, us_cached, 0.0, 1, 1, "cache-rejected");
             }
         }
-        if (st != WD_OK) break;
+        std::vector<TuneCfg> list = cands;
+        std::vector<char> ok;
+        std::vector<double> us;
+        TuneCfg bestc;
+        double best;
+        if ((st = evaluate(list, true, ok, us, bestc, best)) != WD_OK) break;
         c->tuned[sweep_key(sp, lk, k.dag, k.epi)] = bestc;
         c->tune_gen++;
         if (cache && cache[0]) cache_store(cache, cache_key(c, nrhs, sp, lk, k.dag, k.epi), bestc, best * 1e3);
-        Sweep swb = sw;
-        const double gbs = sweep_bytes(c, swb) / (best * 1e-3) / 1e9;
-        char line[256];
-        snprintf(line, sizeof(line),
-                 "%s;sp=%d;lk=%d;nrhs=%d;block=%d;nr=%d;rl=%d;remap=%d;occ=%d;us=%.2f;GB/s=%.1f;candidates=%zu;"
-                 "rejected=%d\n",
-                 k.name, sp, lk, nrhs, bestc.block, bestc.nr, bestc.rl, bestc.remap, bestc.occ, best * 1e3, gbs,
-                 list.size(), rejected);
-        rep += line;
+        report_line(bestc, best * 1e3, sweep_bytes(c, sw) / (best * 1e-3) / 1e9, list.size(), rejected_of(ok),
+                    "timed");
     }
     c->timing = was_timing;
     (void)hipEventDestroy(e0);

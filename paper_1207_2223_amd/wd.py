@@ -65,6 +65,7 @@ _SIGS = {
     "wd_set_stream": (C.c_int, [_P, _P]),
     "wd_gauge_load": (C.c_int, [_P, _P, C.c_uint32]),
     "wd_dslash": (C.c_int, [_P, _P, _P, C.c_int, C.c_int, C.c_int]),
+    "wd_dslash_shaped": (C.c_int, [_P, _P, _P, C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_int32)]),
     "wd_mdagm": (C.c_int, [_P, _P, _P, C.c_double, C.c_int]),
     "wd_cg_solve": (C.c_int, [_P, _P, _P, C.c_int, C.POINTER(C.c_double),
                               C.POINTER(wd_solver_params), C.POINTER(wd_solver_stats)]),
@@ -261,6 +262,20 @@ def wd_dslash(ctx, out, inp, out_parity, dagger=0, prec=WD_F64):
                            int(dagger), int(prec)))
 
 
+def wd_dslash_shaped(ctx, out, inp, out_parity, dagger=0, prec=WD_F64, shape=None):
+    """out, inp: complex128 [nrhs, Vh, 4, 3] (or [Vh, 4, 3]); shape: None or
+    (block, nr, rl, tile order, work-group cap)."""
+    info = _ctx_info(ctx)
+    nrhs = 1 if inp.dim() == 3 else inp.shape[0]
+    if tuple(out.shape) != tuple(inp.shape):
+        raise ValueError(f"out has shape {tuple(out.shape)}, in {tuple(inp.shape)}: they must match")
+    _field(inp, info, info.Vh, (4, 3), "in", nrhs)
+    _field(out, info, info.Vh, (4, 3), "out", nrhs)
+    sh = None if shape is None else (C.c_int32 * 5)(*[int(v) for v in shape])
+    _check(lib().wd_dslash_shaped(ctx, _ptr(out, info, "out"), _ptr(inp, info, "in"), int(nrhs),
+                                  int(out_parity), int(dagger), int(prec), sh))
+
+
 def wd_mdagm(ctx, out, inp, kappa, eo=1):
     info = _ctx_info(ctx)
     n = info.Vh if eo else info.V
@@ -353,7 +368,10 @@ def wd_tune(ctx, nrhs, prec):
         d = {"sweep": f[0]}
         for kv in f[1:]:
             k, v = kv.split("=")
-            d[k] = float(v) if "." in v else int(v)
+            try:
+                d[k] = float(v) if "." in v else int(v)
+            except ValueError:
+                d[k] = v
         rows.append(d)
     return rows
 

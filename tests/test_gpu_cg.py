@@ -133,7 +133,11 @@ def test_near_singular_operator_finishes_in_fp64(wd, oracle, prec):
         st, stats = lat.cg_solve(x, dev(b), [kap], wd.solver_params(prec=pc, maxiter=3000))
         assert st == wd.WD_OK, stats
         tr = true_resid(oracle, dims, U, kap, host(x)[0], b[0], eo=True)
-        assert tr <= 1.2e-10, tr
+        note(f"near-singular {prec} {name}: library residual {stats[0]['true_resid']:.4e}, oracle {tr:.4e}")
+        # the library stops at its own FP64 residual <= 1e-10; the oracle
+        # sums A x in another order, and with |x| ~ 1e4 |b| here their FP64
+        # roundings of b - A x differ by ~ eps |A| |x| ~ 3e-12 |b|
+        assert tr <= 1.05e-10, tr
         res[name] = stats[0]
     note(f"near-singular {prec}: mixed {res['mixed']['iters']} its ({res['mixed']['iters_fp64']} fp64, "
          f"{res['mixed']['reliable_updates']} RU), fp64 {res['fp64']['iters']} its")

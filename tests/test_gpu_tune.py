@@ -115,7 +115,8 @@ def test_cached_shapes_with_work_group_cap(wd, tmp_path, monkeypatch):
     monkeypatch.setenv("WD_TUNE_CACHE", str(cache))
     rows = wd.wd_tune(lat.ctx, 3, wd.WD_F16)
     assert [r["occ"] for r in rows] == [3, 5, 0, 4]
-    assert [r["candidates"] for r in rows] == [0, 0, 0, 0]
+    assert [r["candidates"] for r in rows] == [1, 1, 1, 1]
+    assert [r["source"] for r in rows] == ["cache-verified"] * 4 and all(r["rejected"] == 0 for r in rows)
     B = li.gaussian_spinor(V // 2, seed=52, nrhs=3)
     kap = [0.15, 0.153, 0.156]
     X0 = empty_like_dev(B)
