@@ -134,10 +134,9 @@ def test_near_singular_operator_finishes_in_fp64(wd, oracle, prec):
         assert st == wd.WD_OK, stats
         tr = true_resid(oracle, dims, U, kap, host(x)[0], b[0], eo=True)
         note(f"near-singular {prec} {name}: library residual {stats[0]['true_resid']:.4e}, oracle {tr:.4e}")
-        # the library stops at its own FP64 residual <= 1e-10; the oracle
-        # sums A x in another order, and with |x| ~ 1e4 |b| here their FP64
-        # roundings of b - A x differ by ~ eps |A| |x| ~ 3e-12 |b|
-        assert tr <= 1.05e-10, tr
+        # (the library's FP64 residual and the oracle's agree to about 1e-3
+        # relative here: 7.1793e-11 and 7.1795e-11 for the FP16 solve)
+        assert tr <= 1.01e-10, tr
         res[name] = stats[0]
     note(f"near-singular {prec}: mixed {res['mixed']['iters']} its ({res['mixed']['iters_fp64']} fp64, "
          f"{res['mixed']['reliable_updates']} RU), fp64 {res['fp64']['iters']} its")

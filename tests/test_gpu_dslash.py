@@ -70,13 +70,14 @@ def test_dslash_fp64_full_lattice(wd, oracle, dims):
     lat.close()
 
 
-# (relative 2-norm, max-abs ratio) bounds: about 2x the rounding each format
-# measured on this lattice and field (relative 2-norm F32 9.0e-8, F16 2.5e-4,
-# F16L 4.0e-4, F32L 2.0e-4, F32R 8.7e-8, F16R 2.5e-4, I16 2.8e-5, I16L 2.0e-4),
-# and for the largest error on any component, relative to the largest output
-# component, 4x the measured relative 2-norm.
-SLOPPY_TOL = {"F32": (2e-7, 4e-7), "F16": (6e-4, 1.2e-3), "F16L": (9e-4, 1.8e-3), "F32L": (4.5e-4, 9e-4),
-              "F32R": (2e-7, 4e-7), "F16R": (6e-4, 1.2e-3), "I16": (6e-5, 1.2e-4), "I16L": (4.5e-4, 9e-4)}
+# (relative 2-norm, max-abs ratio) bounds, about 2-2.5x the rounding each
+# format shows on this lattice and field: relative 2-norm / largest component
+# error over largest output component, measured on MI355X: F32 9.0e-8 /
+# 1.25e-7, F16 2.5e-4 / 3.3e-4, F16L 4.0e-4 / 5.5e-4, F32L 2.0e-4 / 2.4e-4,
+# F32R 8.7e-8 / 1.25e-7, F16R 2.5e-4 / 3.3e-4, I16 2.8e-5 / 2.7e-5, I16L
+# 2.0e-4 / 2.4e-4.
+SLOPPY_TOL = {"F32": (2e-7, 3e-7), "F16": (6e-4, 8e-4), "F16L": (9e-4, 1.4e-3), "F32L": (4.5e-4, 6e-4),
+              "F32R": (2e-7, 3e-7), "F16R": (6e-4, 8e-4), "I16": (6e-5, 7e-5), "I16L": (4.5e-4, 6e-4)}
 
 
 @pytest.mark.parametrize("prec", sorted(SLOPPY_TOL))
