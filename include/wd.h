@@ -156,6 +156,20 @@ wd_status wd_dslash_shaped(wd_ctx *c, double *out, const double *in, int nrhs, i
  * eo = 1: out = Mhat^dag Mhat in (even [Vh][4][3]).  FP64 arithmetic. */
 wd_status wd_mdagm(wd_ctx *c, double *out, const double *in, double kappa, int eo);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * normal operator as wd_mdagm -- same arguments, same kernels, the same bits
+ * -- with its packed operand, temporaries and device scalars in a fixed
+ * device array of 64 MiB per GPU (held from the first wd_create on that GPU
+ * until the process ends) instead of context workspaces.  The call allocates
+ * nothing and copies nothing between host and device.  Lattices whose
+ * operator needs more than the 64 MiB (about Vh <= 87000 for eo = 1, Vh <=
+ * 58000 for eo = 0; e.g. 16^3 x 32 even-odd fits, its full lattice does not)
+ * are refused with WD_ERR_ARG before any work is issued.  Every call on one
+ * GPU uses that GPU's array: calls that overlap on one GPU (other streams or
+ * threads) race and must be serialised by the caller. */
+wd_status wd_mdagm_noalloc(wd_ctx *c, double *out, const double *in, double kappa, int eo);
+
 /* Solve A x_j = phi_j for nrhs right-hand sides at once (eq. 3: the inverse
  * of M^dag M applied to the pseudofermion).  A is M^dag M (p->eo = 0, fields
  * [nrhs][V][4][3]) or Mhat^dag Mhat (p->eo = 1, fields [nrhs][Vh][4][3],

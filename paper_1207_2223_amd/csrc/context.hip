@@ -297,6 +297,7 @@ wd_status wd_create(wd_ctx **out, const int32_t dims[4], int device, void *hip_s
     WD_HIP(hipGetDeviceCount(&ndev));
     if (device < 0 || device >= ndev) return set_error(WD_ERR_ARG, "device %d not present", device);
     WD_HIP(hipSetDevice(device));
+    WD_TRY(scratch_setup(device));
     wd_ctx *c = new wd_ctx();
     c->device = device;
     c->stream = (hipStream_t)hip_stream;
@@ -496,26 +497,19 @@ wd_status wd_dslash_shaped(wd_ctx *c, double *out, const double *in, int nrhs, i
     return WD_OK;
 }
 
-wd_status wd_mdagm(wd_ctx *c, double *out, const double *in, double kappa, int eo)
+extern "C++" {
+namespace wd {
+
+// M^dag M (eo = 0) or Mhat^dag Mhat (eo = 1) of `in` into `out` (canonical
+// FP64, device) through the packed buffers A, T, B (FP64, two parity
+// subfields each), with dcf = {-kappa, -kappa^2} and act = {0, 1} on the
+// device: the kernels of wd_mdagm and of its allocation-free variant.
+wd_status mdagm_apply(wd_ctx *c, double *out, const double *in, int eo, const double *dcf, const int *act,
+                      const Field &A, const Field &T, const Field &B)
 {
-    if (!c || !out || !in) return set_error(WD_ERR_ARG, "NULL argument");
-    if (!c->have_gauge) return set_error(WD_ERR_STATE, "no gauge field loaded");
-    if (!std::isfinite(kappa)) return set_error(WD_ERR_ARG, "kappa not finite");
-    WD_HIP(hipSetDevice(c->device));
-    const int sp = SP_F64, lk = c->lk64;
-    double cf[2] = {-kappa, -kappa * kappa};
-    double *dcf;
-    WD_TRY(upload_doubles(c, "mdm_coef", cf, 2, &dcf));
-    int idx[2] = {0, 1};
-    int *act;
-    WD_TRY(upload_ints(c, "mdm_act", idx, 2, &act));
     hipError_t e;
-    Field A, T, B;
-    WD_TRY(alloc_field(c, "mdm_a", sp, 2, 1, &A));
-    WD_TRY(alloc_field(c, "mdm_t", sp, 2, 1, &T));
-    WD_TRY(alloc_field(c, "mdm_b", sp, 2, 1, &B));
     Sweep sw;
-    sw.sp = sp; sw.lk = lk; sw.nact = 1;
+    sw.sp = SP_F64; sw.lk = c->lk64; sw.nact = 1;
     if (eo) {
         // the coefficient array is indexed by RHS id: use id 1 -> -kappa^2
         sw.active = act + 1;
@@ -557,6 +551,28 @@ wd_status wd_mdagm(wd_ctx *c, double *out, const double *in, double kappa, int e
             return set_error(WD_ERR_HIP, "unpack: %s", hipGetErrorString(e));
     }
     return WD_OK;
+}
+
+}  // namespace wd
+}  // extern "C++"
+
+wd_status wd_mdagm(wd_ctx *c, double *out, const double *in, double kappa, int eo)
+{
+    if (!c || !out || !in) return set_error(WD_ERR_ARG, "NULL argument");
+    if (!c->have_gauge) return set_error(WD_ERR_STATE, "no gauge field loaded");
+    if (!std::isfinite(kappa)) return set_error(WD_ERR_ARG, "kappa not finite");
+    WD_HIP(hipSetDevice(c->device));
+    double cf[2] = {-kappa, -kappa * kappa};
+    double *dcf;
+    WD_TRY(upload_doubles(c, "mdm_coef", cf, 2, &dcf));
+    int idx[2] = {0, 1};
+    int *act;
+    WD_TRY(upload_ints(c, "mdm_act", idx, 2, &act));
+    Field A, T, B;
+    WD_TRY(alloc_field(c, "mdm_a", SP_F64, 2, 1, &A));
+    WD_TRY(alloc_field(c, "mdm_t", SP_F64, 2, 1, &T));
+    WD_TRY(alloc_field(c, "mdm_b", SP_F64, 2, 1, &B));
+    return mdagm_apply(c, out, in, eo, dcf, act, A, T, B);
 }
 
 wd_status wd_index_tables(const int32_t dims[4], int32_t *nb, int32_t *cb, uint8_t *par)

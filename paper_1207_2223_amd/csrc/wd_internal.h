@@ -224,5 +224,11 @@ inline int remap_stripes(int remap) { return remap <= 2 || remap >= 5 ? 1 : (rem
 inline int remap_slab_dim(int remap) { return (remap == 5 || remap == 6) ? 3 : 2; }
 const TuneCfg *tuned_cfg(const wd_ctx *c, const Sweep &sw);
 double sweep_bytes(const wd_ctx *c, const Sweep &sw);
+wd_status mdagm_apply(wd_ctx *c, double *out, const double *in, int eo, const double *dcf, const int *act,
+                      const Field &A, const Field &T, const Field &B);
+// The allocation-free entry points' device scratch array (noalloc.hip): its
+// address on `device` is looked up once, with that device current (called by
+// wd_create), and kept per device.
+wd_status scratch_setup(int device);
 
 }  // namespace wd

@@ -67,6 +67,7 @@ _SIGS = {
     "wd_dslash": (C.c_int, [_P, _P, _P, C.c_int, C.c_int, C.c_int]),
     "wd_dslash_shaped": (C.c_int, [_P, _P, _P, C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_int32)]),
     "wd_mdagm": (C.c_int, [_P, _P, _P, C.c_double, C.c_int]),
+    "wd_mdagm_noalloc": (C.c_int, [_P, _P, _P, C.c_double, C.c_int]),
     "wd_cg_solve": (C.c_int, [_P, _P, _P, C.c_int, C.POINTER(C.c_double),
                               C.POINTER(wd_solver_params), C.POINTER(wd_solver_stats)]),
     "wd_index_tables": (C.c_int, [_I32x4, _P, _P, _P]),
@@ -282,6 +283,15 @@ def wd_mdagm(ctx, out, inp, kappa, eo=1):
     _field(out, info, n, (4, 3), "out")
     _field(inp, info, n, (4, 3), "in")
     _check(lib().wd_mdagm(ctx, _ptr(out, info, "out"), _ptr(inp, info, "in"), float(kappa), int(eo)))
+
+
+def wd_mdagm_noalloc(ctx, out, inp, kappa, eo=1):
+    """wd_mdagm without device allocation (a fixed device scratch array)."""
+    info = _ctx_info(ctx)
+    n = info.Vh if eo else info.V
+    _field(out, info, n, (4, 3), "out")
+    _field(inp, info, n, (4, 3), "in")
+    _check(lib().wd_mdagm_noalloc(ctx, _ptr(out, info, "out"), _ptr(inp, info, "in"), float(kappa), int(eo)))
 
 
 def wd_cg_solve(ctx, x, phi, kappa, params=None, check=True):
