@@ -387,7 +387,8 @@ wd_status wd_timing_report(wd_ctx *c, char *buf, size_t len);
 wd_status wd_tune(wd_ctx *c, int nrhs, int prec, char *report, size_t len);
 
 /* Stencil micro-benchmark: `iters` back-to-back sweeps of the stencil with
- * epilogue epi (0 plain D_oe, 1 xpay+norm D_eo, 2 fused CG update D_eo) on
+ * epilogue epi (0 plain D_oe, 1 xpay+norm D_eo, 2 fused CG residual update
+ * D_eo: Ap = x + coef D in, r -= alpha Ap, |r|^2) on
  * nrhs synthetic fields of precision prec, with the tuned shape if tuned = 1
  * and one was kept, else the default.  *ms (HOST) receives the HIP-event
  * time per sweep, *bytes (HOST, may be NULL) its algorithmic bytes. */

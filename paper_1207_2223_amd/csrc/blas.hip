@@ -68,6 +68,49 @@ __global__ void __launch_bounds__(kBlock) k_p_update(FArg p, FArg r, const doubl
     SpinorIO<SP>::store(site_base(p, rid, sub), p.cs, i, pv);
 }
 
+// The directions p[0..m-1] of the last m iterations (ring slots, RHS stride rs).
+struct Ring {
+    const char *base[kMaxRing];
+    long long rs;
+};
+
+// pd = r + beta p[m-1]; with FLUSH first x += alpha_j p[j] for j = 0..m-1,
+// in that order (the order and roundings of advancing x once per iteration).
+template <int SP, int XP, bool FLUSH>
+__global__ void __launch_bounds__(kBlock) k_p_update_ring(Ring p, int m, FArg pd, FArg r, const double *beta,
+                                                           FArg x, const double *ahist, int ahs, int Vh,
+                                                           const int *active)
+{
+    typedef typename SpinorIO<SP>::real real;
+    typedef typename SpinorIO<XP>::real xreal;
+    const int rid = active[blockIdx.y];
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= Vh) return;
+    real pv[24];
+    if constexpr (FLUSH) {
+        xreal xv[24];
+        SpinorIO<XP>::load(x.base + rid * x.rs, x.cs, i, xv);
+#pragma unroll
+        for (int j = 0; j < kMaxRing; j++) {
+            if (j < m) {
+                const real al = (real)ahist[(size_t)j * ahs + rid];
+                SpinorIO<SP>::load(p.base[j] + rid * p.rs, pd.cs, i, pv);
+#pragma unroll
+                for (int k = 0; k < 24; k++) xv[k] = fmaT((xreal)al, (xreal)pv[k], xv[k]);
+            }
+        }
+        SpinorIO<XP>::store(x.base + rid * x.rs, x.cs, i, xv);
+    } else {
+        SpinorIO<SP>::load(p.base[m - 1] + rid * p.rs, pd.cs, i, pv);
+    }
+    real rv[24];
+    SpinorIO<SP>::load(r.base + rid * r.rs, r.cs, i, rv);
+    const real b = (real)beta[rid];
+#pragma unroll
+    for (int k = 0; k < 24; k++) pv[k] = fmaT(b, pv[k], rv[k]);
+    SpinorIO<SP>::store(pd.base + rid * pd.rs, pd.cs, i, pv);
+}
+
 template <int SP, int XP>
 __global__ void __launch_bounds__(kBlock) k_cg_update(FArg x, FArg p, FArg r, FArg Ap,
                                                        const double *alpha, int Vh, int nsub,
@@ -308,6 +351,7 @@ __global__ void __launch_bounds__(kFinBlock) k_finalize(const double *partial, i
                 alpha[rid] = 0.0;
                 rr[rid] = NAN;
             }
+            if (out) out[rid] = alpha[rid];  // the iteration's slot of the alpha history
         } else if (mode == FIN_BETA) {
             beta[rid] = s / rr[rid];
             rr[rid] = s;
@@ -347,6 +391,39 @@ hipError_t blas_p_update(const Field &p, const Field &r, const double *beta, int
     if (p.sp != r.sp) return hipErrorInvalidValue;
 #define F(SP) hipLaunchKernelGGL(k_p_update<SP>, grid_of(Vh, p.nsub, nact), dim3(kBlock), 0, s, fa(p), fa(r), beta, Vh, p.nsub, active)
     SP_SWITCH(p.sp, F)
+#undef F
+    return hipGetLastError();
+}
+
+hipError_t blas_p_update_ring(const Field *p, int m, const Field &pdst, const Field &r, const double *beta,
+                              bool flush, const Field &x, const double *ahist, int ahs, int Vh,
+                              const int *active, int nact, hipStream_t s)
+{
+    if (nact == 0) return hipSuccess;
+    if (m < 1 || m > kMaxRing || pdst.nsub != 1) return hipErrorInvalidValue;
+    Ring R{};
+    for (int j = 0; j < m; j++) R.base[j] = p[j].base;
+    R.rs = p[0].rs;
+    const dim3 grid = grid_of(Vh, 1, nact);
+#define F(SP_, XP_)                                                                                       \
+    if (flush)                                                                                            \
+        hipLaunchKernelGGL((k_p_update_ring<SP_, XP_, true>), grid, dim3(kBlock), 0, s, R, m, fa(pdst), fa(r), \
+                           beta, fa(x), ahist, ahs, Vh, active);                                          \
+    else                                                                                                  \
+        hipLaunchKernelGGL((k_p_update_ring<SP_, XP_, false>), grid, dim3(kBlock), 0, s, R, m, fa(pdst),     \
+                           fa(r), beta, fa(x), ahist, ahs, Vh, active);
+    if (pdst.sp == SP_F64 && (!flush || x.sp == SP_F64)) {
+        F(SP_F64, SP_F64)
+    } else if (pdst.sp != SP_F64 && (!flush || x.sp == SP_F32)) {
+        switch (pdst.sp) {
+        case SP_F32: F(SP_F32, SP_F32) break;
+        case SP_F16: F(SP_F16, SP_F32) break;
+        case SP_I16: F(SP_I16, SP_F32) break;
+        default: return hipErrorInvalidValue;
+        }
+    } else {
+        return hipErrorInvalidValue;
+    }
 #undef F
     return hipGetLastError();
 }

@@ -111,10 +111,12 @@ TuneCfg default_cfg(int sp)
 
 double sweep_bytes(const wd_ctx *c, const Sweep &sw)
 {
-    const double sb = (double)spinor_site_bytes(sw.sp), xb = (double)spinor_site_bytes(sw.xp);
+    const double sb = (double)spinor_site_bytes(sw.sp);
+    // each field read or written once: plain in, out; xpay in, x, out; CG
+    // update in, x, r read and written
     double per_rhs = 2 * sb;
     if (sw.epi == EPI_XPAY) per_rhs = 3 * sb;
-    if (sw.epi == EPI_CGUPD) per_rhs = 5 * sb + 2 * xb;
+    if (sw.epi == EPI_CGUPD) per_rhs = 4 * sb;
     return (double)c->Vh * (8.0 * (double)link_bytes(sw.lk) + sw.nact * per_rhs);
 }
 
@@ -137,10 +139,6 @@ wd_status run_sweep(wd_ctx *c, const Sweep &sw, const TuneCfg *cfg)
     a.x = sw.x.base;
     a.x_rs = sw.x.rs;
     a.coef = sw.coef;
-    a.p = sw.p.base;
-    a.p_rs = sw.p.rs;
-    a.xs = sw.xs.base;
-    a.xs_rs = sw.xs.rs;
     a.r = sw.r.base;
     a.r_rs = sw.r.rs;
     a.alpha = sw.alpha;
@@ -191,8 +189,8 @@ wd_status run_sweep(wd_ctx *c, const Sweep &sw, const TuneCfg *cfg)
         WD_HIP(hipEventRecord(e1, c->stream));
         const double b = sweep_bytes(c, sw);
         char name[96];
-        snprintf(name, sizeof(name), "dslash_kernel<%d, %d, %d, %d, %s, %d, %d>", sw.sp, sw.lk, nr,
-                 rl, sw.dag ? "true" : "false", sw.epi, sw.sp == SP_F64 ? SP_F64 : SP_F32);
+        snprintf(name, sizeof(name), "dslash_kernel<%d, %d, %d, %d, %s, %d>", sw.sp, sw.lk, nr,
+                 rl, sw.dag ? "true" : "false", sw.epi);
         if (c->ev_info.size() < c->ev_used) c->ev_info.resize(c->ev_used);
         c->ev_info[c->ev_used - 1] = std::make_tuple(std::string(name), b, (double)c->Vh * sw.nact);
         c->t_bytes += b;
@@ -679,11 +677,15 @@ size_t wd_bytes_required(const int32_t dims[4], int nrhs, const wd_solver_params
     size_t links = (144 + 48 + 24 + 72) * 4 * (size_t)V;
     const int sp = p->prec_sloppy & 0xf;
     const size_t nsub = p->eo ? 1 : 2;
-    // FP64: b, x, r, p, Ap, a full-size temporary and a one-parity temporary
-    size_t f64 = (6 * nsub + 1) * 192 * Vh;
+    // FP64: b, x, r, p, Ap, a full-size temporary and a one-parity temporary;
+    // even-odd: the ring of search directions of the lane that iterates
+    // (FP64, or the sloppy one)
+    const size_t ring = p->eo ? (size_t)(kMaxRing - 1) : 0;
+    size_t f64 = (6 * nsub + 1 + (sp == WD_F64 ? ring : 0)) * 192 * Vh;
     size_t sl = 0;
-    if (sp != WD_F64) sl = 4 * spinor_site_bytes(sp == WD_F32 ? SP_F32 : SP_F16) * Vh * nsub + 96 * Vh * nsub;
-    return links + (size_t)nrhs * (f64 + sl) + (size_t)nrhs * 4096;
+    if (sp != WD_F64)
+        sl = (4 + ring) * spinor_site_bytes(sp == WD_F32 ? SP_F32 : SP_F16) * Vh * nsub + 96 * Vh * nsub;
+    return links + (size_t)nrhs * (f64 + sl) + (size_t)nrhs * (4096 + 8 * kMaxRing);
 }
 
 }  // extern "C"

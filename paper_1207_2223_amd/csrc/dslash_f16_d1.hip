@@ -1,4 +1,4 @@
-// Stencil instantiations: FP16 spinors (per-site FP32 norm) with FP32 12-real, FP32 18-real or FP16 12-real links, FP32 solution accumulator, adjoint hopping.
+// Stencil instantiations: FP16 spinors (per-site FP32 norm) with FP32 12-real, FP32 18-real or FP16 12-real links, adjoint hopping.
 #include "dslash_impl.h"
 
 namespace wd {
@@ -7,46 +7,46 @@ hipError_t dslash_launch_f16_d1(const DslashArgs &a, int lk, int nr, int rl, int
                               int grid, hipStream_t s)
 {
     if (lk == LK_F32_12) {
-        WD_DSL_SHAPE(SP_F16, LK_F32_12, 1, 1, true, SP_F32)
-        WD_DSL_SHAPE(SP_F16, LK_F32_12, 2, 1, true, SP_F32)
-        WD_DSL_SHAPE(SP_F16, LK_F32_12, 3, 1, true, SP_F32)
-        WD_DSL_SHAPE(SP_F16, LK_F32_12, 4, 1, true, SP_F32)
-        WD_DSL_SHAPE(SP_F16, LK_F32_12, 1, 2, true, SP_F32)
-        WD_DSL_SHAPE(SP_F16, LK_F32_12, 2, 2, true, SP_F32)
-        WD_DSL_SHAPE(SP_F16, LK_F32_12, 3, 2, true, SP_F32)
-        WD_DSL_SHAPE(SP_F16, LK_F32_12, 4, 2, true, SP_F32)
-        WD_DSL_SHAPE(SP_F16, LK_F32_12, 1, 4, true, SP_F32)
-        WD_DSL_SHAPE(SP_F16, LK_F32_12, 2, 4, true, SP_F32)
-        WD_DSL_SHAPE(SP_F16, LK_F32_12, 3, 4, true, SP_F32)
-        WD_DSL_SHAPE(SP_F16, LK_F32_12, 4, 4, true, SP_F32)
+        WD_DSL_SHAPE(SP_F16, LK_F32_12, 1, 1, true)
+        WD_DSL_SHAPE(SP_F16, LK_F32_12, 2, 1, true)
+        WD_DSL_SHAPE(SP_F16, LK_F32_12, 3, 1, true)
+        WD_DSL_SHAPE(SP_F16, LK_F32_12, 4, 1, true)
+        WD_DSL_SHAPE(SP_F16, LK_F32_12, 1, 2, true)
+        WD_DSL_SHAPE(SP_F16, LK_F32_12, 2, 2, true)
+        WD_DSL_SHAPE(SP_F16, LK_F32_12, 3, 2, true)
+        WD_DSL_SHAPE(SP_F16, LK_F32_12, 4, 2, true)
+        WD_DSL_SHAPE(SP_F16, LK_F32_12, 1, 4, true)
+        WD_DSL_SHAPE(SP_F16, LK_F32_12, 2, 4, true)
+        WD_DSL_SHAPE(SP_F16, LK_F32_12, 3, 4, true)
+        WD_DSL_SHAPE(SP_F16, LK_F32_12, 4, 4, true)
     }
     if (lk == LK_F16_12) {
-        WD_DSL_SHAPE(SP_F16, LK_F16_12, 1, 1, true, SP_F32)
-        WD_DSL_SHAPE(SP_F16, LK_F16_12, 2, 1, true, SP_F32)
-        WD_DSL_SHAPE(SP_F16, LK_F16_12, 3, 1, true, SP_F32)
-        WD_DSL_SHAPE(SP_F16, LK_F16_12, 4, 1, true, SP_F32)
-        WD_DSL_SHAPE(SP_F16, LK_F16_12, 1, 2, true, SP_F32)
-        WD_DSL_SHAPE(SP_F16, LK_F16_12, 2, 2, true, SP_F32)
-        WD_DSL_SHAPE(SP_F16, LK_F16_12, 3, 2, true, SP_F32)
-        WD_DSL_SHAPE(SP_F16, LK_F16_12, 4, 2, true, SP_F32)
-        WD_DSL_SHAPE(SP_F16, LK_F16_12, 1, 4, true, SP_F32)
-        WD_DSL_SHAPE(SP_F16, LK_F16_12, 2, 4, true, SP_F32)
-        WD_DSL_SHAPE(SP_F16, LK_F16_12, 3, 4, true, SP_F32)
-        WD_DSL_SHAPE(SP_F16, LK_F16_12, 4, 4, true, SP_F32)
+        WD_DSL_SHAPE(SP_F16, LK_F16_12, 1, 1, true)
+        WD_DSL_SHAPE(SP_F16, LK_F16_12, 2, 1, true)
+        WD_DSL_SHAPE(SP_F16, LK_F16_12, 3, 1, true)
+        WD_DSL_SHAPE(SP_F16, LK_F16_12, 4, 1, true)
+        WD_DSL_SHAPE(SP_F16, LK_F16_12, 1, 2, true)
+        WD_DSL_SHAPE(SP_F16, LK_F16_12, 2, 2, true)
+        WD_DSL_SHAPE(SP_F16, LK_F16_12, 3, 2, true)
+        WD_DSL_SHAPE(SP_F16, LK_F16_12, 4, 2, true)
+        WD_DSL_SHAPE(SP_F16, LK_F16_12, 1, 4, true)
+        WD_DSL_SHAPE(SP_F16, LK_F16_12, 2, 4, true)
+        WD_DSL_SHAPE(SP_F16, LK_F16_12, 3, 4, true)
+        WD_DSL_SHAPE(SP_F16, LK_F16_12, 4, 4, true)
     }
     if (lk == LK_F32_18) {
-        WD_DSL_SHAPE(SP_F16, LK_F32_18, 1, 1, true, SP_F32)
-        WD_DSL_SHAPE(SP_F16, LK_F32_18, 2, 1, true, SP_F32)
-        WD_DSL_SHAPE(SP_F16, LK_F32_18, 3, 1, true, SP_F32)
-        WD_DSL_SHAPE(SP_F16, LK_F32_18, 4, 1, true, SP_F32)
-        WD_DSL_SHAPE(SP_F16, LK_F32_18, 1, 2, true, SP_F32)
-        WD_DSL_SHAPE(SP_F16, LK_F32_18, 2, 2, true, SP_F32)
-        WD_DSL_SHAPE(SP_F16, LK_F32_18, 3, 2, true, SP_F32)
-        WD_DSL_SHAPE(SP_F16, LK_F32_18, 4, 2, true, SP_F32)
-        WD_DSL_SHAPE(SP_F16, LK_F32_18, 1, 4, true, SP_F32)
-        WD_DSL_SHAPE(SP_F16, LK_F32_18, 2, 4, true, SP_F32)
-        WD_DSL_SHAPE(SP_F16, LK_F32_18, 3, 4, true, SP_F32)
-        WD_DSL_SHAPE(SP_F16, LK_F32_18, 4, 4, true, SP_F32)
+        WD_DSL_SHAPE(SP_F16, LK_F32_18, 1, 1, true)
+        WD_DSL_SHAPE(SP_F16, LK_F32_18, 2, 1, true)
+        WD_DSL_SHAPE(SP_F16, LK_F32_18, 3, 1, true)
+        WD_DSL_SHAPE(SP_F16, LK_F32_18, 4, 1, true)
+        WD_DSL_SHAPE(SP_F16, LK_F32_18, 1, 2, true)
+        WD_DSL_SHAPE(SP_F16, LK_F32_18, 2, 2, true)
+        WD_DSL_SHAPE(SP_F16, LK_F32_18, 3, 2, true)
+        WD_DSL_SHAPE(SP_F16, LK_F32_18, 4, 2, true)
+        WD_DSL_SHAPE(SP_F16, LK_F32_18, 1, 4, true)
+        WD_DSL_SHAPE(SP_F16, LK_F32_18, 2, 4, true)
+        WD_DSL_SHAPE(SP_F16, LK_F32_18, 3, 4, true)
+        WD_DSL_SHAPE(SP_F16, LK_F32_18, 4, 4, true)
     }
     return hipErrorInvalidValue;
 }

@@ -7,46 +7,46 @@ hipError_t dslash_launch_f32_d0(const DslashArgs &a, int lk, int nr, int rl, int
                               int grid, hipStream_t s)
 {
     if (lk == LK_F32_12) {
-        WD_DSL_SHAPE(SP_F32, LK_F32_12, 1, 1, false, SP_F32)
-        WD_DSL_SHAPE(SP_F32, LK_F32_12, 2, 1, false, SP_F32)
-        WD_DSL_SHAPE(SP_F32, LK_F32_12, 3, 1, false, SP_F32)
-        WD_DSL_SHAPE(SP_F32, LK_F32_12, 4, 1, false, SP_F32)
-        WD_DSL_SHAPE(SP_F32, LK_F32_12, 1, 2, false, SP_F32)
-        WD_DSL_SHAPE(SP_F32, LK_F32_12, 2, 2, false, SP_F32)
-        WD_DSL_SHAPE(SP_F32, LK_F32_12, 3, 2, false, SP_F32)
-        WD_DSL_SHAPE(SP_F32, LK_F32_12, 4, 2, false, SP_F32)
-        WD_DSL_SHAPE(SP_F32, LK_F32_12, 1, 4, false, SP_F32)
-        WD_DSL_SHAPE(SP_F32, LK_F32_12, 2, 4, false, SP_F32)
-        WD_DSL_SHAPE(SP_F32, LK_F32_12, 3, 4, false, SP_F32)
-        WD_DSL_SHAPE(SP_F32, LK_F32_12, 4, 4, false, SP_F32)
+        WD_DSL_SHAPE(SP_F32, LK_F32_12, 1, 1, false)
+        WD_DSL_SHAPE(SP_F32, LK_F32_12, 2, 1, false)
+        WD_DSL_SHAPE(SP_F32, LK_F32_12, 3, 1, false)
+        WD_DSL_SHAPE(SP_F32, LK_F32_12, 4, 1, false)
+        WD_DSL_SHAPE(SP_F32, LK_F32_12, 1, 2, false)
+        WD_DSL_SHAPE(SP_F32, LK_F32_12, 2, 2, false)
+        WD_DSL_SHAPE(SP_F32, LK_F32_12, 3, 2, false)
+        WD_DSL_SHAPE(SP_F32, LK_F32_12, 4, 2, false)
+        WD_DSL_SHAPE(SP_F32, LK_F32_12, 1, 4, false)
+        WD_DSL_SHAPE(SP_F32, LK_F32_12, 2, 4, false)
+        WD_DSL_SHAPE(SP_F32, LK_F32_12, 3, 4, false)
+        WD_DSL_SHAPE(SP_F32, LK_F32_12, 4, 4, false)
     }
     if (lk == LK_F16_12) {
-        WD_DSL_SHAPE(SP_F32, LK_F16_12, 1, 1, false, SP_F32)
-        WD_DSL_SHAPE(SP_F32, LK_F16_12, 2, 1, false, SP_F32)
-        WD_DSL_SHAPE(SP_F32, LK_F16_12, 3, 1, false, SP_F32)
-        WD_DSL_SHAPE(SP_F32, LK_F16_12, 4, 1, false, SP_F32)
-        WD_DSL_SHAPE(SP_F32, LK_F16_12, 1, 2, false, SP_F32)
-        WD_DSL_SHAPE(SP_F32, LK_F16_12, 2, 2, false, SP_F32)
-        WD_DSL_SHAPE(SP_F32, LK_F16_12, 3, 2, false, SP_F32)
-        WD_DSL_SHAPE(SP_F32, LK_F16_12, 4, 2, false, SP_F32)
-        WD_DSL_SHAPE(SP_F32, LK_F16_12, 1, 4, false, SP_F32)
-        WD_DSL_SHAPE(SP_F32, LK_F16_12, 2, 4, false, SP_F32)
-        WD_DSL_SHAPE(SP_F32, LK_F16_12, 3, 4, false, SP_F32)
-        WD_DSL_SHAPE(SP_F32, LK_F16_12, 4, 4, false, SP_F32)
+        WD_DSL_SHAPE(SP_F32, LK_F16_12, 1, 1, false)
+        WD_DSL_SHAPE(SP_F32, LK_F16_12, 2, 1, false)
+        WD_DSL_SHAPE(SP_F32, LK_F16_12, 3, 1, false)
+        WD_DSL_SHAPE(SP_F32, LK_F16_12, 4, 1, false)
+        WD_DSL_SHAPE(SP_F32, LK_F16_12, 1, 2, false)
+        WD_DSL_SHAPE(SP_F32, LK_F16_12, 2, 2, false)
+        WD_DSL_SHAPE(SP_F32, LK_F16_12, 3, 2, false)
+        WD_DSL_SHAPE(SP_F32, LK_F16_12, 4, 2, false)
+        WD_DSL_SHAPE(SP_F32, LK_F16_12, 1, 4, false)
+        WD_DSL_SHAPE(SP_F32, LK_F16_12, 2, 4, false)
+        WD_DSL_SHAPE(SP_F32, LK_F16_12, 3, 4, false)
+        WD_DSL_SHAPE(SP_F32, LK_F16_12, 4, 4, false)
     }
     if (lk == LK_F32_18) {
-        WD_DSL_SHAPE(SP_F32, LK_F32_18, 1, 1, false, SP_F32)
-        WD_DSL_SHAPE(SP_F32, LK_F32_18, 2, 1, false, SP_F32)
-        WD_DSL_SHAPE(SP_F32, LK_F32_18, 3, 1, false, SP_F32)
-        WD_DSL_SHAPE(SP_F32, LK_F32_18, 4, 1, false, SP_F32)
-        WD_DSL_SHAPE(SP_F32, LK_F32_18, 1, 2, false, SP_F32)
-        WD_DSL_SHAPE(SP_F32, LK_F32_18, 2, 2, false, SP_F32)
-        WD_DSL_SHAPE(SP_F32, LK_F32_18, 3, 2, false, SP_F32)
-        WD_DSL_SHAPE(SP_F32, LK_F32_18, 4, 2, false, SP_F32)
-        WD_DSL_SHAPE(SP_F32, LK_F32_18, 1, 4, false, SP_F32)
-        WD_DSL_SHAPE(SP_F32, LK_F32_18, 2, 4, false, SP_F32)
-        WD_DSL_SHAPE(SP_F32, LK_F32_18, 3, 4, false, SP_F32)
-        WD_DSL_SHAPE(SP_F32, LK_F32_18, 4, 4, false, SP_F32)
+        WD_DSL_SHAPE(SP_F32, LK_F32_18, 1, 1, false)
+        WD_DSL_SHAPE(SP_F32, LK_F32_18, 2, 1, false)
+        WD_DSL_SHAPE(SP_F32, LK_F32_18, 3, 1, false)
+        WD_DSL_SHAPE(SP_F32, LK_F32_18, 4, 1, false)
+        WD_DSL_SHAPE(SP_F32, LK_F32_18, 1, 2, false)
+        WD_DSL_SHAPE(SP_F32, LK_F32_18, 2, 2, false)
+        WD_DSL_SHAPE(SP_F32, LK_F32_18, 3, 2, false)
+        WD_DSL_SHAPE(SP_F32, LK_F32_18, 4, 2, false)
+        WD_DSL_SHAPE(SP_F32, LK_F32_18, 1, 4, false)
+        WD_DSL_SHAPE(SP_F32, LK_F32_18, 2, 4, false)
+        WD_DSL_SHAPE(SP_F32, LK_F32_18, 3, 4, false)
+        WD_DSL_SHAPE(SP_F32, LK_F32_18, 4, 4, false)
     }
     return hipErrorInvalidValue;
 }

@@ -7,20 +7,20 @@ hipError_t dslash_launch_f64_d0(const DslashArgs &a, int lk, int nr, int rl, int
                               int grid, hipStream_t s)
 {
     if (lk == LK_F64_18) {
-        WD_DSL_SHAPE(SP_F64, LK_F64_18, 1, 1, false, SP_F64)
-        WD_DSL_SHAPE(SP_F64, LK_F64_18, 2, 1, false, SP_F64)
-        WD_DSL_SHAPE(SP_F64, LK_F64_18, 1, 2, false, SP_F64)
-        WD_DSL_SHAPE(SP_F64, LK_F64_18, 2, 2, false, SP_F64)
-        WD_DSL_SHAPE(SP_F64, LK_F64_18, 1, 4, false, SP_F64)
-        WD_DSL_SHAPE(SP_F64, LK_F64_18, 2, 4, false, SP_F64)
+        WD_DSL_SHAPE(SP_F64, LK_F64_18, 1, 1, false)
+        WD_DSL_SHAPE(SP_F64, LK_F64_18, 2, 1, false)
+        WD_DSL_SHAPE(SP_F64, LK_F64_18, 1, 2, false)
+        WD_DSL_SHAPE(SP_F64, LK_F64_18, 2, 2, false)
+        WD_DSL_SHAPE(SP_F64, LK_F64_18, 1, 4, false)
+        WD_DSL_SHAPE(SP_F64, LK_F64_18, 2, 4, false)
     }
     if (lk == LK_F64_12) {
-        WD_DSL_SHAPE(SP_F64, LK_F64_12, 1, 1, false, SP_F64)
-        WD_DSL_SHAPE(SP_F64, LK_F64_12, 2, 1, false, SP_F64)
-        WD_DSL_SHAPE(SP_F64, LK_F64_12, 1, 2, false, SP_F64)
-        WD_DSL_SHAPE(SP_F64, LK_F64_12, 2, 2, false, SP_F64)
-        WD_DSL_SHAPE(SP_F64, LK_F64_12, 1, 4, false, SP_F64)
-        WD_DSL_SHAPE(SP_F64, LK_F64_12, 2, 4, false, SP_F64)
+        WD_DSL_SHAPE(SP_F64, LK_F64_12, 1, 1, false)
+        WD_DSL_SHAPE(SP_F64, LK_F64_12, 2, 1, false)
+        WD_DSL_SHAPE(SP_F64, LK_F64_12, 1, 2, false)
+        WD_DSL_SHAPE(SP_F64, LK_F64_12, 2, 2, false)
+        WD_DSL_SHAPE(SP_F64, LK_F64_12, 1, 4, false)
+        WD_DSL_SHAPE(SP_F64, LK_F64_12, 2, 4, false)
     }
     return hipErrorInvalidValue;
 }

@@ -7,20 +7,20 @@ hipError_t dslash_launch_f64_d1(const DslashArgs &a, int lk, int nr, int rl, int
                               int grid, hipStream_t s)
 {
     if (lk == LK_F64_18) {
-        WD_DSL_SHAPE(SP_F64, LK_F64_18, 1, 1, true, SP_F64)
-        WD_DSL_SHAPE(SP_F64, LK_F64_18, 2, 1, true, SP_F64)
-        WD_DSL_SHAPE(SP_F64, LK_F64_18, 1, 2, true, SP_F64)
-        WD_DSL_SHAPE(SP_F64, LK_F64_18, 2, 2, true, SP_F64)
-        WD_DSL_SHAPE(SP_F64, LK_F64_18, 1, 4, true, SP_F64)
-        WD_DSL_SHAPE(SP_F64, LK_F64_18, 2, 4, true, SP_F64)
+        WD_DSL_SHAPE(SP_F64, LK_F64_18, 1, 1, true)
+        WD_DSL_SHAPE(SP_F64, LK_F64_18, 2, 1, true)
+        WD_DSL_SHAPE(SP_F64, LK_F64_18, 1, 2, true)
+        WD_DSL_SHAPE(SP_F64, LK_F64_18, 2, 2, true)
+        WD_DSL_SHAPE(SP_F64, LK_F64_18, 1, 4, true)
+        WD_DSL_SHAPE(SP_F64, LK_F64_18, 2, 4, true)
     }
     if (lk == LK_F64_12) {
-        WD_DSL_SHAPE(SP_F64, LK_F64_12, 1, 1, true, SP_F64)
-        WD_DSL_SHAPE(SP_F64, LK_F64_12, 2, 1, true, SP_F64)
-        WD_DSL_SHAPE(SP_F64, LK_F64_12, 1, 2, true, SP_F64)
-        WD_DSL_SHAPE(SP_F64, LK_F64_12, 2, 2, true, SP_F64)
-        WD_DSL_SHAPE(SP_F64, LK_F64_12, 1, 4, true, SP_F64)
-        WD_DSL_SHAPE(SP_F64, LK_F64_12, 2, 4, true, SP_F64)
+        WD_DSL_SHAPE(SP_F64, LK_F64_12, 1, 1, true)
+        WD_DSL_SHAPE(SP_F64, LK_F64_12, 2, 1, true)
+        WD_DSL_SHAPE(SP_F64, LK_F64_12, 1, 2, true)
+        WD_DSL_SHAPE(SP_F64, LK_F64_12, 2, 2, true)
+        WD_DSL_SHAPE(SP_F64, LK_F64_12, 1, 4, true)
+        WD_DSL_SHAPE(SP_F64, LK_F64_12, 2, 4, true)
     }
     return hipErrorInvalidValue;
 }

@@ -1,4 +1,4 @@
-// Stencil instantiations: int16 fixed-point spinors (per-site FP32 norm) with FP32 12-real or FP16 12-real links, FP32 solution accumulator, forward hopping.
+// Stencil instantiations: int16 fixed-point spinors (per-site FP32 norm) with FP32 12-real or FP16 12-real links, forward hopping.
 #include "dslash_impl.h"
 
 namespace wd {
@@ -7,32 +7,32 @@ hipError_t dslash_launch_i16_d0(const DslashArgs &a, int lk, int nr, int rl, int
                               int grid, hipStream_t s)
 {
     if (lk == LK_F32_12) {
-        WD_DSL_SHAPE(SP_I16, LK_F32_12, 1, 1, false, SP_F32)
-        WD_DSL_SHAPE(SP_I16, LK_F32_12, 2, 1, false, SP_F32)
-        WD_DSL_SHAPE(SP_I16, LK_F32_12, 3, 1, false, SP_F32)
-        WD_DSL_SHAPE(SP_I16, LK_F32_12, 4, 1, false, SP_F32)
-        WD_DSL_SHAPE(SP_I16, LK_F32_12, 1, 2, false, SP_F32)
-        WD_DSL_SHAPE(SP_I16, LK_F32_12, 2, 2, false, SP_F32)
-        WD_DSL_SHAPE(SP_I16, LK_F32_12, 3, 2, false, SP_F32)
-        WD_DSL_SHAPE(SP_I16, LK_F32_12, 4, 2, false, SP_F32)
-        WD_DSL_SHAPE(SP_I16, LK_F32_12, 1, 4, false, SP_F32)
-        WD_DSL_SHAPE(SP_I16, LK_F32_12, 2, 4, false, SP_F32)
-        WD_DSL_SHAPE(SP_I16, LK_F32_12, 3, 4, false, SP_F32)
-        WD_DSL_SHAPE(SP_I16, LK_F32_12, 4, 4, false, SP_F32)
+        WD_DSL_SHAPE(SP_I16, LK_F32_12, 1, 1, false)
+        WD_DSL_SHAPE(SP_I16, LK_F32_12, 2, 1, false)
+        WD_DSL_SHAPE(SP_I16, LK_F32_12, 3, 1, false)
+        WD_DSL_SHAPE(SP_I16, LK_F32_12, 4, 1, false)
+        WD_DSL_SHAPE(SP_I16, LK_F32_12, 1, 2, false)
+        WD_DSL_SHAPE(SP_I16, LK_F32_12, 2, 2, false)
+        WD_DSL_SHAPE(SP_I16, LK_F32_12, 3, 2, false)
+        WD_DSL_SHAPE(SP_I16, LK_F32_12, 4, 2, false)
+        WD_DSL_SHAPE(SP_I16, LK_F32_12, 1, 4, false)
+        WD_DSL_SHAPE(SP_I16, LK_F32_12, 2, 4, false)
+        WD_DSL_SHAPE(SP_I16, LK_F32_12, 3, 4, false)
+        WD_DSL_SHAPE(SP_I16, LK_F32_12, 4, 4, false)
     }
     if (lk == LK_F16_12) {
-        WD_DSL_SHAPE(SP_I16, LK_F16_12, 1, 1, false, SP_F32)
-        WD_DSL_SHAPE(SP_I16, LK_F16_12, 2, 1, false, SP_F32)
-        WD_DSL_SHAPE(SP_I16, LK_F16_12, 3, 1, false, SP_F32)
-        WD_DSL_SHAPE(SP_I16, LK_F16_12, 4, 1, false, SP_F32)
-        WD_DSL_SHAPE(SP_I16, LK_F16_12, 1, 2, false, SP_F32)
-        WD_DSL_SHAPE(SP_I16, LK_F16_12, 2, 2, false, SP_F32)
-        WD_DSL_SHAPE(SP_I16, LK_F16_12, 3, 2, false, SP_F32)
-        WD_DSL_SHAPE(SP_I16, LK_F16_12, 4, 2, false, SP_F32)
-        WD_DSL_SHAPE(SP_I16, LK_F16_12, 1, 4, false, SP_F32)
-        WD_DSL_SHAPE(SP_I16, LK_F16_12, 2, 4, false, SP_F32)
-        WD_DSL_SHAPE(SP_I16, LK_F16_12, 3, 4, false, SP_F32)
-        WD_DSL_SHAPE(SP_I16, LK_F16_12, 4, 4, false, SP_F32)
+        WD_DSL_SHAPE(SP_I16, LK_F16_12, 1, 1, false)
+        WD_DSL_SHAPE(SP_I16, LK_F16_12, 2, 1, false)
+        WD_DSL_SHAPE(SP_I16, LK_F16_12, 3, 1, false)
+        WD_DSL_SHAPE(SP_I16, LK_F16_12, 4, 1, false)
+        WD_DSL_SHAPE(SP_I16, LK_F16_12, 1, 2, false)
+        WD_DSL_SHAPE(SP_I16, LK_F16_12, 2, 2, false)
+        WD_DSL_SHAPE(SP_I16, LK_F16_12, 3, 2, false)
+        WD_DSL_SHAPE(SP_I16, LK_F16_12, 4, 2, false)
+        WD_DSL_SHAPE(SP_I16, LK_F16_12, 1, 4, false)
+        WD_DSL_SHAPE(SP_I16, LK_F16_12, 2, 4, false)
+        WD_DSL_SHAPE(SP_I16, LK_F16_12, 3, 4, false)
+        WD_DSL_SHAPE(SP_I16, LK_F16_12, 4, 4, false)
     }
     return hipErrorInvalidValue;
 }

@@ -15,9 +15,10 @@
 // Epilogues:
 //   EPI_PLAIN  out = D in
 //   EPI_XPAY   out = x + coef[rid] * D in        (+ |out|^2 partial sums)
-//   EPI_CGUPD  Ap  = x + coef[rid] * D in;  xs += alpha p;  r -= alpha Ap
-//              (+ |r|^2 partial sums) -- the last sweep of Mhat^dag Mhat p
-//              fused with the CG vector updates.
+//   EPI_CGUPD  Ap  = x + coef[rid] * D in;  r -= alpha Ap  (+ |r|^2 partial
+//              sums) -- the last sweep of Mhat^dag Mhat p fused with the CG
+//              residual update (the solution is advanced from the search
+//              directions of several iterations at once, by the p update).
 // Partial sums cover 16 consecutive sites of one RHS and are formed with the
 // same pairing tree for every (NR, RL, block) choice, so every launch shape
 // gives bitwise-identical vectors and norms.
@@ -214,7 +215,7 @@ __device__ __forceinline__ double group16_sum(double v)
     return v;
 }
 
-template <int SP, int LK, int NR, int RL, bool DAG, int EPI, int XP>
+template <int SP, int LK, int NR, int RL, bool DAG, int EPI>
 __global__ void __launch_bounds__(256) dslash_kernel(DslashArgs a)
 {
     typedef typename SpinorIO<SP>::real real;
@@ -327,21 +328,15 @@ __global__ void __launch_bounds__(256) dslash_kernel(DslashArgs a)
             } else {
                 const real cf = (real)a.coef[rid[r]];
                 const real al = (real)a.alpha[rid[r]];
-                real ap[24], pv[24], rv_[24];
-                typename SpinorIO<XP>::real xv[24];
+                real ap[24], rv_[24];
                 SpinorIO<SP>::template load<true>(a.x + rid[r] * a.x_rs, cs, i, ap);
-                SpinorIO<SP>::template load<true>(a.p + rid[r] * a.p_rs, cs, i, pv);
                 SpinorIO<SP>::template load<true>(a.r + rid[r] * a.r_rs, cs, i, rv_);
-                SpinorIO<XP>::template load<true>(a.xs + rid[r] * a.xs_rs, cs, i, xv);
-                typedef typename SpinorIO<XP>::real xreal;
 #pragma unroll
                 for (int k = 0; k < 24; k++) {
                     ap[k] = fmaT(cf, acc[r][k], ap[k]);
-                    xv[k] = fmaT((xreal)al, (xreal)pv[k], xv[k]);
                     rv_[k] = fmaT(-al, ap[k], rv_[k]);
                     nrm = fmaT((double)rv_[k], (double)rv_[k], nrm);
                 }
-                SpinorIO<XP>::template store<true>(a.xs + rid[r] * a.xs_rs, cs, i, xv);
                 SpinorIO<SP>::template store<true>(a.r + rid[r] * a.r_rs, cs, i, rv_);
             }
         }
@@ -353,28 +348,28 @@ __global__ void __launch_bounds__(256) dslash_kernel(DslashArgs a)
     }
 }
 
-// Runtime -> template dispatch for one (SP, XP) pair.
-#define WD_DSL_EPI(SP_, LK_, NR_, RL_, DAG_, XP_)                                                \
+// Runtime -> template dispatch over the epilogue for one instance.
+#define WD_DSL_EPI(SP_, LK_, NR_, RL_, DAG_)                                                \
     switch (epi) {                                                                                \
     case EPI_PLAIN:                                                                               \
-        hipLaunchKernelGGL((dslash_kernel<SP_, LK_, NR_, RL_, DAG_, EPI_PLAIN, XP_>), dim3(grid),  \
+        hipLaunchKernelGGL((dslash_kernel<SP_, LK_, NR_, RL_, DAG_, EPI_PLAIN>), dim3(grid),  \
                            dim3(block), a.lds, s, a);                                                 \
         return hipGetLastError();                                                                 \
     case EPI_XPAY:                                                                                \
-        hipLaunchKernelGGL((dslash_kernel<SP_, LK_, NR_, RL_, DAG_, EPI_XPAY, XP_>), dim3(grid),   \
+        hipLaunchKernelGGL((dslash_kernel<SP_, LK_, NR_, RL_, DAG_, EPI_XPAY>), dim3(grid),   \
                            dim3(block), a.lds, s, a);                                                 \
         return hipGetLastError();                                                                 \
     case EPI_CGUPD:                                                                               \
-        hipLaunchKernelGGL((dslash_kernel<SP_, LK_, NR_, RL_, DAG_, EPI_CGUPD, XP_>), dim3(grid),  \
+        hipLaunchKernelGGL((dslash_kernel<SP_, LK_, NR_, RL_, DAG_, EPI_CGUPD>), dim3(grid),  \
                            dim3(block), a.lds, s, a);                                                 \
         return hipGetLastError();                                                                 \
     default:                                                                                      \
         return hipErrorInvalidValue;                                                              \
     }
 
-#define WD_DSL_SHAPE(SP_, LK_, NR_, RL_, DAG_, XP_)                                              \
+#define WD_DSL_SHAPE(SP_, LK_, NR_, RL_, DAG_)                                                   \
     if (nr == NR_ && rl == RL_) {                                                                 \
-        WD_DSL_EPI(SP_, LK_, NR_, RL_, DAG_, XP_)                                                 \
+        WD_DSL_EPI(SP_, LK_, NR_, RL_, DAG_)                                                      \
     }
 
 }  // namespace wd

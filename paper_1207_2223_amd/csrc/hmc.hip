@@ -520,7 +520,7 @@ wd_status mhat_dag(wd_ctx *c, const double *in_e, double *out_e, double kappa)
     WD_TRY(upload_ints(c, "hmc_act", &zero, 1, &act));
     HIPCHK(pack_spinor(in_e, A, 1, 0, c->g, c->stream));
     Sweep sw;
-    sw.sp = SP_F64; sw.lk = c->lk64; sw.xp = SP_F64; sw.active = act; sw.nact = 1; sw.coef = dcf;
+    sw.sp = SP_F64; sw.lk = c->lk64; sw.active = act; sw.nact = 1; sw.coef = dcf;
     sw.dag = 1;
     sw.P = 1; sw.epi = EPI_PLAIN; sw.in = A; sw.out = T;
     WD_TRY(run_sweep(c, sw, nullptr));

@@ -9,12 +9,18 @@
 //   t2   = p - k^2 D_eo t_o,  pAp = |t2|^2           (sweep 2, fused norm)
 //   alpha = rr / pAp                                 (finalize, on device)
 //   t_o  = D_oe^dag t2                               (sweep 3)
-//   Ap   = t2 - k^2 D_eo^dag t_o;  x += alpha p;  r -= alpha Ap;  rr' = |r|^2
+//   Ap   = t2 - k^2 D_eo^dag t_o;  r -= alpha Ap;  rr' = |r|^2
 //                                                    (sweep 4, fused update)
 //   beta = rr' / rr                                  (finalize, on device)
-//   p    = r + beta p
+//   p'   = r + beta p
 // alpha and beta never leave the device; the host reads the residual norms
-// after every step of k iterations.  In mixed precision p, r and the
+// after every step of k iterations.  The solution is not touched by the
+// iteration itself: each iteration's p goes to its own slot of a ring of
+// kRing directions (and alpha to a matching history), and every kRing
+// iterations, and at the end of each step, the p update first adds
+// alpha_j p_j of the iterations since the last flush to x, in iteration
+// order -- the same roundings as x += alpha p once per iteration, with the
+// solution read and written once per flush instead of once per iteration.  In mixed precision p, r and the
 // intermediates are FP32 or FP16 (per-site norm) and the solution increment
 // accumulates in FP32; when |r| falls below delta * (its maximum since the
 // last update), or the sloppy residual claims convergence, the FP64 solution
@@ -61,6 +67,7 @@ struct BatchSolver {
         int sp, lk, xp;
         Field P, R, T2, TO, X;
         bool sloppy;  // X is an increment added to x64 at reliable updates
+        std::vector<Field> Pr;  // even-odd: ring of search directions, Pr[0] == P
     };
 
     // a slot whose FP64 true residual has not reached a new minimum over this
@@ -72,6 +79,9 @@ struct BatchSolver {
     // than this factor (in |r|^2): the recursion has lost its accuracy
     static constexpr double kDriftRestart = 4.0;
     static constexpr int kScalars = 9;  // per-slot device scalars (bb .. rr_s)
+    // directions kept between solution flushes (even-odd lanes; a mixed
+    // solve's FP64 lane, used by escalated RHS only, flushes every iteration)
+    static constexpr int kRing = kMaxRing;
     static constexpr size_t kMaxGraphs = 32;  // captured steps kept per context
 
     wd_ctx *c = nullptr;
@@ -85,6 +95,7 @@ struct BatchSolver {
     double *bb = nullptr, *rr = nullptr, *alpha = nullptr, *beta = nullptr, *dre = nullptr, *dim = nullptr;
     double *coef1 = nullptr, *coef2 = nullptr, *partial = nullptr, *partial2 = nullptr;
     double *rr_s = nullptr;  // recursive |r|^2 saved at a reliable update
+    double *ahist = nullptr; // alpha of the iterations since the last flush, [kRing][cap]
     double *hbuf = nullptr;  // pinned, cap doubles
     int *act = nullptr, *act64 = nullptr, *lst = nullptr;  // device id lists
     std::vector<int> state, iters, iters64, rus, status, last_ru, stall, active, active64;
@@ -92,6 +103,7 @@ struct BatchSolver {
     bool trace = false;
 
     std::string nm(const char *s) const { return pre + s; }
+    std::string ring_name(int j) const { return pre + (mixed ? "ps@" : "p@") + std::to_string(j); }
 
     wd_status init(wd_ctx *ctx, int capacity, const wd_solver_params &prm, const std::string &prefix)
     {
@@ -150,6 +162,8 @@ struct BatchSolver {
         act = (int *)vp;
         act64 = act + cap;
         lst = act64 + cap;
+        WD_TRY(ws_get(c, nm("ahist"), sizeof(double) * kRing * cap, &vp));
+        ahist = (double *)vp;
         WD_TRY(alloc_field(c, nm("b"), SP_F64, nsub, cap, &b64));
         WD_TRY(alloc_field(c, nm("x"), SP_F64, nsub, cap, &x64));
         WD_TRY(alloc_field(c, nm("r"), SP_F64, nsub, cap, &r64));
@@ -157,17 +171,24 @@ struct BatchSolver {
         WD_TRY(alloc_field(c, nm("te"), SP_F64, nsub, cap, &te64));
         WD_TRY(alloc_field(c, nm("ap"), SP_F64, nsub, cap, &Ap64));
         WD_TRY(alloc_field(c, nm("p"), SP_F64, nsub, cap, &p64));
-        lane_d = Lane{SP_F64, c->lk64, SP_F64, p64, r64, te64, to64, x64, false};
+        lane_d = Lane{SP_F64, c->lk64, SP_F64, p64, r64, te64, to64, x64, false, {p64}};
         if (mixed) {
             WD_TRY(alloc_field(c, nm("ps"), sp, 1, cap, &ps));
             WD_TRY(alloc_field(c, nm("rs"), sp, 1, cap, &rs));
             WD_TRY(alloc_field(c, nm("t2s"), sp, 1, cap, &t2s));
             WD_TRY(alloc_field(c, nm("tos"), sp, 1, cap, &tos));
             WD_TRY(alloc_field(c, nm("xs"), xp, 1, cap, &xs));
-            lane_s = Lane{sp, lk, xp, ps, rs, t2s, tos, xs, true};
-        } else {
-            lane_s = lane_d;
+            lane_s = Lane{sp, lk, xp, ps, rs, t2s, tos, xs, true, {ps}};
         }
+        // the ring slots 1 .. kRing-1 of the lane that carries the iteration
+        Lane &L = mixed ? lane_s : lane_d;
+        if (p.eo)
+            for (int j = 1; j < kRing; j++) {
+                Field f;
+                WD_TRY(alloc_field(c, ring_name(j), L.sp, 1, cap, &f));
+                L.Pr.push_back(f);
+            }
+        if (!mixed) lane_s = lane_d;
         if (hbuf) (void)hipHostFree(hbuf);
         hbuf = nullptr;
         WD_HIP(hipHostMalloc((void **)&hbuf, sizeof(double) * cap, hipHostMallocDefault));
@@ -202,6 +223,12 @@ struct BatchSolver {
             for (auto f : {std::make_pair("ps", &ps), std::make_pair("rs", &rs), std::make_pair("t2s", &t2s),
                            std::make_pair("tos", &tos), std::make_pair("xs", &xs)})
                 sp_list.push_back({nm(f.first), (size_t)f.second->rs, 0});
+        // ring slots hold no state across steps (the solution is flushed at
+        // every step's end, and the direction is back in slot 0), nor does
+        // the alpha history
+        const Lane &RL = mixed ? lane_s : lane_d;
+        for (int j = 1; j < (int)RL.Pr.size(); j++) sp_list.push_back({ring_name(j), (size_t)RL.Pr[j].rs, 2});
+        sp_list.push_back({nm("ahist"), sizeof(double) * kRing, 2});
         const hipStream_t s = c->stream;
         WD_HIP(hipStreamSynchronize(s));
         std::vector<void *> fresh(sp_list.size(), nullptr);
@@ -296,7 +323,6 @@ struct BatchSolver {
         Sweep sw;
         sw.sp = spp;
         sw.lk = lkk;
-        sw.xp = spp;
         sw.active = ids;
         sw.nact = n;
         if (p.eo) {
@@ -334,34 +360,66 @@ struct BatchSolver {
         return WD_OK;
     }
 
-    // One CG iteration of the listed RHS of a lane (see the file header).
-    wd_status iterate(const Lane &L, const int *ids, int n)
+    // Ring slots of a lane (1 for the full-lattice iteration).
+    static int ring_of(const Lane &L) { return (int)L.Pr.size(); }
+
+    // One CG iteration of the listed RHS of a lane (see the file header):
+    // iteration j of the lane's ring cycle; flush: the p update advances the
+    // solution by the directions of iterations 0..j and puts the new
+    // direction back in slot 0.
+    wd_status iterate(const Lane &L, const int *ids, int n, int j, bool flush)
     {
         const hipStream_t s = c->stream;
         if (p.eo) {
+            const Field &Pj = L.Pr[j];
             Sweep sw;
-            sw.sp = L.sp; sw.lk = L.lk; sw.xp = L.xp; sw.active = ids; sw.nact = n;
+            sw.sp = L.sp; sw.lk = L.lk; sw.active = ids; sw.nact = n;
             sw.coef = coef2;
-            sw.P = 1; sw.dag = 0; sw.epi = EPI_PLAIN; sw.in = L.P; sw.out = L.TO;
+            sw.P = 1; sw.dag = 0; sw.epi = EPI_PLAIN; sw.in = Pj; sw.out = L.TO;
             WD_TRY(run_sweep(c, sw, nullptr));
-            sw.P = 0; sw.epi = EPI_XPAY; sw.in = L.TO; sw.x = L.P; sw.out = L.T2;
+            sw.P = 0; sw.epi = EPI_XPAY; sw.in = L.TO; sw.x = Pj; sw.out = L.T2;
             sw.partial = partial; sw.pstride = pstride; sw.pw_off = 0;
             WD_TRY(run_sweep(c, sw, nullptr));
-            HIPCHK(blas_finalize(partial, pstride, nwD, ids, n, FIN_ALPHA, rr, alpha, beta, nullptr, s));
+            HIPCHK(blas_finalize(partial, pstride, nwD, ids, n, FIN_ALPHA, rr, alpha, beta,
+                                 ahist + (size_t)j * cap, s));
             sw.partial = nullptr;
             sw.P = 1; sw.dag = 1; sw.epi = EPI_PLAIN; sw.in = L.T2; sw.out = L.TO;
             WD_TRY(run_sweep(c, sw, nullptr));
-            sw.P = 0; sw.epi = EPI_CGUPD; sw.in = L.TO; sw.x = L.T2; sw.p = L.P; sw.xs = L.X; sw.r = L.R;
+            sw.P = 0; sw.epi = EPI_CGUPD; sw.in = L.TO; sw.x = L.T2; sw.r = L.R;
             sw.alpha = alpha; sw.partial = partial;
             WD_TRY(run_sweep(c, sw, nullptr));
             HIPCHK(blas_finalize(partial, pstride, nw1, ids, n, FIN_BETA, rr, alpha, beta, nullptr, s));
+            if (flush)
+                HIPCHK(blas_p_update_ring(L.Pr.data(), j + 1, L.Pr[0], L.R, beta, true, L.X, ahist, cap, Vh, ids,
+                                          n, s));
+            else
+                HIPCHK(blas_p_update_ring(&L.Pr[j], 1, L.Pr[j + 1], L.R, beta, false, L.X, ahist, cap, Vh, ids,
+                                          n, s));
         } else {
             WD_TRY(apply_A(L.sp, L.lk, L.P, Ap64, ids, n, true));
             HIPCHK(blas_finalize(partial, pstride, nwD, ids, n, FIN_ALPHA, rr, alpha, beta, nullptr, s));
             HIPCHK(blas_cg_update(L.X, L.P, L.R, Ap64, alpha, Vh, ids, n, partial, pstride, s));
             HIPCHK(blas_finalize(partial, pstride, nwF, ids, n, FIN_BETA, rr, alpha, beta, nullptr, s));
+            HIPCHK(blas_p_update(L.P, L.R, beta, Vh, ids, n, s));
         }
-        HIPCHK(blas_p_update(L.P, L.R, beta, Vh, ids, n, s));
+        return WD_OK;
+    }
+
+    // The k iterations of a step on both lanes: iteration kk is slot kk mod
+    // ring of each lane's cycle; a lane flushes at the end of its ring and at
+    // the step's end.
+    wd_status iterate_step(int k, int nact, int nact64)
+    {
+        for (int kk = 0; kk < k; kk++) {
+            if (nact) {
+                const int R = ring_of(lane_s), j = kk % R;
+                WD_TRY(iterate(lane_s, act, nact, j, j == R - 1 || kk == k - 1));
+            }
+            if (nact64) {
+                const int R = ring_of(lane_d), j = kk % R;
+                WD_TRY(iterate(lane_d, act64, nact64, j, j == R - 1 || kk == k - 1));
+            }
+        }
         return WD_OK;
     }
 
@@ -501,14 +559,17 @@ struct BatchSolver {
         for (const void *q : {(const void *)c->links64, (const void *)c->links32, (const void *)c->links16,
                               (const void *)c->links32r, (const void *)coef1, (const void *)coef2,
                               (const void *)rr, (const void *)alpha, (const void *)beta, (const void *)partial,
-                              (const void *)act, (const void *)act64})
+                              (const void *)act, (const void *)act64, (const void *)ahist})
             add((unsigned long long)(uintptr_t)q);
+        add((unsigned long long)cap);
         for (const Lane *L : {&lane_s, &lane_d}) {
             addf(L->P);
             addf(L->R);
             addf(L->T2);
             addf(L->TO);
             addf(L->X);
+            add((unsigned long long)L->Pr.size());
+            for (const Field &f : L->Pr) addf(f);
         }
         addf(Ap64);
         return key;
@@ -529,11 +590,7 @@ struct BatchSolver {
             const hipStream_t saved = c->stream;
             WD_HIP(hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeThreadLocal));
             c->stream = c->capture_stream;
-            wd_status st = WD_OK;
-            for (int kk = 0; kk < k && st == WD_OK; kk++) {
-                if (nact) st = iterate(lane_s, act, nact);
-                if (st == WD_OK && nact64) st = iterate(lane_d, act64, nact64);
-            }
+            const wd_status st = iterate_step(k, nact, nact64);
             c->stream = saved;
             hipGraph_t gph = nullptr;
             const hipError_t e = hipStreamEndCapture(c->capture_stream, &gph);
@@ -564,10 +621,7 @@ struct BatchSolver {
         if (p.graphs && !c->timing) {
             WD_TRY(run_graph(k, nact, nact64));
         } else {
-            for (int kk = 0; kk < k; kk++) {
-                if (nact) WD_TRY(iterate(lane_s, act, nact));
-                if (nact64) WD_TRY(iterate(lane_d, act64, nact64));
-            }
+            WD_TRY(iterate_step(k, nact, nact64));
         }
         for (int j : active) iters[j] += k;
         for (int j : active64) {

@@ -113,25 +113,21 @@ static wd_status prec_decode(const wd_ctx *c, int prec, int *sp, int *lk, int *x
 }
 
 struct TuneFields {
-    Field in, out, x, p, xs, r, xs0, r0, outref, xsref, rref;
+    Field in, out, x, r, r0, outref, rref;
     double *coef, *alpha, *partial, *pref;
     int *act;
     int pstride;
 };
 
-static wd_status tune_fields(wd_ctx *c, int sp, int xp, int nrhs, TuneFields *t)
+static wd_status tune_fields(wd_ctx *c, int sp, int nrhs, TuneFields *t)
 {
     WD_TRY(alloc_field(c, "tn_in", sp, 1, nrhs, &t->in));
     WD_TRY(alloc_field(c, "tn_out", sp, 1, nrhs, &t->out));
     WD_TRY(alloc_field(c, "tn_x", sp, 1, nrhs, &t->x));
-    WD_TRY(alloc_field(c, "tn_p", sp, 1, nrhs, &t->p));
     WD_TRY(alloc_field(c, "tn_r", sp, 1, nrhs, &t->r));
     WD_TRY(alloc_field(c, "tn_r0", sp, 1, nrhs, &t->r0));
     WD_TRY(alloc_field(c, "tn_rref", sp, 1, nrhs, &t->rref));
     WD_TRY(alloc_field(c, "tn_outref", sp, 1, nrhs, &t->outref));
-    WD_TRY(alloc_field(c, "tn_xs", xp, 1, nrhs, &t->xs));
-    WD_TRY(alloc_field(c, "tn_xs0", xp, 1, nrhs, &t->xs0));
-    WD_TRY(alloc_field(c, "tn_xsref", xp, 1, nrhs, &t->xsref));
     const int Vh = (int)c->Vh;
     t->pstride = 2 * ngroups_of(Vh) + 1;
     std::vector<double> cf(nrhs), al(nrhs);
@@ -152,9 +148,7 @@ static wd_status tune_fields(wd_ctx *c, int sp, int xp, int nrhs, TuneFields *t)
     hipStream_t s = c->stream;
     HIPCHK(fill(t->in, Vh, nrhs, 1, s));
     HIPCHK(fill(t->x, Vh, nrhs, 2, s));
-    HIPCHK(fill(t->p, Vh, nrhs, 3, s));
     HIPCHK(fill(t->r0, Vh, nrhs, 4, s));
-    HIPCHK(fill(t->xs0, Vh, nrhs, 5, s));
     HIPCHK(hipMemsetAsync(t->partial, 0, sizeof(double) * t->pstride * nrhs, s));
     return WD_OK;
 }
@@ -242,7 +236,7 @@ extern "C" wd_status wd_tune(wd_ctx *c, int nrhs, int prec, char *report, size_t
     const int Vh = (int)c->Vh;
     hipStream_t s = c->stream;
     TuneFields t;
-    WD_TRY(tune_fields(c, sp, xp, nrhs, &t));
+    WD_TRY(tune_fields(c, sp, nrhs, &t));
     void *vp;
     WD_TRY(ws_get(c, "tn_count", sizeof(unsigned) * 4, &vp));
     unsigned *dcount = (unsigned *)vp;
@@ -276,14 +270,13 @@ extern "C" wd_status wd_tune(wd_ctx *c, int nrhs, int prec, char *report, size_t
     const Kind kinds[4] = {{1, 0, EPI_PLAIN, "D_oe"}, {0, 0, EPI_XPAY, "xpay D_eo +norm"},
                            {1, 1, EPI_PLAIN, "D_oe^dag"}, {0, 1, EPI_CGUPD, "cg-update D_eo^dag"}};
     const size_t sb = (size_t)t.in.rs;  // bytes per RHS of a spinor field (padded)
-    const size_t xb = (size_t)t.xs.rs;
     std::string rep;
     wd_status st = WD_OK;
     const char *cache = getenv("WD_TUNE_CACHE");
     for (const Kind &k : kinds) {
         Sweep sw;
-        sw.sp = sp; sw.lk = lk; sw.xp = xp; sw.dag = k.dag; sw.epi = k.epi; sw.P = k.P;
-        sw.in = t.in; sw.out = t.out; sw.x = t.x; sw.p = t.p; sw.xs = t.xs; sw.r = t.r;
+        sw.sp = sp; sw.lk = lk; sw.dag = k.dag; sw.epi = k.epi; sw.P = k.P;
+        sw.in = t.in; sw.out = t.out; sw.x = t.x; sw.r = t.r;
         sw.coef = t.coef; sw.alpha = t.alpha; sw.active = t.act; sw.nact = nrhs;
         sw.partial = (k.epi == EPI_PLAIN) ? nullptr : t.partial;
         sw.pstride = t.pstride;
@@ -313,7 +306,6 @@ extern "C" wd_status wd_tune(wd_ctx *c, int nrhs, int prec, char *report, size_t
                 const TuneCfg cf = list[q];
                 if (k.epi == EPI_CGUPD) {
                     HIPCHK(hipMemcpyAsync(t.r.base, t.r0.base, sb * nrhs, hipMemcpyDeviceToDevice, s));
-                    HIPCHK(hipMemcpyAsync(t.xs.base, t.xs0.base, xb * nrhs, hipMemcpyDeviceToDevice, s));
                 } else {
                     HIPCHK(fill(t.out, Vh, nrhs, 1000 + (unsigned)q, s));
                 }
@@ -323,15 +315,12 @@ extern "C" wd_status wd_tune(wd_ctx *c, int nrhs, int prec, char *report, size_t
                 if (q == 0) {
                     HIPCHK(hipMemcpyAsync(t.outref.base, t.out.base, sb * nrhs, hipMemcpyDeviceToDevice, s));
                     HIPCHK(hipMemcpyAsync(t.rref.base, t.r.base, sb * nrhs, hipMemcpyDeviceToDevice, s));
-                    HIPCHK(hipMemcpyAsync(t.xsref.base, t.xs.base, xb * nrhs, hipMemcpyDeviceToDevice, s));
                     HIPCHK(hipMemcpyAsync(t.pref, t.partial, sizeof(double) * t.pstride * nrhs,
                                           hipMemcpyDeviceToDevice, s));
                 } else {
                     unsigned bad = 0;
                     if (k.epi == EPI_CGUPD) {
                         WD_TRY(compare(c, t.r.base, t.rref.base, sb * nrhs, dcount, nd));
-                        bad += *nd;
-                        WD_TRY(compare(c, t.xs.base, t.xsref.base, xb * nrhs, dcount, nd));
                         bad += *nd;
                     } else {
                         WD_TRY(compare(c, t.out.base, t.outref.base, sb * nrhs, dcount, nd));
@@ -436,13 +425,12 @@ extern "C" wd_status wd_bench_dslash(wd_ctx *c, int nrhs, int prec, int epi, int
     int sp, lk, xp;
     WD_TRY(prec_decode(c, prec, &sp, &lk, &xp));
     TuneFields t;
-    WD_TRY(tune_fields(c, sp, xp, nrhs, &t));
+    WD_TRY(tune_fields(c, sp, nrhs, &t));
     hipStream_t s = c->stream;
     HIPCHK(hipMemcpyAsync(t.r.base, t.r0.base, (size_t)t.r.rs * nrhs, hipMemcpyDeviceToDevice, s));
-    HIPCHK(hipMemcpyAsync(t.xs.base, t.xs0.base, (size_t)t.xs.rs * nrhs, hipMemcpyDeviceToDevice, s));
     Sweep sw;
-    sw.sp = sp; sw.lk = lk; sw.xp = xp; sw.dag = 0; sw.epi = epi; sw.P = (epi == EPI_PLAIN) ? 1 : 0;
-    sw.in = t.in; sw.out = t.out; sw.x = t.x; sw.p = t.p; sw.xs = t.xs; sw.r = t.r;
+    sw.sp = sp; sw.lk = lk; sw.dag = 0; sw.epi = epi; sw.P = (epi == EPI_PLAIN) ? 1 : 0;
+    sw.in = t.in; sw.out = t.out; sw.x = t.x; sw.r = t.r;
     sw.coef = t.coef; sw.alpha = t.alpha; sw.active = t.act; sw.nact = nrhs;
     sw.partial = (epi == EPI_PLAIN) ? nullptr : t.partial;
     sw.pstride = t.pstride;

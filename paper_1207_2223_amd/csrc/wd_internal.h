@@ -56,11 +56,7 @@ struct DslashArgs {
     const char *x;         // xpay: out = x + coef*D in
     long long x_rs;
     const double *coef;    // [rid]
-    const char *p;         // CG update: xs += alpha p, r -= alpha (x + coef*D in)
-    long long p_rs;
-    char *xs;
-    long long xs_rs;
-    char *r;
+    char *r;               // CG update: r -= alpha (x + coef*D in)
     long long r_rs;
     const double *alpha;   // [rid]
     const int *active;     // RHS ids processed by this launch
@@ -104,6 +100,15 @@ hipError_t blas_norm(const Field &a, int Vh, const int *active, int nact, double
                      int pstride, hipStream_t s);
 hipError_t blas_p_update(const Field &p, const Field &r, const double *beta, int Vh,
                          const int *active, int nact, hipStream_t s);
+// The CG search-direction update of an even-odd iteration with the solution
+// update deferred: p_dst = r + beta p[m-1] with p[j] the directions of the
+// last m iterations (slots of a ring, p[m-1] the current one); with flush,
+// first x += alpha_j p[j] for j = 0 .. m-1 in that order (alpha_j =
+// ahist[j*ahs + rid]), the same roundings as advancing x every iteration.
+constexpr int kMaxRing = 8;
+hipError_t blas_p_update_ring(const Field *p, int m, const Field &pdst, const Field &r, const double *beta,
+                              bool flush, const Field &x, const double *ahist, int ahs, int Vh,
+                              const int *active, int nact, hipStream_t s);
 hipError_t blas_cg_update(const Field &x, const Field &p, const Field &r, const Field &Ap,
                           const double *alpha, int Vh, const int *active, int nact,
                           double *partial, int pstride, hipStream_t s);
@@ -196,11 +201,10 @@ wd_status decode_prec(const wd_ctx *c, int prec, int *sp, int *lk, int *xp);
 struct Sweep {
     int sp = SP_F64;
     int lk = LK_F64_18;
-    int xp = SP_F64;
     int dag = 0;
     int epi = EPI_PLAIN;
     int P = 0;
-    Field in, out, x, p, xs, r;
+    Field in, out, x, r;
     const double *coef = nullptr;
     const double *alpha = nullptr;
     const int *active = nullptr;
