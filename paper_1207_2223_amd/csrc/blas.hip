@@ -10,7 +10,7 @@ namespace wd {
 namespace {
 
 constexpr int kBlock = 256;
-constexpr int kFinBlock = 1024;
+constexpr int kFinBlock = kFinLanes;
 
 __device__ __forceinline__ double sum16(double v)
 {
@@ -308,22 +308,6 @@ __global__ void __launch_bounds__(kBlock) k_xpay_ratio(FArg p, FArg r, const dou
     SpinorIO<SP>::store(site_base(p, rid, sub), p.cs, i, pv);
 }
 
-// Lane v's share of a finalize sum: partials v, v + kFinBlock, ... added in
-// that order; loaded four at a time so that the loads overlap (the zeros
-// padding a short last group change no value, at most the sign of a zero).
-__device__ __forceinline__ double lane_sum(const double *pp, int nw, int v)
-{
-    double acc = 0.0;
-    for (int w = v; w < nw; w += 4 * kFinBlock) {
-        double x[4];
-#pragma unroll
-        for (int m = 0; m < 4; m++) x[m] = (w + m * kFinBlock < nw) ? pp[w + m * kFinBlock] : 0.0;
-#pragma unroll
-        for (int m = 0; m < 4; m++) acc += x[m];
-    }
-    return acc;
-}
-
 // One work-group per active RHS: fixed-order sum of its partials, then the
 // CG scalar update selected by mode.
 __global__ void __launch_bounds__(kFinBlock) k_finalize(const double *partial, int pstride, int nw,
@@ -332,7 +316,7 @@ __global__ void __launch_bounds__(kFinBlock) k_finalize(const double *partial, i
 {
     __shared__ double sh[kFinBlock];
     const int rid = active[blockIdx.x];
-    const double v = lane_sum(partial + (size_t)rid * pstride, nw, threadIdx.x);
+    const double v = fin_lane_sum(partial + (size_t)rid * pstride, nw, threadIdx.x);
     sh[threadIdx.x] = v;
     __syncthreads();
     for (int off = kFinBlock / 2; off > 0; off >>= 1) {
@@ -344,14 +328,8 @@ __global__ void __launch_bounds__(kFinBlock) k_finalize(const double *partial, i
         if (mode == FIN_STORE) {
             out[rid] = s;
         } else if (mode == FIN_ALPHA) {
-            // s = p.Ap = |M p|^2 ; breakdown (s <= 0 or not finite) poisons rr
-            if (s > 0.0 && s < INFINITY) {
-                alpha[rid] = rr[rid] / s;
-            } else {
-                alpha[rid] = 0.0;
-                rr[rid] = NAN;
-            }
-            if (out) out[rid] = alpha[rid];  // the iteration's slot of the alpha history
+            // s = p.Ap = |M p|^2; out: the iteration's slot of the alpha history
+            fin_alpha_update(s, rid, rr, alpha, out);
         } else if (mode == FIN_BETA) {
             beta[rid] = s / rr[rid];
             rr[rid] = s;

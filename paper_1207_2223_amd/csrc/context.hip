@@ -149,6 +149,13 @@ wd_status run_sweep(wd_ctx *c, const Sweep &sw, const TuneCfg *cfg)
     a.partial = sw.partial;
     a.pstride = sw.pstride;
     a.pw_off = sw.pw_off;
+    a.fin_blocks = sw.fin_partial ? sw.nact : 0;
+    a.fin_nw = sw.fin_nw;
+    a.fin_pstride = sw.fin_pstride;
+    a.fin_partial = sw.fin_partial;
+    a.fin_rr = sw.fin_rr;
+    a.fin_alpha = sw.fin_alpha;
+    a.fin_out = sw.fin_out;
     if (t.occ != 0 && (t.occ < 2 || t.occ > kMaxOcc))
         return set_error(WD_ERR_ARG, "work-group cap %d not 0 or in 2..%d", t.occ, kMaxOcc);
     a.lds = occ_lds_bytes(t.occ);
@@ -166,7 +173,7 @@ wd_status run_sweep(wd_ctx *c, const Sweep &sw, const TuneCfg *cfg)
         a.nzl = c->g.L[remap_slab_dim(t.remap)] / 8;
         a.nys = remap_stripes(t.remap);
     }
-    const long long grid = (long long)ntiles * a.G;
+    const long long grid = (long long)ntiles * a.G + a.fin_blocks;
     if (grid > 0x7fffffffLL) return set_error(WD_ERR_ARG, "grid too large");
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (c->timing) {

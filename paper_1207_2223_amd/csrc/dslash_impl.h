@@ -220,13 +220,27 @@ __global__ void __launch_bounds__(256) dslash_kernel(DslashArgs a)
 {
     typedef typename SpinorIO<SP>::real real;
     static_assert(sizeof(typename LinkIO<LK>::real) == sizeof(real), "link/spinor precision pair");
+    // the leading work-groups, if any, finalize the CG alpha of one active
+    // RHS each (first wavefront; the order of every CG scalar's sum), the
+    // others are the stencil's tiles; they are independent of each other
+    if ((int)blockIdx.x < a.fin_blocks) {
+        if (threadIdx.x < 64) {
+            const int rid = a.active[blockIdx.x];
+            const double s = fin_wave_sum(a.fin_partial + (size_t)rid * a.fin_pstride, a.fin_nw, (int)threadIdx.x);
+            if (threadIdx.x == 0) fin_alpha_update(s, rid, a.fin_rr, a.fin_alpha, a.fin_out);
+        }
+        return;
+    }
+    // tile blocks: index and count without the finalize blocks (a block's
+    // XCD is still its index mod 8, shifted alike for all of them)
+    const int bid = (int)blockIdx.x - a.fin_blocks, nblk = (int)gridDim.x - a.fin_blocks;
     int tile, grp;
     if (a.remap == 7) {
         // z-slab per XCD as order 2, but RHS-group-major: the XCD sweeps its
         // whole slab for one RHS group before the next, so only NR*RL RHS of
         // spinor data are in flight (the links are re-read per group).
-        const int x = blockIdx.x & 7, j = blockIdx.x >> 3;
-        const int tx = (int)(gridDim.x / 8) / a.G;  // tiles per XCD
+        const int x = bid & 7, j = bid >> 3;
+        const int tx = (nblk / 8) / a.G;  // tiles per XCD
         grp = j / tx;
         const int sidx = j - grp * tx;
         const int q = sidx % a.tpp, zt = sidx / a.tpp;
@@ -238,7 +252,7 @@ __global__ void __launch_bounds__(256) dslash_kernel(DslashArgs a)
         // before and after it on the same XCD, its z-neighbours ntl tiles
         // away.  Order 5 takes (tile-in-plane, z, t), order 6 (z,
         // tile-in-plane, t), slowest to fastest.
-        const int x = blockIdx.x & 7, j = blockIdx.x >> 3;
+        const int x = bid & 7, j = bid >> 3;
         const int sidx = j / a.G;
         grp = j - sidx * a.G;
         const int tl = sidx % a.nzl, rest = sidx / a.nzl;
@@ -260,7 +274,7 @@ __global__ void __launch_bounds__(256) dslash_kernel(DslashArgs a)
         // tile-in-stripe) order, z fastest among planes, so the t and z
         // neighbours of a tile were read a few tiles earlier on the same XCD
         // (same L2), and a narrower stripe keeps that window smaller.
-        const int x = blockIdx.x & 7, j = blockIdx.x >> 3;
+        const int x = bid & 7, j = bid >> 3;
         const int sidx = j / a.G;
         grp = j - sidx * a.G;
         const int tps = a.tpp / a.nys;
@@ -269,7 +283,7 @@ __global__ void __launch_bounds__(256) dslash_kernel(DslashArgs a)
         const int t = ts % a.g.L[3], st = ts / a.g.L[3];
         tile = ((t * a.g.L[2]) + x * a.nzl + zl) * a.tpp + st * tps + qs;
     } else {
-        const int L = a.remap ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+        const int L = a.remap ? xcd_remap(bid, nblk) : bid;
         tile = L / a.G;
         grp = L - tile * a.G;
     }

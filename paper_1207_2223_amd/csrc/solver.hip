@@ -7,8 +7,8 @@
 // active RHS, four stencil sweeps and one vector kernel:
 //   t_o  = D_oe p                                   (sweep 1)
 //   t2   = p - k^2 D_eo t_o,  pAp = |t2|^2           (sweep 2, fused norm)
-//   alpha = rr / pAp                                 (finalize, on device)
-//   t_o  = D_oe^dag t2                               (sweep 3)
+//   t_o  = D_oe^dag t2                               (sweep 3; its leading
+//   alpha = rr / pAp                                  work-groups finalize alpha)
 //   Ap   = t2 - k^2 D_eo^dag t_o;  r -= alpha Ap;  rr' = |r|^2
 //                                                    (sweep 4, fused update)
 //   beta = rr' / rr                                  (finalize, on device)
@@ -380,11 +380,15 @@ struct BatchSolver {
             sw.P = 0; sw.epi = EPI_XPAY; sw.in = L.TO; sw.x = Pj; sw.out = L.T2;
             sw.partial = partial; sw.pstride = pstride; sw.pw_off = 0;
             WD_TRY(run_sweep(c, sw, nullptr));
-            HIPCHK(blas_finalize(partial, pstride, nwD, ids, n, FIN_ALPHA, rr, alpha, beta,
-                                 ahist + (size_t)j * cap, s));
+            // sweep 3 does not use alpha: it finalizes alpha = rr / p.Ap of
+            // sweep 2's partials in extra work-groups while it runs, for
+            // sweep 4 (one dispatch fewer than a separate finalize)
             sw.partial = nullptr;
             sw.P = 1; sw.dag = 1; sw.epi = EPI_PLAIN; sw.in = L.T2; sw.out = L.TO;
+            sw.fin_partial = partial; sw.fin_nw = nwD; sw.fin_pstride = pstride;
+            sw.fin_rr = rr; sw.fin_alpha = alpha; sw.fin_out = ahist + (size_t)j * cap;
             WD_TRY(run_sweep(c, sw, nullptr));
+            sw.fin_partial = nullptr;
             sw.P = 0; sw.epi = EPI_CGUPD; sw.in = L.TO; sw.x = L.T2; sw.r = L.R;
             sw.alpha = alpha; sw.partial = partial;
             WD_TRY(run_sweep(c, sw, nullptr));

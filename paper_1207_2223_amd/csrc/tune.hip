@@ -266,9 +266,14 @@ extern "C" wd_status wd_tune(wd_ctx *c, int nrhs, int prec, char *report, size_t
                     cands.push_back(q);
                 }
 
-    struct Kind { int P, dag, epi; const char *name; };
-    const Kind kinds[4] = {{1, 0, EPI_PLAIN, "D_oe"}, {0, 0, EPI_XPAY, "xpay D_eo +norm"},
-                           {1, 1, EPI_PLAIN, "D_oe^dag"}, {0, 1, EPI_CGUPD, "cg-update D_eo^dag"}};
+    // (the solver's D_oe^dag sweep also finalizes alpha in extra work-groups:
+    // timed here with them, on the partials and scalars of tn_fin)
+    struct Kind { int P, dag, epi; const char *name; bool fin; };
+    const Kind kinds[4] = {{1, 0, EPI_PLAIN, "D_oe", false}, {0, 0, EPI_XPAY, "xpay D_eo +norm", false},
+                           {1, 1, EPI_PLAIN, "D_oe^dag", true}, {0, 1, EPI_CGUPD, "cg-update D_eo^dag", false}};
+    WD_TRY(ws_get(c, "tn_fin", sizeof(double) * 3 * nrhs, &vp));
+    double *fin = (double *)vp;
+    HIPCHK(fill_bytes(fin, sizeof(double) * 3 * nrhs, 0x3Fu, s));  // finite positive doubles
     const size_t sb = (size_t)t.in.rs;  // bytes per RHS of a spinor field (padded)
     std::string rep;
     wd_status st = WD_OK;
@@ -280,6 +285,14 @@ extern "C" wd_status wd_tune(wd_ctx *c, int nrhs, int prec, char *report, size_t
         sw.coef = t.coef; sw.alpha = t.alpha; sw.active = t.act; sw.nact = nrhs;
         sw.partial = (k.epi == EPI_PLAIN) ? nullptr : t.partial;
         sw.pstride = t.pstride;
+        if (k.fin) {
+            sw.fin_partial = t.pref;
+            sw.fin_nw = ngroups_of(Vh);
+            sw.fin_pstride = t.pstride;
+            sw.fin_rr = fin;
+            sw.fin_alpha = fin + nrhs;
+            sw.fin_out = fin + 2 * nrhs;
+        }
 
         // Runs list[0] (the reference shape) and then every other entry on
         // identical inputs, with every output poisoned first so that a shape

@@ -790,4 +790,87 @@ __device__ __forceinline__ int xcd_remap(int b, int nb)
 }
 
 
+// ---------------------------------------------------------------------------
+// Fixed-order reduction of per-site-group partial sums (the CG dot products)
+// ---------------------------------------------------------------------------
+// A sum of nw partials is formed over kFinLanes virtual lanes: lane v adds
+// partials v, v + kFinLanes, v + 2 kFinLanes, ... in that order (loaded four
+// at a time; the zeros padding a short last group change no value, at most
+// the sign of a zero), then the lanes are combined by a halving tree (lane
+// i += lane i + h for h = kFinLanes/2 .. 1).  Every place that finalizes a CG
+// scalar uses this order, so the scalars do not depend on where it runs.
+constexpr int kFinLanes = 1024;
+
+__device__ __forceinline__ double fin_lane_sum(const double *pp, int nw, int v)
+{
+    double acc = 0.0;
+    for (int w = v; w < nw; w += 4 * kFinLanes) {
+        double x[4];
+#pragma unroll
+        for (int m = 0; m < 4; m++) x[m] = (w + m * kFinLanes < nw) ? pp[w + m * kFinLanes] : 0.0;
+#pragma unroll
+        for (int m = 0; m < 4; m++) acc += x[m];
+    }
+    return acc;
+}
+
+// Four virtual lanes l + 64 q (q = q0..q3) of one wavefront lane, summed as
+// fin_lane_sum does, then paired as the tree pairs them: (q0 + q1) + (q2 + q3).
+__device__ __forceinline__ double fin_lanes4(const double *pp, int nw, int l, int q0, int q1, int q2, int q3)
+{
+    const int qs[4] = {q0, q1, q2, q3};
+    double a[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int w0 = 0; w0 < nw; w0 += 4 * kFinLanes) {
+        double x[4][4];
+#pragma unroll
+        for (int i = 0; i < 4; i++)
+#pragma unroll
+            for (int m = 0; m < 4; m++) {
+                const int w = w0 + l + 64 * qs[i] + m * kFinLanes;
+                x[i][m] = w < nw ? pp[w] : 0.0;
+            }
+#pragma unroll
+        for (int i = 0; i < 4; i++)
+#pragma unroll
+            for (int m = 0; m < 4; m++) a[i] += x[i][m];
+    }
+    return (a[0] + a[1]) + (a[2] + a[3]);
+}
+
+// The whole sum by one wavefront (lanes l = 0..63 of the calling wave), in
+// the order above: virtual lane l + 64 q belongs to lane l, and the tree
+// levels h = 512 .. 64 pair q with q + h / 64, i.e. the value of lane l is
+// (((s0+s8) + (s4+s12)) + ((s2+s10) + (s6+s14))) + (((s1+s9) + (s5+s13)) +
+// ((s3+s11) + (s7+s15))), evaluated four leaves at a time to keep few
+// registers live; the last six levels pair lanes.  Result in lane 0.
+__device__ __forceinline__ double fin_wave_sum(const double *pp, int nw, int l)
+{
+    static_assert(kFinLanes == 1024, "the leaf order below is that of 16 virtual lanes per lane");
+    const double A = fin_lanes4(pp, nw, l, 0, 8, 4, 12);
+    const double B = fin_lanes4(pp, nw, l, 2, 10, 6, 14);
+    const double AB = A + B;
+    const double C = fin_lanes4(pp, nw, l, 1, 9, 5, 13);
+    const double D = fin_lanes4(pp, nw, l, 3, 11, 7, 15);
+    double v = AB + (C + D);
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        const double o = __shfl_down(v, off, 64);
+        if (l < off) v += o;
+    }
+    return v;
+}
+
+// alpha = rr / (p . A p) of CG, with a breakdown (p.Ap <= 0 or not finite)
+// poisoning rr; out (may be null) receives a copy of alpha.
+__device__ __forceinline__ void fin_alpha_update(double pap, int rid, double *rr, double *alpha, double *out)
+{
+    if (pap > 0.0 && pap < INFINITY) {
+        alpha[rid] = rr[rid] / pap;
+    } else {
+        alpha[rid] = 0.0;
+        rr[rid] = NAN;
+    }
+    if (out) out[rid] = alpha[rid];
+}
+
 }  // namespace wd

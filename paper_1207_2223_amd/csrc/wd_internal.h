@@ -70,6 +70,17 @@ struct DslashArgs {
     int pstride;
     int pw_off;
     unsigned lds;          // dynamic LDS bytes per work-group (unused by the kernel: caps occupancy)
+    // CG alpha finalized by the first fin_blocks work-groups (one per active
+    // RHS, before the stencil's tiles): alpha = rr / sum of fin_partial
+    // (fin_nw partials per RHS, stride fin_pstride), written to fin_alpha
+    // and fin_out (if not null); 0 = none
+    int fin_blocks;
+    int fin_nw;
+    int fin_pstride;
+    const double *fin_partial;
+    double *fin_rr;
+    double *fin_alpha;
+    double *fin_out;
 };
 
 // Launch shape of one stencil sweep: threads per work-group, RHS per lane
@@ -212,6 +223,14 @@ struct Sweep {
     double *partial = nullptr;
     int pstride = 0;
     int pw_off = 0;
+    // optional: the CG alpha of the partials fin_partial, finalized inside
+    // this sweep by extra work-groups (see DslashArgs)
+    const double *fin_partial = nullptr;
+    int fin_nw = 0;
+    int fin_pstride = 0;
+    double *fin_rr = nullptr;
+    double *fin_alpha = nullptr;
+    double *fin_out = nullptr;
 };
 wd_status run_sweep(wd_ctx *c, const Sweep &sw, const TuneCfg *cfg);
 wd_status upload_doubles(wd_ctx *c, const std::string &name, const double *v, int n, double **dev);
