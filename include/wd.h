@@ -144,8 +144,12 @@ wd_status wd_dslash(wd_ctx *c, double *out, const double *in, int out_parity, in
  * on nrhs right-hand sides at once (in, out: [nrhs][Vh][4][3], 1..64) with an
  * explicit launch shape of the stencil kernel: shape (HOST int32[5]) =
  * {threads per work-group (64, 128, 192 or 256), RHS per lane, lanes per
- * site, tile order (0..7, as the autotuner's), work-groups per CU cap (0 or
- * 2..8)}, or NULL for the default shape.  Every supported shape gives the
+ * site, tile order (0..7, as the autotuner's; 8, 9, 10: the LDS-staged
+ * kernel walking 4, 8 or 16 t-planes of a z-plane column per work-group, with
+ * 256 threads, 1 lane per site, 1 or 2 RHS per lane, no cap, FP16 or FP32
+ * spinors, where a plane of one parity holds a multiple of 64 sites up to
+ * 512, Lz is a multiple of 8 and Lt of the chunk), work-groups per CU cap (0
+ * or 2..8)}, or NULL for the default shape.  Every supported shape gives the
  * same bits; WD_ERR_ARG for a shape this lattice or precision does not
  * support (e.g. a slab tile order when the slab extent is not a multiple of
  * 8).  For checking launch shapes against a reference operator. */
@@ -371,8 +375,9 @@ wd_status wd_timing_report(wd_ctx *c, char *buf, size_t len);
 /* Autotune the launch shapes of the even-odd solver's four stencil sweeps for
  * nrhs right-hand sides in precision prec (wd_prec, | WD_LINKS_F16).  Every
  * supported shape (threads per work-group, RHS per lane, lanes per site, XCD
- * tile order) is timed with HIP events on synthetic fields, then the fastest
- * with a cap of 2..8 work-groups per compute unit; a shape whose
+ * tile order, and where it applies the LDS-staged kernel, see
+ * wd_dslash_shaped) is timed with HIP events on synthetic fields, then the
+ * fastest with a cap of 2..8 work-groups per compute unit; a shape whose
  * vectors or norm partials are not bitwise identical to the reference shape
  * is rejected.  The fastest shapes are kept in the context and used by
  * solves with wd_solver_params.tuned = 1.  report: HOST buffer of len bytes

@@ -120,6 +120,40 @@ double sweep_bytes(const wd_ctx *c, const Sweep &sw)
     return (double)c->Vh * (8.0 * (double)link_bytes(sw.lk) + sw.nact * per_rhs);
 }
 
+// Per-launch HIP events of the stencil timing (wd_timing_enable).
+static wd_status timing_begin(wd_ctx *c, hipEvent_t *e0, hipEvent_t *e1)
+{
+    if (c->ev_used == c->events.size()) {
+        hipEvent_t x0, x1;
+        WD_HIP(hipEventCreate(&x0));
+        WD_HIP(hipEventCreate(&x1));
+        c->events.push_back({x0, x1});
+    }
+    *e0 = c->events[c->ev_used].first;
+    *e1 = c->events[c->ev_used].second;
+    c->ev_used++;
+    WD_HIP(hipEventRecord(*e0, c->stream));
+    return WD_OK;
+}
+
+static void timing_end(wd_ctx *c, const Sweep &sw, hipEvent_t e1, bool lds, int nr, int rl)
+{
+    (void)hipEventRecord(e1, c->stream);
+    const double b = sweep_bytes(c, sw);
+    char name[96];
+    // the kernel's template instance as profilers print it
+    if (lds)
+        snprintf(name, sizeof(name), "dslash_lds_kernel<%d, %d, %d, %s, %d>", sw.sp, sw.lk, nr,
+                 sw.dag ? "true" : "false", sw.epi);
+    else
+        snprintf(name, sizeof(name), "dslash_kernel<%d, %d, %d, %d, %s, %d>", sw.sp, sw.lk, nr, rl,
+                 sw.dag ? "true" : "false", sw.epi);
+    if (c->ev_info.size() < c->ev_used) c->ev_info.resize(c->ev_used);
+    c->ev_info[c->ev_used - 1] = std::make_tuple(std::string(name), b, (double)c->Vh * sw.nact);
+    c->t_bytes += b;
+    c->t_launches++;
+}
+
 wd_status run_sweep(wd_ctx *c, const Sweep &sw, const TuneCfg *cfg)
 {
     if (sw.nact <= 0) return WD_OK;
@@ -164,6 +198,23 @@ wd_status run_sweep(wd_ctx *c, const Sweep &sw, const TuneCfg *cfg)
     a.tpp = 1;
     a.nzl = 1;
     a.nys = 1;
+    if (is_lds_order(t.remap)) {
+        if (!lds_order_ok(c, sw.sp, sw.lk, nr, t.remap) || rl != 1 || t.block != 256 || t.occ != 0)
+            return set_error(WD_ERR_ARG, "LDS-staged order %d does not apply here (sp %d lk %d nr %d rl %d block %d "
+                             "cap %d)", t.remap, sw.sp, sw.lk, nr, rl, t.block, t.occ);
+        a.tpp = lds_chunk(t.remap);
+        a.nzl = c->g.L[2] / 8;
+        a.lds = lds_order_bytes(c, sw.sp, nr);
+        const long long grid = (long long)c->g.L[2] * (c->g.L[3] / a.tpp) * a.G + a.fin_blocks;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (c->timing) WD_TRY(timing_begin(c, &e0, &e1));
+        hipError_t e = dslash_lds_launch(a, sw.sp, sw.lk, nr, sw.dag, sw.epi, (int)grid, a.lds, c->stream);
+        if (e != hipSuccess)
+            return set_error(WD_ERR_HIP, "LDS stencil launch (sp %d lk %d nr %d epi %d, %u bytes LDS): %s", sw.sp,
+                             sw.lk, nr, sw.epi, a.lds, hipGetErrorString(e));
+        if (c->timing) timing_end(c, sw, e1, true, nr, rl);
+        return WD_OK;
+    }
     if (t.remap >= kTileOrders || t.remap < 0) return set_error(WD_ERR_ARG, "tile order %d unknown", t.remap);
     if (t.remap >= 2) {
         if (!slab_order_ok(c->g, spb, t.remap))
@@ -176,34 +227,26 @@ wd_status run_sweep(wd_ctx *c, const Sweep &sw, const TuneCfg *cfg)
     const long long grid = (long long)ntiles * a.G + a.fin_blocks;
     if (grid > 0x7fffffffLL) return set_error(WD_ERR_ARG, "grid too large");
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (c->timing) {
-        if (c->ev_used == c->events.size()) {
-            hipEvent_t x0, x1;
-            WD_HIP(hipEventCreate(&x0));
-            WD_HIP(hipEventCreate(&x1));
-            c->events.push_back({x0, x1});
-        }
-        e0 = c->events[c->ev_used].first;
-        e1 = c->events[c->ev_used].second;
-        c->ev_used++;
-        WD_HIP(hipEventRecord(e0, c->stream));
-    }
+    if (c->timing) WD_TRY(timing_begin(c, &e0, &e1));
     hipError_t e = dslash_launch(a, sw.sp, sw.lk, nr, rl, sw.dag, sw.epi, t.block, (int)grid, c->stream);
     if (e != hipSuccess)
         return set_error(WD_ERR_HIP, "stencil launch (sp %d lk %d nr %d rl %d epi %d block %d): %s",
                          sw.sp, sw.lk, nr, rl, sw.epi, t.block, hipGetErrorString(e));
-    if (c->timing) {
-        WD_HIP(hipEventRecord(e1, c->stream));
-        const double b = sweep_bytes(c, sw);
-        char name[96];
-        snprintf(name, sizeof(name), "dslash_kernel<%d, %d, %d, %d, %s, %d>", sw.sp, sw.lk, nr,
-                 rl, sw.dag ? "true" : "false", sw.epi);
-        if (c->ev_info.size() < c->ev_used) c->ev_info.resize(c->ev_used);
-        c->ev_info[c->ev_used - 1] = std::make_tuple(std::string(name), b, (double)c->Vh * sw.nact);
-        c->t_bytes += b;
-        c->t_launches++;
-    }
+    if (c->timing) timing_end(c, sw, e1, false, nr, rl);
     return WD_OK;
+}
+
+unsigned lds_order_bytes(const wd_ctx *c, int sp, int nr)
+{
+    return 3u * (unsigned)nr * (unsigned)(c->g.Lxh * c->g.L[1]) * (unsigned)spinor_site_bytes(sp);
+}
+
+bool lds_order_ok(const wd_ctx *c, int sp, int lk, int nr, int remap)
+{
+    if (!is_lds_order(remap) || !dslash_lds_supported(sp, lk, nr)) return false;
+    const int S = c->g.Lxh * c->g.L[1];
+    return S % 64 == 0 && S <= 512 && c->g.L[2] % 8 == 0 && c->g.L[3] % lds_chunk(remap) == 0 &&
+           (long long)lds_order_bytes(c, sp, nr) <= (long long)c->lds_max;
 }
 
 bool slab_order_ok(const Geom &g, int spb, int remap)
@@ -303,8 +346,11 @@ wd_status wd_create(wd_ctx **out, const int32_t dims[4], int device, void *hip_s
     if (device < 0 || device >= ndev) return set_error(WD_ERR_ARG, "device %d not present", device);
     WD_HIP(hipSetDevice(device));
     WD_TRY(scratch_setup(device));
+    int lds_max = 0;
+    WD_HIP(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, device));
     wd_ctx *c = new wd_ctx();
     c->device = device;
+    c->lds_max = lds_max;
     c->stream = (hipStream_t)hip_stream;
     for (int mu = 0; mu < 4; mu++) {
         c->dims[mu] = dims[mu];
@@ -472,9 +518,11 @@ wd_status wd_dslash_shaped(wd_ctx *c, double *out, const double *in, int nrhs, i
         t.remap = shape[3];
         t.occ = shape[4];
     }
-    if (!dslash_shape_supported(sp, t.nr, t.rl) || t.block < 64 || t.block > 256 || (t.block & 63) ||
-        t.remap < 0 || t.remap >= kTileOrders || (t.occ != 0 && (t.occ < 2 || t.occ > kMaxOcc)) ||
-        (t.remap >= 2 && !slab_order_ok(c->g, t.block / t.rl, t.remap)))
+    const bool lds_ok = is_lds_order(t.remap) && lds_order_ok(c, sp, lk, t.nr, t.remap) && t.rl == 1 &&
+                        t.block == 256 && t.occ == 0;
+    if (!lds_ok && (!dslash_shape_supported(sp, t.nr, t.rl) || t.block < 64 || t.block > 256 || (t.block & 63) ||
+                    t.remap < 0 || t.remap >= kTileOrders || (t.occ != 0 && (t.occ < 2 || t.occ > kMaxOcc)) ||
+                    (t.remap >= 2 && !slab_order_ok(c->g, t.block / t.rl, t.remap))))
         return set_error(WD_ERR_ARG, "launch shape block %d nr %d rl %d order %d cap %d not supported here",
                          t.block, t.nr, t.rl, t.remap, t.occ);
     WD_HIP(hipSetDevice(c->device));

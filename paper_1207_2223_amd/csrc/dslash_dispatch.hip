@@ -12,6 +12,28 @@ hipError_t dslash_launch_f16_d1(const DslashArgs &a, int lk, int nr, int rl, int
 hipError_t dslash_launch_i16_d0(const DslashArgs &a, int lk, int nr, int rl, int epi, int block, int grid, hipStream_t s);
 hipError_t dslash_launch_i16_d1(const DslashArgs &a, int lk, int nr, int rl, int epi, int block, int grid, hipStream_t s);
 
+hipError_t dslash_lds_launch_f16_d0(const DslashArgs &a, int lk, int nr, int epi, int grid, unsigned lds_bytes, hipStream_t s);
+hipError_t dslash_lds_launch_f16_d1(const DslashArgs &a, int lk, int nr, int epi, int grid, unsigned lds_bytes, hipStream_t s);
+hipError_t dslash_lds_launch_f32_d0(const DslashArgs &a, int lk, int nr, int epi, int grid, unsigned lds_bytes, hipStream_t s);
+hipError_t dslash_lds_launch_f32_d1(const DslashArgs &a, int lk, int nr, int epi, int grid, unsigned lds_bytes, hipStream_t s);
+
+hipError_t dslash_lds_launch(const DslashArgs &a, int sp, int lk, int nr, int dag, int epi, int grid,
+                             unsigned lds_bytes, hipStream_t s)
+{
+    if (sp == SP_F16) return dag ? dslash_lds_launch_f16_d1(a, lk, nr, epi, grid, lds_bytes, s)
+                         : dslash_lds_launch_f16_d0(a, lk, nr, epi, grid, lds_bytes, s);
+    if (sp == SP_F32) return dag ? dslash_lds_launch_f32_d1(a, lk, nr, epi, grid, lds_bytes, s)
+                         : dslash_lds_launch_f32_d0(a, lk, nr, epi, grid, lds_bytes, s);
+    return hipErrorInvalidValue;
+}
+
+bool dslash_lds_supported(int sp, int lk, int nr)
+{
+    if (sp == SP_F16) return (lk == LK_F32_12 || lk == LK_F16_12) && (nr == 1 || nr == 2);
+    if (sp == SP_F32) return lk == LK_F32_12 && nr == 1;
+    return false;
+}
+
 hipError_t dslash_launch(const DslashArgs &a, int sp, int lk, int nr, int rl, int dag, int epi, int block,
                          int grid, hipStream_t s)
 {

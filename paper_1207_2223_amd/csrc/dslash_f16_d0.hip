@@ -51,4 +51,19 @@ hipError_t dslash_launch_f16_d0(const DslashArgs &a, int lk, int nr, int rl, int
     return hipErrorInvalidValue;
 }
 
+// The LDS-staged t-walking instances (RL = 1).
+hipError_t dslash_lds_launch_f16_d0(const DslashArgs &a, int lk, int nr, int epi, int grid, unsigned lds_bytes,
+                                  hipStream_t s)
+{
+    if (lk == LK_F32_12) {
+        WD_DSL_LDS_SHAPE(SP_F16, LK_F32_12, 1, false)
+        WD_DSL_LDS_SHAPE(SP_F16, LK_F32_12, 2, false)
+    }
+    if (lk == LK_F16_12) {
+        WD_DSL_LDS_SHAPE(SP_F16, LK_F16_12, 1, false)
+        WD_DSL_LDS_SHAPE(SP_F16, LK_F16_12, 2, false)
+    }
+    return hipErrorInvalidValue;
+}
+
 }  // namespace wd

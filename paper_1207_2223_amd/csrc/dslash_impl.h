@@ -101,10 +101,121 @@ __device__ __forceinline__ float load_nb_h2(const char *f, int cs, int j, h2_t v
     return ld_off<float, UNI>(f + (size_t)48 * cs, UNI ? pin_v((uint32_t)j * 4u) : (uint32_t)j * 4u);
 }
 
+// Where a sweep reads the neighbour spinors.  GlobalNb: from the input field
+// in global memory, for every direction (UNI: the field base is the same in
+// every lane).  Each load returns the values as stored and the per-site scale
+// of the format (1 without a norm); rid is the RHS id, r its index in the
+// lane's group, j the neighbour's checkerboard index.
+template <bool UNI>
+struct GlobalNb {
+    template <int MU, int DIR>
+    __device__ __forceinline__ float half(const DslashArgs &a, int rid, int, int j, _Float16 v[24]) const
+    {
+        return load_nb_half<UNI>(a.in + rid * a.in_rs, a.g.cs, j, v);
+    }
+    template <int MU, int DIR>
+    __device__ __forceinline__ float h2(const DslashArgs &a, int rid, int, int j, h2_t v[12]) const
+    {
+        return load_nb_h2<UNI>(a.in + rid * a.in_rs, a.g.cs, j, v);
+    }
+    template <int MU, int DIR>
+    __device__ __forceinline__ float i16(const DslashArgs &a, int rid, int, int j, int v[24]) const
+    {
+        return load_nb_i16<UNI>(a.in + rid * a.in_rs, a.g.cs, j, v);
+    }
+    template <int MU, int DIR, int SP, typename real>
+    __device__ __forceinline__ real gen(const DslashArgs &a, int rid, int, int j, real v[24]) const
+    {
+        return load_nb<SP>(a.in + rid * a.in_rs, a.g.cs, j, v);
+    }
+};
+
+// LdsNb: the input planes (z, t-1), (z, t), (z, t+1) of the sites a work-group
+// walks are staged in LDS (slot[0..2]; base[] their first checkerboard
+// index), so the x, y and t neighbours come from LDS; the z neighbours from
+// global memory.  Within a slot, RHS r occupies rstride bytes laid out like
+// the global structure of arrays with chunk stride S (the sites of a plane):
+// 16-byte chunk q of site jl at (q * S + jl) * 16, then the per-site norms.
+typedef __attribute__((address_space(3))) char lds_char;
+
+template <int SP>
+struct LdsNb {
+    const lds_char *slot[3];
+    int base[3];
+    int S;
+    int rstride;
+
+    template <int MU, int DIR>
+    __device__ __forceinline__ const lds_char *at(int r, int j, int *jl) const
+    {
+        constexpr int k = (MU == 3) ? DIR + 1 : 1;
+        *jl = j - base[k];
+        return slot[k] + r * rstride;
+    }
+    template <int MU, int DIR>
+    __device__ __forceinline__ float half(const DslashArgs &a, int rid, int r, int j, _Float16 v[24]) const
+    {
+        if constexpr (MU == 2) {
+            return GlobalNb<true>{}.template half<MU, DIR>(a, rid, r, j, v);
+        } else {
+            int jl;
+            const lds_char *p = at<MU, DIR>(r, j, &jl);
+#pragma unroll
+            for (int q = 0; q < 3; q++) {
+                const half8_t w = *(const __attribute__((address_space(3))) half8_t *)(p + (q * S + jl) * 16);
+#pragma unroll
+                for (int e = 0; e < 8; e++) v[8 * q + e] = w[e];
+            }
+            return *(const __attribute__((address_space(3))) float *)(p + 48 * S + jl * 4);
+        }
+    }
+    template <int MU, int DIR>
+    __device__ __forceinline__ float h2(const DslashArgs &a, int rid, int r, int j, h2_t v[12]) const
+    {
+        if constexpr (MU == 2) {
+            return GlobalNb<true>{}.template h2<MU, DIR>(a, rid, r, j, v);
+        } else {
+            int jl;
+            const lds_char *p = at<MU, DIR>(r, j, &jl);
+#pragma unroll
+            for (int q = 0; q < 3; q++) {
+                const half8_t w = *(const __attribute__((address_space(3))) half8_t *)(p + (q * S + jl) * 16);
+#pragma unroll
+                for (int e = 0; e < 4; e++) v[4 * q + e] = h2_t{w[2 * e], w[2 * e + 1]};
+            }
+            return *(const __attribute__((address_space(3))) float *)(p + 48 * S + jl * 4);
+        }
+    }
+    template <int MU, int DIR>
+    __device__ __forceinline__ float i16(const DslashArgs &a, int rid, int r, int j, int v[24]) const
+    {
+        return GlobalNb<true>{}.template i16<MU, DIR>(a, rid, r, j, v);  // (no LDS variant for int16)
+    }
+    template <int MU, int DIR, int SP_, typename real>
+    __device__ __forceinline__ real gen(const DslashArgs &a, int rid, int r, int j, real v[24]) const
+    {
+        if constexpr (MU == 2 || SP_ != SP_F32) {
+            return GlobalNb<true>{}.template gen<MU, DIR, SP_>(a, rid, r, j, v);
+        } else {
+            int jl;
+            const lds_char *p = at<MU, DIR>(r, j, &jl);
+#pragma unroll
+            for (int q = 0; q < 6; q++) {
+                const flt4_t w = *(const __attribute__((address_space(3))) flt4_t *)(p + (q * S + jl) * 16);
+                v[4 * q] = w.x;
+                v[4 * q + 1] = w.y;
+                v[4 * q + 2] = w.z;
+                v[4 * q + 3] = w.w;
+            }
+            return (real)1;
+        }
+    }
+};
+
 // FP16 spinors with FP16 links: dot2 matvec on FP16 inputs, FP32 results.
-template <int MU, int NR, bool DAG, bool UNI>
-__device__ __forceinline__ void hop_dir_f16dot(const DslashArgs &a, int i, const int c[4], const int rid[NR],
-                                               float acc[NR][24])
+template <int MU, int NR, bool DAG, class NB>
+__device__ __forceinline__ void hop_dir_f16dot(const DslashArgs &a, const NB &nb, int i, const int c[4],
+                                               const int rid[NR], float acc[NR][24])
 {
     constexpr int SF = DAG ? +1 : -1;
     constexpr int SB = -SF;
@@ -117,7 +228,7 @@ __device__ __forceinline__ void hop_dir_f16dot(const DslashArgs &a, int i, const
         for (int r = 0; r < NR; r++) {
             h2_t v[12], h[6];
             float w[12];
-            const float sc = load_nb_h2<UNI>(a.in + rid[r] * a.in_rs, cs, j, v);
+            const float sc = nb.template h2<MU, +1>(a, rid[r], r, j, v);
             project_h2<MU, SF>(v, h);
             su3_mul_half_dot2(A, B, h, w);
             accumulate_scaled<MU, SF>(acc[r], w, sc);
@@ -130,7 +241,7 @@ __device__ __forceinline__ void hop_dir_f16dot(const DslashArgs &a, int i, const
         for (int r = 0; r < NR; r++) {
             h2_t v[12], h[6];
             float w[12];
-            const float sc = load_nb_h2<UNI>(a.in + rid[r] * a.in_rs, cs, j, v);
+            const float sc = nb.template h2<MU, -1>(a, rid[r], r, j, v);
             project_h2<MU, SB>(v, h);
             su3_mul_half_dot2(A, B, h, w);
             accumulate_scaled<MU, SB>(acc[r], w, sc);
@@ -138,13 +249,14 @@ __device__ __forceinline__ void hop_dir_f16dot(const DslashArgs &a, int i, const
     }
 }
 
-// UNI: the RHS ids (and so the field bases) are the same in every lane.
-template <int MU, int SP, int LK, int NR, bool DAG, bool UNI, typename real>
-__device__ __forceinline__ void hop_dir(const DslashArgs &a, int i, const int c[4],
+// The two terms of direction MU for the NR RHS of a lane; nb supplies the
+// neighbour spinors.
+template <int MU, int SP, int LK, int NR, bool DAG, class NB, typename real>
+__device__ __forceinline__ void hop_dir(const DslashArgs &a, const NB &nb, int i, const int c[4],
                                         const int rid[NR], real acc[NR][24])
 {
     if constexpr (SP == SP_F16 && LK == LK_F16_12) {
-        hop_dir_f16dot<MU, NR, DAG, UNI>(a, i, c, rid, acc);
+        hop_dir_f16dot<MU, NR, DAG>(a, nb, i, c, rid, acc);
         return;
     }
     constexpr int SF = DAG ? +1 : -1;  // forward: (1 - g) for H, (1 + g) for H^dag
@@ -159,15 +271,15 @@ __device__ __forceinline__ void hop_dir(const DslashArgs &a, int i, const int c[
             real h[12], w[12], sc;
             if constexpr (SP == SP_F16) {
                 _Float16 v[24];
-                sc = load_nb_half<UNI>(a.in + rid[r] * a.in_rs, cs, j, v);
+                sc = nb.template half<MU, +1>(a, rid[r], r, j, v);
                 project_mix<MU, SF>(v, h);
             } else if constexpr (SP == SP_I16) {
                 int v[24];
-                sc = load_nb_i16<UNI>(a.in + rid[r] * a.in_rs, cs, j, v);
+                sc = nb.template i16<MU, +1>(a, rid[r], r, j, v);
                 project_int<MU, SF>(v, h);
             } else {
                 real v[24];
-                sc = load_nb<SP>(a.in + rid[r] * a.in_rs, cs, j, v);
+                sc = nb.template gen<MU, +1, SP>(a, rid[r], r, j, v);
                 project<MU, SF>(v, h);
             }
             su3_mul_half<false>(u, h, w);
@@ -185,15 +297,15 @@ __device__ __forceinline__ void hop_dir(const DslashArgs &a, int i, const int c[
             real h[12], w[12], sc;
             if constexpr (SP == SP_F16) {
                 _Float16 v[24];
-                sc = load_nb_half<UNI>(a.in + rid[r] * a.in_rs, cs, j, v);
+                sc = nb.template half<MU, -1>(a, rid[r], r, j, v);
                 project_mix<MU, SB>(v, h);
             } else if constexpr (SP == SP_I16) {
                 int v[24];
-                sc = load_nb_i16<UNI>(a.in + rid[r] * a.in_rs, cs, j, v);
+                sc = nb.template i16<MU, -1>(a, rid[r], r, j, v);
                 project_int<MU, SB>(v, h);
             } else {
                 real v[24];
-                sc = load_nb<SP>(a.in + rid[r] * a.in_rs, cs, j, v);
+                sc = nb.template gen<MU, -1, SP>(a, rid[r], r, j, v);
                 project<MU, SB>(v, h);
             }
             su3_mul_half<true>(u, h, w);
@@ -213,6 +325,54 @@ __device__ __forceinline__ double group16_sum(double v)
 #pragma unroll
     for (int off = 8 * RL; off >= RL; off >>= 1) v += __shfl_xor(v, off, 64);
     return v;
+}
+
+// The epilogue of output site i (live: a site of this lattice) for the NR
+// RHS of a lane (rv: the slot holds an active RHS): plain store, xpay with
+// |out|^2, or the CG residual update with |r|^2; the norm partials of 16
+// consecutive sites are summed with the same pairing tree for every shape.
+template <int SP, int NR, int RL, int EPI, typename real>
+__device__ __forceinline__ void dslash_epilogue(const DslashArgs &a, int i, bool live, const int (&rid)[NR],
+                                                const bool (&rv)[NR], real (&acc)[NR][24])
+{
+    const int Vh = a.g.Vh, cs = a.g.cs;
+#pragma unroll
+    for (int r = 0; r < NR; r++) {
+        double nrm = 0.0;
+        if (live && rv[r]) {
+            if (EPI == EPI_PLAIN) {
+                SpinorIO<SP>::template store<true>(a.out + rid[r] * a.out_rs, cs, i, acc[r]);
+            } else if (EPI == EPI_XPAY) {
+                const real cf = (real)a.coef[rid[r]];
+                real xv[24];
+                SpinorIO<SP>::template load<true>(a.x + rid[r] * a.x_rs, cs, i, xv);
+#pragma unroll
+                for (int k = 0; k < 24; k++) {
+                    xv[k] = fmaT(cf, acc[r][k], xv[k]);
+                    nrm = fmaT((double)xv[k], (double)xv[k], nrm);
+                }
+                SpinorIO<SP>::template store<true>(a.out + rid[r] * a.out_rs, cs, i, xv);
+            } else {
+                const real cf = (real)a.coef[rid[r]];
+                const real al = (real)a.alpha[rid[r]];
+                real ap[24], rv_[24];
+                SpinorIO<SP>::template load<true>(a.x + rid[r] * a.x_rs, cs, i, ap);
+                SpinorIO<SP>::template load<true>(a.r + rid[r] * a.r_rs, cs, i, rv_);
+#pragma unroll
+                for (int k = 0; k < 24; k++) {
+                    ap[k] = fmaT(cf, acc[r][k], ap[k]);
+                    rv_[k] = fmaT(-al, ap[k], rv_[k]);
+                    nrm = fmaT((double)rv_[k], (double)rv_[k], nrm);
+                }
+                SpinorIO<SP>::template store<true>(a.r + rid[r] * a.r_rs, cs, i, rv_);
+            }
+        }
+        if (EPI != EPI_PLAIN && a.partial != nullptr) {
+            const double s = group16_sum<RL>(nrm);
+            if ((i & 15) == 0 && i < Vh && rv[r] && ((int)threadIdx.x % (16 * RL)) < RL)
+                a.partial[(size_t)rid[r] * a.pstride + a.pw_off + (i >> 4)] = s;
+        }
+    }
 }
 
 template <int SP, int LK, int NR, int RL, bool DAG, int EPI>
@@ -290,8 +450,7 @@ __global__ void __launch_bounds__(256) dslash_kernel(DslashArgs a)
     const int spb = blockDim.x / RL;
     const int i = tile * spb + (int)threadIdx.x / RL;
     const int lr = (int)threadIdx.x % RL;
-    const int Vh = a.g.Vh, cs = a.g.cs;
-    const bool live = i < Vh;
+    const bool live = i < a.g.Vh;
 
     int rid[NR];
     bool rv[NR];
@@ -317,48 +476,186 @@ __global__ void __launch_bounds__(256) dslash_kernel(DslashArgs a)
     if (live) {
         int c[4];
         site_coords(a.g, i, a.P, c);
-        hop_dir<0, SP, LK, NR, DAG, RL == 1>(a, i, c, rid, acc);
-        hop_dir<1, SP, LK, NR, DAG, RL == 1>(a, i, c, rid, acc);
-        hop_dir<2, SP, LK, NR, DAG, RL == 1>(a, i, c, rid, acc);
-        hop_dir<3, SP, LK, NR, DAG, RL == 1>(a, i, c, rid, acc);
+        const GlobalNb<RL == 1> nb;
+        hop_dir<0, SP, LK, NR, DAG>(a, nb, i, c, rid, acc);
+        hop_dir<1, SP, LK, NR, DAG>(a, nb, i, c, rid, acc);
+        hop_dir<2, SP, LK, NR, DAG>(a, nb, i, c, rid, acc);
+        hop_dir<3, SP, LK, NR, DAG>(a, nb, i, c, rid, acc);
     }
 
+    dslash_epilogue<SP, NR, RL, EPI>(a, i, live, rid, rv, acc);
+}
+
+// ---------------------------------------------------------------------------
+// The LDS-staged variant: a work-group walks t along one z-plane column
+// ---------------------------------------------------------------------------
+// Work-group (z, t-chunk, RHS group) computes the output sites of the planes
+// (z, t) for t in [t0, t0 + Tc), 256 threads over the S = Lx/2 * Ly sites of
+// a plane, one lane per site and NR RHS per lane.  The input planes (z, t-1),
+// (z, t), (z, t+1) of its RHS group are held in a ring of three LDS slots:
+// the x and y neighbours of a site lie in plane (z, t), the t neighbours in
+// (z, t+-1), so six of the eight neighbour spinors come from LDS and each
+// input site of the column is read from HBM once per work-group (plus the
+// two planes before and after the chunk); the z neighbours are read from
+// global memory, where the work-groups of the adjacent z-planes (same XCD,
+// same t and RHS group) read them too.  While a plane is computed, the next
+// one is loaded into registers, and stored into the slot freed by the plane
+// just finished.  The arithmetic, the epilogue and its norm partials are
+// those of dslash_kernel, so the results are the same bits.
+//
+// XCD mapping: XCD x = block mod 8 takes the z-planes [x nzl, (x+1) nzl) (Lz
+// divisible by 8); its j-th block is z-plane j mod nzl (fastest), then the t
+// chunk, then the RHS group.
+
+constexpr int kLdsThreads = 256;
+constexpr int kLdsMaxPlane = 512;
+
+// The chunk count of a spinor format's 16-byte chunks (the norm aside).
+template <int SP>
+__host__ __device__ constexpr int spinor_chunks() { return SP == SP_F32 ? 6 : 3; }
+
+template <int SP>
+__host__ __device__ constexpr int lds_site_bytes() { return SP == SP_F32 ? 96 : 52; }
+
+template <int SP, int NR, int SPT>
+struct PlaneRegs {
+    u32x4_t ch[NR][SPT][spinor_chunks<SP>()];
+    float nrm[NR][SPT];
+};
+
+// Global -> registers: plane (z, t) of the input field for the lane's sites
+// tid + 256 k (k < SPT) and the NR RHS of the group.
+template <int SP, int NR, int SPT>
+__device__ __forceinline__ void plane_fetch(const DslashArgs &a, const int rid[NR], int pbase, int S,
+                                            PlaneRegs<SP, NR, SPT> &R)
+{
+    const int cs = a.g.cs;
 #pragma unroll
     for (int r = 0; r < NR; r++) {
-        double nrm = 0.0;
-        if (live && rv[r]) {
-            if (EPI == EPI_PLAIN) {
-                SpinorIO<SP>::template store<true>(a.out + rid[r] * a.out_rs, cs, i, acc[r]);
-            } else if (EPI == EPI_XPAY) {
-                const real cf = (real)a.coef[rid[r]];
-                real xv[24];
-                SpinorIO<SP>::template load<true>(a.x + rid[r] * a.x_rs, cs, i, xv);
+        const char *f = a.in + rid[r] * a.in_rs;
 #pragma unroll
-                for (int k = 0; k < 24; k++) {
-                    xv[k] = fmaT(cf, acc[r][k], xv[k]);
-                    nrm = fmaT((double)xv[k], (double)xv[k], nrm);
-                }
-                SpinorIO<SP>::template store<true>(a.out + rid[r] * a.out_rs, cs, i, xv);
-            } else {
-                const real cf = (real)a.coef[rid[r]];
-                const real al = (real)a.alpha[rid[r]];
-                real ap[24], rv_[24];
-                SpinorIO<SP>::template load<true>(a.x + rid[r] * a.x_rs, cs, i, ap);
-                SpinorIO<SP>::template load<true>(a.r + rid[r] * a.r_rs, cs, i, rv_);
+        for (int k = 0; k < SPT; k++) {
+            const int jl = (int)threadIdx.x + kLdsThreads * k;
+            if (jl < S) {
+                const int j = pbase + jl;
 #pragma unroll
-                for (int k = 0; k < 24; k++) {
-                    ap[k] = fmaT(cf, acc[r][k], ap[k]);
-                    rv_[k] = fmaT(-al, ap[k], rv_[k]);
-                    nrm = fmaT((double)rv_[k], (double)rv_[k], nrm);
-                }
-                SpinorIO<SP>::template store<true>(a.r + rid[r] * a.r_rs, cs, i, rv_);
+                for (int q = 0; q < spinor_chunks<SP>(); q++)
+                    R.ch[r][k][q] = *reinterpret_cast<const u32x4_t *>(f + ((size_t)q * cs + j) * 16);
+                if constexpr (has_norm(SP))
+                    R.nrm[r][k] = reinterpret_cast<const float *>(f + (size_t)48 * cs)[j];
             }
         }
-        if (EPI != EPI_PLAIN && a.partial != nullptr) {
-            const double s = group16_sum<RL>(nrm);
-            if ((i & 15) == 0 && i < Vh && rv[r] && ((int)threadIdx.x % (16 * RL)) < RL)
-                a.partial[(size_t)rid[r] * a.pstride + a.pw_off + (i >> 4)] = s;
+    }
+}
+
+// Registers -> LDS slot (layout of LdsNb).
+template <int SP, int NR, int SPT>
+__device__ __forceinline__ void plane_store(lds_char *slot, int S, const PlaneRegs<SP, NR, SPT> &R)
+{
+    const int rstride = S * lds_site_bytes<SP>();
+#pragma unroll
+    for (int r = 0; r < NR; r++) {
+        lds_char *p = slot + r * rstride;
+#pragma unroll
+        for (int k = 0; k < SPT; k++) {
+            const int jl = (int)threadIdx.x + kLdsThreads * k;
+            if (jl < S) {
+#pragma unroll
+                for (int q = 0; q < spinor_chunks<SP>(); q++)
+                    *(__attribute__((address_space(3))) u32x4_t *)(p + (q * S + jl) * 16) = R.ch[r][k][q];
+                if constexpr (has_norm(SP))
+                    *(__attribute__((address_space(3))) float *)(p + 48 * S + jl * 4) = R.nrm[r][k];
+            }
         }
+    }
+}
+
+template <int SP, int LK, int NR, bool DAG, int EPI>
+__global__ void __launch_bounds__(kLdsThreads) dslash_lds_kernel(DslashArgs a)
+{
+    typedef typename SpinorIO<SP>::real real;
+    static_assert(SP == SP_F16 || SP == SP_F32, "LDS staging of FP16 and FP32 spinors");
+    constexpr int SPT = kLdsMaxPlane / kLdsThreads;  // sites per thread and plane, at most
+    extern __shared__ __attribute__((aligned(16))) char lds_dyn[];
+    if ((int)blockIdx.x < a.fin_blocks) {
+        if (threadIdx.x < 64) {
+            const int rid = a.active[blockIdx.x];
+            const double s = fin_wave_sum(a.fin_partial + (size_t)rid * a.fin_pstride, a.fin_nw, (int)threadIdx.x);
+            if (threadIdx.x == 0) fin_alpha_update(s, rid, a.fin_rr, a.fin_alpha, a.fin_out);
+        }
+        return;
+    }
+    const int bid = (int)blockIdx.x - a.fin_blocks;
+    const int Lz = a.g.L[2], Lt = a.g.L[3];
+    const int S = a.g.Lxh * a.g.L[1];
+    const int Tc = a.tpp;  // t planes per work-group
+    const int nzl = a.nzl, ntc = Lt / Tc;
+    const int x = bid & 7, jb = bid >> 3;
+    const int zl = jb % nzl, rest = jb / nzl;
+    const int tc = rest % ntc, grp = rest / ntc;
+    const int z = x * nzl + zl, t0 = tc * Tc;
+
+    int rid[NR];
+    bool rv[NR];
+#pragma unroll
+    for (int r = 0; r < NR; r++) {
+        const int slot = grp * NR + r;
+        rv[r] = slot < a.nact;
+        rid[r] = __builtin_amdgcn_readfirstlane(rv[r] ? a.active[slot] : 0);
+    }
+    auto pbase = [&](int t) { return S * (z + Lz * (((t % Lt) + Lt) % Lt)); };
+    lds_char *lds = (lds_char *)lds_dyn;
+    const int slot_bytes = NR * S * lds_site_bytes<SP>();
+    // prologue: planes t0 - 1, t0, t0 + 1 in slots 0, 1, 2
+    {
+        PlaneRegs<SP, NR, SPT> R;
+#pragma unroll 1
+        for (int q = 0; q < 3; q++) {
+            plane_fetch<SP, NR, SPT>(a, rid, pbase(t0 - 1 + q), S, R);
+            plane_store<SP, NR, SPT>(lds + q * slot_bytes, S, R);
+        }
+    }
+    __syncthreads();
+#pragma unroll 1
+    for (int tr = 0; tr < Tc; tr++) {
+        const int t = t0 + tr;
+        PlaneRegs<SP, NR, SPT> nxt;
+        const bool more = tr + 1 < Tc;
+        if (more) plane_fetch<SP, NR, SPT>(a, rid, pbase(t + 2), S, nxt);
+        LdsNb<SP> nb;
+        nb.S = S;
+        nb.rstride = S * lds_site_bytes<SP>();
+#pragma unroll
+        for (int q = 0; q < 3; q++) {
+            nb.slot[q] = lds + ((tr + q) % 3) * slot_bytes;
+            nb.base[q] = pbase(t - 1 + q);
+        }
+#pragma unroll
+        for (int k = 0; k < SPT; k++) {
+            const int il = (int)threadIdx.x + kLdsThreads * k;
+            if (k * kLdsThreads < S) {  // (whole waves: S is a multiple of 64)
+                const bool live = il < S;
+                // (an idle lane's index is past the lattice: it stores and sums nothing)
+                const int i = live ? pbase(t) + il : a.g.Vh;
+                real acc[NR][24];
+#pragma unroll
+                for (int r = 0; r < NR; r++)
+#pragma unroll
+                    for (int e = 0; e < 24; e++) acc[r][e] = 0;
+                if (live) {
+                    int c[4];
+                    site_coords(a.g, i, a.P, c);
+                    hop_dir<0, SP, LK, NR, DAG>(a, nb, i, c, rid, acc);
+                    hop_dir<1, SP, LK, NR, DAG>(a, nb, i, c, rid, acc);
+                    hop_dir<2, SP, LK, NR, DAG>(a, nb, i, c, rid, acc);
+                    hop_dir<3, SP, LK, NR, DAG>(a, nb, i, c, rid, acc);
+                }
+                dslash_epilogue<SP, NR, 1, EPI>(a, i, live, rid, rv, acc);
+            }
+        }
+        __syncthreads();  // every lane is done with the slot of plane t - 1
+        if (more) plane_store<SP, NR, SPT>(lds + (tr % 3) * slot_bytes, S, nxt);
+        __syncthreads();
     }
 }
 
@@ -384,6 +681,41 @@ __global__ void __launch_bounds__(256) dslash_kernel(DslashArgs a)
 #define WD_DSL_SHAPE(SP_, LK_, NR_, RL_, DAG_)                                                   \
     if (nr == NR_ && rl == RL_) {                                                                 \
         WD_DSL_EPI(SP_, LK_, NR_, RL_, DAG_)                                                      \
+    }
+
+// (the dynamic LDS limit of each LDS instance is raised to the device's
+// maximum once)
+#define WD_DSL_LDS_ONE(SP_, LK_, NR_, DAG_, EPI_)                                                   \
+    {                                                                                             \
+        static bool lim_ = false;                                                                 \
+        if (!lim_) {                                                                              \
+            int dev_ = 0, mx_ = 0;                                                                \
+            hipError_t e_ = hipGetDevice(&dev_);                                                  \
+            if (e_ == hipSuccess)                                                                 \
+                e_ = hipDeviceGetAttribute(&mx_, hipDeviceAttributeMaxSharedMemoryPerBlock, dev_); \
+            if (e_ == hipSuccess)                                                                 \
+                e_ = hipFuncSetAttribute(                                                         \
+                    reinterpret_cast<const void *>(&dslash_lds_kernel<SP_, LK_, NR_, DAG_, EPI_>),  \
+                    hipFuncAttributeMaxDynamicSharedMemorySize, mx_);                             \
+            if (e_ != hipSuccess) return e_;                                                      \
+            lim_ = true;                                                                          \
+        }                                                                                         \
+        hipLaunchKernelGGL((dslash_lds_kernel<SP_, LK_, NR_, DAG_, EPI_>), dim3(grid),             \
+                           dim3(kLdsThreads), lds_bytes, s, a);                                   \
+        return hipGetLastError();                                                                 \
+    }
+
+#define WD_DSL_LDS_EPI(SP_, LK_, NR_, DAG_)                                                        \
+    switch (epi) {                                                                                \
+    case EPI_PLAIN: WD_DSL_LDS_ONE(SP_, LK_, NR_, DAG_, EPI_PLAIN)                                 \
+    case EPI_XPAY: WD_DSL_LDS_ONE(SP_, LK_, NR_, DAG_, EPI_XPAY)                                   \
+    case EPI_CGUPD: WD_DSL_LDS_ONE(SP_, LK_, NR_, DAG_, EPI_CGUPD)                                 \
+    default: return hipErrorInvalidValue;                                                         \
+    }
+
+#define WD_DSL_LDS_SHAPE(SP_, LK_, NR_, DAG_)                                                      \
+    if (nr == NR_) {                                                                              \
+        WD_DSL_LDS_EPI(SP_, LK_, NR_, DAG_)                                                       \
     }
 
 }  // namespace wd

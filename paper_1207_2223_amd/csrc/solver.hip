@@ -101,6 +101,7 @@ struct BatchSolver {
     std::vector<int> state, iters, iters64, rus, status, last_ru, stall, active, active64;
     std::vector<double> bbh, maxrr, best, tres, kap;
     bool trace = false;
+    bool fold = true;  // alpha finalized inside sweep 3 (else by its own kernel)
 
     std::string nm(const char *s) const { return pre + s; }
     std::string ring_name(int j) const { return pre + (mixed ? "ps@" : "p@") + std::to_string(j); }
@@ -136,6 +137,10 @@ struct BatchSolver {
         active64.clear();
         const char *te = getenv("WD_SOLVER_TRACE");
         trace = te && te[0] == '1';
+        // WD_SEPARATE_FINALIZE=1: alpha by the separate finalize kernel (the
+        // same summation order; for checking that both give the same bits)
+        const char *sf = getenv("WD_SEPARATE_FINALIZE");
+        fold = !(sf && sf[0] == '1');
         return WD_OK;
     }
 
@@ -385,8 +390,13 @@ struct BatchSolver {
             // sweep 4 (one dispatch fewer than a separate finalize)
             sw.partial = nullptr;
             sw.P = 1; sw.dag = 1; sw.epi = EPI_PLAIN; sw.in = L.T2; sw.out = L.TO;
-            sw.fin_partial = partial; sw.fin_nw = nwD; sw.fin_pstride = pstride;
-            sw.fin_rr = rr; sw.fin_alpha = alpha; sw.fin_out = ahist + (size_t)j * cap;
+            if (fold) {
+                sw.fin_partial = partial; sw.fin_nw = nwD; sw.fin_pstride = pstride;
+                sw.fin_rr = rr; sw.fin_alpha = alpha; sw.fin_out = ahist + (size_t)j * cap;
+            } else {
+                HIPCHK(blas_finalize(partial, pstride, nwD, ids, n, FIN_ALPHA, rr, alpha, beta,
+                                     ahist + (size_t)j * cap, s));
+            }
             WD_TRY(run_sweep(c, sw, nullptr));
             sw.fin_partial = nullptr;
             sw.P = 0; sw.epi = EPI_CGUPD; sw.in = L.TO; sw.x = L.T2; sw.r = L.R;
@@ -558,7 +568,7 @@ struct BatchSolver {
                                      (unsigned long long)c->use_tuned, (unsigned long long)c->tune_gen,
                                      (unsigned long long)sp, (unsigned long long)lk, (unsigned long long)xp,
                                      (unsigned long long)c->lk64, (unsigned long long)p.eo,
-                                     (unsigned long long)pstride})
+                                     (unsigned long long)pstride, (unsigned long long)fold})
             add(v);
         for (const void *q : {(const void *)c->links64, (const void *)c->links32, (const void *)c->links16,
                               (const void *)c->links32r, (const void *)coef1, (const void *)coef2,

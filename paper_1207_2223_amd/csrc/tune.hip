@@ -265,6 +265,18 @@ extern "C" wd_status wd_tune(wd_ctx *c, int nrhs, int prec, char *report, size_t
                     q.remap = rm;
                     cands.push_back(q);
                 }
+    // the LDS-staged t-walking kernel: 256 threads, one lane per site, 1 or 2
+    // RHS per lane, 4, 8 or 16 t-planes per work-group
+    for (int nr = 1; nr <= 2; nr++)
+        for (int rm = kLdsOrder0; rm < kLdsOrder0 + kLdsOrders; rm++) {
+            if (!lds_order_ok(c, sp, lk, nr, rm) || (nr > 2 * nrhs && nr != 1)) continue;
+            TuneCfg q;
+            q.block = 256;
+            q.nr = nr;
+            q.rl = 1;
+            q.remap = rm;
+            cands.push_back(q);
+        }
 
     // (the solver's D_oe^dag sweep also finalizes alpha in extra work-groups:
     // timed here with them, on the partials and scalars of tn_fin)
@@ -278,6 +290,9 @@ extern "C" wd_status wd_tune(wd_ctx *c, int nrhs, int prec, char *report, size_t
     std::string rep;
     wd_status st = WD_OK;
     const char *cache = getenv("WD_TUNE_CACHE");
+    // WD_TUNE_VERBOSE=1: every timed candidate on stderr
+    const char *vb = getenv("WD_TUNE_VERBOSE");
+    const bool verbose = vb && vb[0] == '1';
     for (const Kind &k : kinds) {
         Sweep sw;
         sw.sp = sp; sw.lk = lk; sw.dag = k.dag; sw.epi = k.epi; sw.P = k.P;
@@ -307,7 +322,7 @@ extern "C" wd_status wd_tune(wd_ctx *c, int nrhs, int prec, char *report, size_t
             bestc = list[0];
             const size_t nfirst = list.size();
             for (size_t q = 0;; q++) {
-                if (occ_pass && q == nfirst && best < 1e30)
+                if (occ_pass && q == nfirst && best < 1e30 && !is_lds_order(bestc.remap))
                     for (int oc = 2; oc <= kMaxOcc; oc++) {
                         TuneCfg v = bestc;
                         v.occ = oc;
@@ -358,6 +373,9 @@ extern "C" wd_status wd_tune(wd_ctx *c, int nrhs, int prec, char *report, size_t
                     tbest = std::min(tbest, (double)ms / 4);
                 }
                 us[q] = tbest * 1e3;
+                if (verbose)
+                    fprintf(stderr, "[wd tune] %s sp %d lk %d nrhs %d: block %d nr %d rl %d order %d cap %d: %.2f us\n",
+                            k.name, sp, lk, nrhs, cf.block, cf.nr, cf.rl, cf.remap, cf.occ, us[q]);
                 if (tbest < best) {
                     best = tbest;
                     bestc = cf;
@@ -386,7 +404,9 @@ extern "C" wd_status wd_tune(wd_ctx *c, int nrhs, int prec, char *report, size_t
             double us_cached = 0;
             if (cache_lookup(cache, cache_key(c, nrhs, sp, lk, k.dag, k.epi), &cc, &us_cached) &&
                 dslash_shape_supported(sp, cc.nr, cc.rl) && (cc.occ == 0 || (cc.occ >= 2 && cc.occ <= kMaxOcc)) &&
-                (cc.remap < 2 || slab_order_ok(c->g, cc.block / cc.rl, cc.remap))) {
+                (is_lds_order(cc.remap)
+                     ? (lds_order_ok(c, sp, lk, cc.nr, cc.remap) && cc.rl == 1 && cc.block == 256 && cc.occ == 0)
+                     : (cc.remap < 2 || slab_order_ok(c->g, cc.block / cc.rl, cc.remap)))) {
                 std::vector<TuneCfg> vl = {cands[0], cc};
                 std::vector<char> ok;
                 std::vector<double> us;

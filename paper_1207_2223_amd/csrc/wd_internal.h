@@ -104,6 +104,12 @@ inline unsigned occ_lds_bytes(int occ) { return occ > 0 ? kLdsPerCU / (unsigned)
 hipError_t dslash_launch(const DslashArgs &a, int sp, int lk, int nr, int rl, int dag, int epi,
                          int block, int grid, hipStream_t s);
 bool dslash_shape_supported(int sp, int nr, int rl);
+// The LDS-staged t-walking stencil (tile orders kLdsOrder0 and up: work-groups
+// of 256 threads walking kLdsChunk[order - kLdsOrder0] t-planes of one
+// z-plane column, NR RHS per lane, one lane per site).
+hipError_t dslash_lds_launch(const DslashArgs &a, int sp, int lk, int nr, int dag, int epi, int grid,
+                             unsigned lds_bytes, hipStream_t s);
+bool dslash_lds_supported(int sp, int lk, int nr);
 
 // BLAS-1 / reductions (blas.hip).  All take an active-RHS list.
 enum { FIN_STORE = 0, FIN_ALPHA = 1, FIN_BETA = 2, FIN_RR = 3 };
@@ -159,6 +165,7 @@ hipError_t debug_tables(const Geom &g, int32_t *nb, int32_t *cb, uint8_t *par, h
 // The context: one lattice on one device.
 struct wd_ctx {
     int device = 0;
+    int lds_max = 0;  // bytes of LDS a work-group may use on this device
     hipStream_t stream = nullptr;
     int dims[4] = {0, 0, 0, 0};
     long long V = 0, Vh = 0;
@@ -243,6 +250,17 @@ TuneCfg default_cfg(int sp);
 // RHS groups outermost.
 constexpr int kTileOrders = 8;
 bool slab_order_ok(const Geom &g, int spb, int remap = 2);
+// Tile orders kLdsOrder0 .. kLdsOrder0 + kLdsOrders - 1: the LDS-staged
+// t-walking kernel with lds_chunk(order) t-planes per work-group (256
+// threads, one lane per site, no work-group cap).  It applies when a plane of
+// one parity has a multiple of 64 sites and at most 512, Lz is a multiple of
+// 8, Lt of the chunk, and three input planes of the RHS group fit in LDS.
+constexpr int kLdsOrder0 = kTileOrders;
+constexpr int kLdsOrders = 3;
+inline int lds_chunk(int remap) { return 4 << (remap - kLdsOrder0); }
+inline bool is_lds_order(int remap) { return remap >= kLdsOrder0 && remap < kLdsOrder0 + kLdsOrders; }
+bool lds_order_ok(const wd_ctx *c, int sp, int lk, int nr, int remap);
+unsigned lds_order_bytes(const wd_ctx *c, int sp, int nr);
 inline int remap_stripes(int remap) { return remap <= 2 || remap >= 5 ? 1 : (remap == 3 ? 2 : 4); }
 inline int remap_slab_dim(int remap) { return (remap == 5 || remap == 6) ? 3 : 2; }
 const TuneCfg *tuned_cfg(const wd_ctx *c, const Sweep &sw);

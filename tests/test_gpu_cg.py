@@ -174,6 +174,32 @@ def test_graph_replay_equals_eager_launches(wd, prec):
     lat.close()
 
 
+@pytest.mark.parametrize("prec", ["F64", "F16"])
+def test_in_sweep_alpha_finalize_equals_separate_kernel(wd, monkeypatch, prec):
+    """CG's alpha is finalized by leading work-groups of the third stencil
+    sweep; with WD_SEPARATE_FINALIZE=1 by its own kernel instead.  Both sum
+    the partials in the same order: the solves (one RHS escalated to the FP64
+    lane in the mixed case) agree bit for bit, with and without graphs."""
+    dims = (8, 8, 8, 8)
+    U = li.random_su3_field(dims, 0.5, seed=1003)
+    B = li.gaussian_spinor(li.volume(dims) // 2, seed=704, nrhs=4)
+    kap = [0.14757, 0.15, 0.155, 0.157]
+    code = {"F64": wd.WD_F64, "F16": wd.WD_F16}[prec]
+    lat = wd.Lattice(dims)
+    lat.gauge_load(dev(U), recon=12)
+    out = []
+    for sep, graphs in (("0", 1), ("1", 1), ("1", 0)):
+        monkeypatch.setenv("WD_SEPARATE_FINALIZE", sep)
+        X = empty_like_dev(B)
+        st, stats = lat.cg_solve(X, dev(B), kap, wd.solver_params(prec=code, maxiter=3000, graphs=graphs))
+        assert st == wd.WD_OK, stats
+        out.append((host(X), [(s["iters"], s["iters_fp64"], s["reliable_updates"]) for s in stats]))
+    note(f"alpha finalize {prec}: iters {out[0][1]}")
+    assert out[0][1] == out[1][1] == out[2][1]
+    assert all(np.array_equal(out[0][0].view(np.uint64), o[0].view(np.uint64)) for o in out[1:])
+    lat.close()
+
+
 def test_initial_guess(wd, oracle):
     """initial_guess = 1 starts from the vectors in x: from the solution of a
     nearby operator (kappa + 1e-3) the mixed solve needs fewer iterations and

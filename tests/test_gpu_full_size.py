@@ -52,13 +52,16 @@ def order_ok(dims, spb, remap):
 
 
 def all_shapes(dims, f64):
+    """Every launch shape of the FP64 or the FP16 (FP32 12-real links)
+    stencil on this lattice, the LDS-staged ones included."""
+    from test_gpu_tune import lds_candidates
     out = []
     for nr, rl in (F64_SHAPES if f64 else SLOPPY_SHAPES):
         for block in (64, 128, 256):
             for remap in range(8):
                 if order_ok(dims, block // rl, remap):
                     out.append((block, nr, rl, remap, 0))
-    return out
+    return out + lds_candidates(dims, 0 if f64 else 2, 12)
 
 
 def bits(t):
@@ -83,7 +86,8 @@ def tiled_field(dims, eps, seed, tile=8):
 def test_every_launch_shape_and_tile_order(wd, oracle, dims):
     """(16,16,16,32): 2 z-planes and 4 t-planes per XCD; (32,32,16,16): 512
     sites per plane (the 32^3 x 64 plane, so 4 y-stripes apply) with 2 z- and
-    2 t-planes per XCD."""
+    2 t-planes per XCD.  The FP16 shapes include the LDS-staged kernel (4, 8,
+    16 t-planes per work-group, 1 and 2 RHS per lane)."""
     import torch
     V = li.volume(dims)
     U = li.random_su3_field(dims, 0.5, seed=1201)
@@ -106,7 +110,7 @@ def test_every_launch_shape_and_tile_order(wd, oracle, dims):
                 assert e <= 6e-4 and m <= 3e-3
             shapes = all_shapes(dims, f64)
             orders = sorted({s[3] for s in shapes})
-            assert orders == list(range(8))
+            assert orders == list(range(8 if f64 else 11))
             checked = set()
             out = torch.empty_like(d_in)
             for shape in shapes:
