@@ -60,10 +60,11 @@ WORKLOADS = {
     "c6_measure": dict(dims=(32, 32, 32, 64), eps=0.5, kappa=0.156, cfg=2, src=(0, 0, 0, 0)),
 }
 PRECS = {"f64": 0, "f32": 1, "f16": 2, "f16l16": 2 | 0x10, "f32l16": 1 | 0x10,
-         "f16r18": 2 | 0x20, "f32r18": 1 | 0x20, "i16": 3, "i16l16": 3 | 0x10}
+         "f16r18": 2 | 0x20, "f32r18": 1 | 0x20, "i16": 3, "i16l16": 3 | 0x10,
+         "f32r8": 1 | 0x40, "f16r8": 2 | 0x40}
 DTYPE = {"f64": "f64", "f32": "f32", "f16": "f16+norm/f32", "f16l16": "f16+norm/f32",
          "f32l16": "f32", "f16r18": "f16+norm/f32", "f32r18": "f32", "i16": "i16+norm/f32",
-         "i16l16": "i16+norm/f32"}
+         "i16l16": "i16+norm/f32", "f32r8": "f32", "f16r8": "f16+norm/f32"}
 DEFAULT_STEPS = {"c4_serving": (1, 1), "c5_hmc": (40, 60)}
 
 
@@ -473,7 +474,8 @@ def dslash_section(wd, Ud, dims, stream_gbs, prec, nrhs, tuned=1):
     log("[bench] stencil error vs FP64: " + ", ".join(f"{k} {v:.2e}" for k, v in err.items()))
     del psi, ref, out
     rows = []
-    cases = [("f64", 0, 1), ("f32", 1, 1), ("f16", 2, 1), ("f16l16", 2 | 0x10, 1)]
+    cases = [("f64", 0, 1), ("f32", 1, 1), ("f16", 2, 1), ("f16l16", 2 | 0x10, 1), ("f32r8", 1 | 0x40, 1),
+             ("f16r8", 2 | 0x40, 1)]
     cases.append((next(k for k, v in PRECS.items() if v == prec), prec, nrhs))
     for name, code, n in cases:
         if tuned:

@@ -71,6 +71,13 @@ typedef enum { WD_F64 = 0, WD_F32 = 1, WD_F16 = 2, WD_I16 = 3 } wd_prec;
  * links. */
 #define WD_LINKS_F16 0x10
 #define WD_LINKS_R18 0x20
+/* Or-ed into WD_F32 / WD_F16: FP32 links stored as 8 reals (32 bytes instead
+ * of 48; the paper's closing remarks on reconstructing links on the fly): of
+ * a column- and row-permuted copy of the link, chosen per link so that the
+ * reconstruction is well conditioned, a2, a3, b1 and the phases of a1 and
+ * c1; the rest is rebuilt in registers from unitarity and det U = 1.  1 or 2
+ * RHS per lane (for sweeps with few RHS, where the link bytes weigh most). */
+#define WD_LINKS_R8 0x40
 typedef enum { WD_FULL = 0, WD_EVEN = 1, WD_ODD = 2 } wd_parity;
 
 /* wd_gauge_load flags: storage of the FP64 operator's links. */

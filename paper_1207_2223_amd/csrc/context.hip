@@ -82,18 +82,20 @@ const char *link_ptr(const wd_ctx *c, int lk)
     if (lk == LK_F64_18 || lk == LK_F64_12) return c->links64;
     if (lk == LK_F32_12) return c->links32;
     if (lk == LK_F32_18) return c->links32r;
+    if (lk == LK_F32_8) return c->links8;
     return c->links16;
 }
 
 wd_status decode_prec(const wd_ctx *c, int prec, int *sp, int *lk, int *xp)
 {
     const int base = prec & 0xf;
-    const bool l16 = (prec & WD_LINKS_F16) != 0, r18 = (prec & WD_LINKS_R18) != 0;
-    if ((prec & ~(0xf | WD_LINKS_F16 | WD_LINKS_R18)) || base > WD_I16 || (base == WD_F64 && (l16 || r18)) ||
-        (l16 && r18) || (base == WD_I16 && r18))
+    const bool l16 = (prec & WD_LINKS_F16) != 0, r18 = (prec & WD_LINKS_R18) != 0, r8 = (prec & WD_LINKS_R8) != 0;
+    if ((prec & ~(0xf | WD_LINKS_F16 | WD_LINKS_R18 | WD_LINKS_R8)) || base > WD_I16 ||
+        (base == WD_F64 && (l16 || r18 || r8)) || (int)l16 + (int)r18 + (int)r8 > 1 ||
+        (base == WD_I16 && (r18 || r8)))
         return set_error(WD_ERR_ARG, "bad precision code 0x%x", prec);
     *sp = base == WD_F64 ? SP_F64 : (base == WD_F32 ? SP_F32 : (base == WD_F16 ? SP_F16 : SP_I16));
-    *lk = *sp == SP_F64 ? c->lk64 : (l16 ? LK_F16_12 : (r18 ? LK_F32_18 : LK_F32_12));
+    *lk = *sp == SP_F64 ? c->lk64 : (l16 ? LK_F16_12 : (r18 ? LK_F32_18 : (r8 ? LK_F32_8 : LK_F32_12)));
     *xp = *sp == SP_F64 ? SP_F64 : SP_F32;
     return WD_OK;
 }
@@ -159,7 +161,7 @@ wd_status run_sweep(wd_ctx *c, const Sweep &sw, const TuneCfg *cfg)
     if (sw.nact <= 0) return WD_OK;
     if (!cfg && c->use_tuned) cfg = tuned_cfg(c, sw);
     TuneCfg t = cfg ? *cfg : default_cfg(sw.sp);
-    if (!dslash_shape_supported(sw.sp, t.nr, t.rl) || t.block < 64 || t.block > 256 || (t.block & 63))
+    if (!dslash_shape_supported(sw.sp, sw.lk, t.nr, t.rl) || t.block < 64 || t.block > 256 || (t.block & 63))
         return set_error(WD_ERR_ARG, "unsupported launch shape block %d nr %d rl %d", t.block, t.nr, t.rl);
     const int nr = t.nr, rl = t.rl;
     DslashArgs a;
@@ -381,6 +383,7 @@ wd_status wd_destroy(wd_ctx *c)
     if (c->links32) (void)hipFree(c->links32);
     if (c->links16) (void)hipFree(c->links16);
     if (c->links32r) (void)hipFree(c->links32r);
+    if (c->links8) (void)hipFree(c->links8);
     for (int k = 0; k < 2; k++)
         if (c->pinned[k]) (void)hipHostFree(c->pinned[k]);
     for (auto &e : c->events) {
@@ -409,7 +412,8 @@ wd_status wd_gauge_load(wd_ctx *c, const double *U, uint32_t flags)
     const int lk64 = (flags & WD_RECON_12) ? LK_F64_12 : LK_F64_18;
     const size_t nl = (size_t)8 * c->g.cs;  // (parity, mu) blocks of cs link slots
     const size_t n64 = link_bytes(lk64) * nl, n32 = link_bytes(LK_F32_12) * nl,
-                 n16 = link_bytes(LK_F16_12) * nl, n32r = link_bytes(LK_F32_18) * nl;
+                 n16 = link_bytes(LK_F16_12) * nl, n32r = link_bytes(LK_F32_18) * nl,
+                 n8 = link_bytes(LK_F32_8) * nl;
     WD_HIP(hipStreamSynchronize(c->stream));
     if (c->links64 && c->lk64 != lk64) {
         WD_HIP(hipFree(c->links64));
@@ -428,12 +432,14 @@ wd_status wd_gauge_load(wd_ctx *c, const double *U, uint32_t flags)
     WD_TRY(alloc(&c->links32, n32));
     WD_TRY(alloc(&c->links16, n16));
     WD_TRY(alloc(&c->links32r, n32r));
+    WD_TRY(alloc(&c->links8, n8));
     c->lk64 = lk64;
     hipError_t e;
     if ((e = pack_gauge(U, c->links64, lk64, c->g, c->stream)) != hipSuccess ||
         (e = pack_gauge(U, c->links32, LK_F32_12, c->g, c->stream)) != hipSuccess ||
         (e = pack_gauge(U, c->links16, LK_F16_12, c->g, c->stream)) != hipSuccess ||
-        (e = pack_gauge(U, c->links32r, LK_F32_18, c->g, c->stream)) != hipSuccess)
+        (e = pack_gauge(U, c->links32r, LK_F32_18, c->g, c->stream)) != hipSuccess ||
+        (e = pack_gauge(U, c->links8, LK_F32_8, c->g, c->stream)) != hipSuccess)
         return set_error(WD_ERR_HIP, "gauge packing failed: %s", hipGetErrorString(e));
     c->have_gauge = true;
     return WD_OK;
@@ -520,7 +526,7 @@ wd_status wd_dslash_shaped(wd_ctx *c, double *out, const double *in, int nrhs, i
     }
     const bool lds_ok = is_lds_order(t.remap) && lds_order_ok(c, sp, lk, t.nr, t.remap) && t.rl == 1 &&
                         t.block == 256 && t.occ == 0;
-    if (!lds_ok && (!dslash_shape_supported(sp, t.nr, t.rl) || t.block < 64 || t.block > 256 || (t.block & 63) ||
+    if (!lds_ok && (!dslash_shape_supported(sp, lk, t.nr, t.rl) || t.block < 64 || t.block > 256 || (t.block & 63) ||
                     t.remap < 0 || t.remap >= kTileOrders || (t.occ != 0 && (t.occ < 2 || t.occ > kMaxOcc)) ||
                     (t.remap >= 2 && !slab_order_ok(c->g, t.block / t.rl, t.remap))))
         return set_error(WD_ERR_ARG, "launch shape block %d nr %d rl %d order %d cap %d not supported here",

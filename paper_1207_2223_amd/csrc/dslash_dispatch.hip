@@ -48,10 +48,10 @@ hipError_t dslash_launch(const DslashArgs &a, int sp, int lk, int nr, int rl, in
     return hipErrorInvalidValue;
 }
 
-bool dslash_shape_supported(int sp, int nr, int rl)
+bool dslash_shape_supported(int sp, int lk, int nr, int rl)
 {
     if (rl != 1 && rl != 2 && rl != 4) return false;
-    if (sp == SP_F64) return nr == 1 || nr == 2;
+    if (sp == SP_F64 || lk == LK_F32_8) return nr == 1 || nr == 2;  // (8-real links: for few RHS)
     return nr >= 1 && nr <= 4;
 }
 

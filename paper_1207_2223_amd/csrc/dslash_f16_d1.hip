@@ -1,4 +1,4 @@
-// Stencil instantiations: FP16 spinors (per-site FP32 norm) with FP32 12-real, FP32 18-real or FP16 12-real links, adjoint hopping.
+// Stencil instantiations: FP16 spinors (per-site FP32 norm) with FP32 12-real, FP32 18-real, FP16 12-real or FP32 8-real links, adjoint hopping.
 #include "dslash_impl.h"
 
 namespace wd {
@@ -47,6 +47,14 @@ hipError_t dslash_launch_f16_d1(const DslashArgs &a, int lk, int nr, int rl, int
         WD_DSL_SHAPE(SP_F16, LK_F32_18, 2, 4, true)
         WD_DSL_SHAPE(SP_F16, LK_F32_18, 3, 4, true)
         WD_DSL_SHAPE(SP_F16, LK_F32_18, 4, 4, true)
+    }
+    if (lk == LK_F32_8) {
+        WD_DSL_SHAPE(SP_F16, LK_F32_8, 1, 1, true)
+        WD_DSL_SHAPE(SP_F16, LK_F32_8, 2, 1, true)
+        WD_DSL_SHAPE(SP_F16, LK_F32_8, 1, 2, true)
+        WD_DSL_SHAPE(SP_F16, LK_F32_8, 2, 2, true)
+        WD_DSL_SHAPE(SP_F16, LK_F32_8, 1, 4, true)
+        WD_DSL_SHAPE(SP_F16, LK_F32_8, 2, 4, true)
     }
     return hipErrorInvalidValue;
 }

@@ -218,6 +218,7 @@ wd_status face_setup(wd_ctx *c, int prec, int P, int *sp, int *lk, Field *fi, Fi
     int xp;
     WD_TRY(decode_prec(c, prec, sp, lk, &xp));
     if (*sp == SP_I16) return set_error(WD_ERR_ARG, "faces take FP64, FP32 or FP16 spinors");
+    if (*lk == LK_F32_8) return set_error(WD_ERR_ARG, "faces take 12- or 18-real links");
     WD_TRY(alloc_field(c, "fc_in", *sp, 1, 1, fi));
     WD_TRY(alloc_field(c, "fc_out", *sp, 1, 1, fo));
     const int fs = c->g.Lxh * c->g.L[1] * c->g.L[2];

@@ -48,6 +48,40 @@ __global__ void __launch_bounds__(kBlock) k_pack_gauge(const double *U, char *ds
         for (int k = 0; k < 3; k++)
             d[k * cs + cb] = make_float4((float)u[4 * k], (float)u[4 * k + 1], (float)u[4 * k + 2],
                                          (float)u[4 * k + 3]);
+    } else if (LK == LK_F32_8) {
+        // U' = s P C_k(U) (see LinkIO<LK_F32_8>): k takes the largest entry
+        // of row 1 to U'_11; P swaps rows 2 and 3 (and s = -1) when |U'_31| <
+        // |U'_21|; a block-diagonal U' keeps its lower block's first row
+        double m[3];
+        for (int j = 0; j < 3; j++) m[j] = u[2 * j] * u[2 * j] + u[2 * j + 1] * u[2 * j + 1];
+        const int k = (m[1] > m[0] && m[1] >= m[2]) ? 1 : ((m[2] > m[0] && m[2] > m[1]) ? 2 : 0);
+        double v[18];
+        for (int row = 0; row < 3; row++)
+            for (int j = 0; j < 3; j++) {
+                v[6 * row + 2 * j] = u[6 * row + 2 * ((j + k) % 3)];
+                v[6 * row + 2 * j + 1] = u[6 * row + 2 * ((j + k) % 3) + 1];
+            }
+        const double N = v[2] * v[2] + v[3] * v[3] + v[4] * v[4] + v[5] * v[5];
+        const bool deg = !(N >= 1e-30);
+        const bool swp = !deg && v[12] * v[12] + v[13] * v[13] < v[6] * v[6] + v[7] * v[7];
+        if (swp)
+            for (int e = 0; e < 6; e++) {
+                const double r2 = v[6 + e];
+                v[6 + e] = -v[12 + e];
+                v[12 + e] = -r2;
+                v[e] = -v[e];
+            }
+        const double inv2pi = 0.15915494309189535;
+        // the phases in revolutions, k and (P, block) in their lowest mantissa bits
+        const float pa = __uint_as_float((__float_as_uint((float)(atan2(v[1], v[0]) * inv2pi)) & ~3u) | (unsigned)k);
+        const float pc = __uint_as_float((__float_as_uint(deg ? 0.0f : (float)(atan2(v[13], v[12]) * inv2pi)) & ~3u) |
+                                         (swp ? 1u : 0u) | (deg ? 2u : 0u));
+        float4 *d = reinterpret_cast<float4 *>(dst) + (size_t)blk * 2 * cs;
+        if (deg)
+            d[cb] = make_float4((float)v[8], (float)v[9], (float)v[10], (float)v[11]);
+        else
+            d[cb] = make_float4((float)v[2], (float)v[3], (float)v[4], (float)v[5]);
+        d[cs + cb] = make_float4(deg ? 0.0f : (float)v[6], deg ? 0.0f : (float)v[7], pa, pc);
     } else if (LK == LK_F32_18) {
         float4 *d = reinterpret_cast<float4 *>(dst) + (size_t)blk * 4 * cs;
         for (int k = 0; k < 4; k++)
@@ -147,6 +181,7 @@ hipError_t pack_gauge(const double *U, char *dst, int lk, const Geom &g, hipStre
     case LK_F32_12: hipLaunchKernelGGL(k_pack_gauge<LK_F32_12>, gr, dim3(kBlock), 0, s, U, dst, g); break;
     case LK_F16_12: hipLaunchKernelGGL(k_pack_gauge<LK_F16_12>, gr, dim3(kBlock), 0, s, U, dst, g); break;
     case LK_F32_18: hipLaunchKernelGGL(k_pack_gauge<LK_F32_18>, gr, dim3(kBlock), 0, s, U, dst, g); break;
+    case LK_F32_8: hipLaunchKernelGGL(k_pack_gauge<LK_F32_8>, gr, dim3(kBlock), 0, s, U, dst, g); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -571,7 +571,8 @@ struct BatchSolver {
                                      (unsigned long long)pstride, (unsigned long long)fold})
             add(v);
         for (const void *q : {(const void *)c->links64, (const void *)c->links32, (const void *)c->links16,
-                              (const void *)c->links32r, (const void *)coef1, (const void *)coef2,
+                              (const void *)c->links32r, (const void *)c->links8, (const void *)coef1,
+                              (const void *)coef2,
                               (const void *)rr, (const void *)alpha, (const void *)beta, (const void *)partial,
                               (const void *)act, (const void *)act64, (const void *)ahist})
             add((unsigned long long)(uintptr_t)q);

@@ -255,7 +255,7 @@ extern "C" wd_status wd_tune(wd_ctx *c, int nrhs, int prec, char *report, size_t
         for (int nr : nrs)
             for (int b : blocks)
                 for (int rm = 0; rm < kTileOrders; rm++) {
-                    if (!dslash_shape_supported(sp, nr, rl)) continue;
+                    if (!dslash_shape_supported(sp, lk, nr, rl)) continue;
                     if (rm >= 2 && !slab_order_ok(c->g, b / rl, rm)) continue;
                     if (nr * rl > 2 * nrhs && !(nr == 1 && rl == 1)) continue;  // mostly idle lanes
                     TuneCfg q;
@@ -403,7 +403,7 @@ extern "C" wd_status wd_tune(wd_ctx *c, int nrhs, int prec, char *report, size_t
             TuneCfg cc;
             double us_cached = 0;
             if (cache_lookup(cache, cache_key(c, nrhs, sp, lk, k.dag, k.epi), &cc, &us_cached) &&
-                dslash_shape_supported(sp, cc.nr, cc.rl) && (cc.occ == 0 || (cc.occ >= 2 && cc.occ <= kMaxOcc)) &&
+                dslash_shape_supported(sp, lk, cc.nr, cc.rl) && (cc.occ == 0 || (cc.occ >= 2 && cc.occ <= kMaxOcc)) &&
                 (is_lds_order(cc.remap)
                      ? (lds_order_ok(c, sp, lk, cc.nr, cc.remap) && cc.rl == 1 && cc.block == 256 && cc.occ == 0)
                      : (cc.remap < 2 || slab_order_ok(c->g, cc.block / cc.rl, cc.remap)))) {

@@ -27,7 +27,7 @@ enum { SP_F64 = 0, SP_F32 = 1, SP_F16 = 2, SP_I16 = 3 };
 
 // Formats that store a per-site FP32 norm next to 16-bit values.
 __host__ __device__ constexpr bool has_norm(int sp) { return sp == SP_F16 || sp == SP_I16; }
-enum { LK_F64_18 = 0, LK_F64_12 = 1, LK_F32_12 = 2, LK_F16_12 = 3, LK_F32_18 = 4 };
+enum { LK_F64_18 = 0, LK_F64_12 = 1, LK_F32_12 = 2, LK_F16_12 = 3, LK_F32_18 = 4, LK_F32_8 = 5 };
 
 typedef _Float16 half8_t __attribute__((ext_vector_type(8)));
 
@@ -444,10 +444,104 @@ template <> struct LinkIO<LK_F32_18> {
     }
 };
 
+// FP32 with 8 reals.  The link U is stored as U' = s P C_k(U): C_k shifts
+// the columns cyclically (C_k(U)_ij = U_i,(j+k)%3, det unchanged), with k
+// chosen so that U'_11 = U_1k is the largest entry of row 1 (|a1|^2 >= 1/3:
+// |a1| = sqrt(1 - N) is then accurate in FP32); P swaps rows 2 and 3 and
+// s = -1 when |U'_31| < |U'_21| (s P has det 1), so that |c1|^2 >= N / 2.
+// U' is kept as a2, a3 (float4 chunk 0), b1 and the phases of a1 and c1 in
+// revolutions (arg / 2 pi; chunk 1), with k in the two lowest mantissa bits of
+// the first phase and P in the lowest bit of the second (a change of at most
+// 3 ulp of a phase).  The rest follows from unitarity and det U' = 1: with
+// N = |a2|^2 + |a3|^2,
+//   |a1| = sqrt(1 - N),  |c1| = sqrt(N - |b1|^2)  (row 1, column 1 unit),
+//   b2 = -(c1* a3* + a2 a1* b1) / N,   b3 = (a2* c1* - a3 a1* b1) / N,
+//   c2 = (a3* b1* - a2 a1* c1) / N,   c3 = -(a2* b1* + a3 a1* c1) / N
+// (the 2x2 systems of row orthogonality with c* = a x b and b* = c x a);
+// every term keeps the relative precision of the stored values, so the
+// division by a small N costs no accuracy.  N = 0 (below 1e-30: U'
+// block-diagonal, e.g. U = 1) leaves the lower block W undetermined: such a
+// link stores W's first row (p, q) in chunk 0, b1 = 0, and bit 1 of the
+// second phase set; then W = [[p, q], [-a1* q*, a1* p*]] (det W = a1*,
+// |a1| = 1).  Finally U = C_-k(s P U').
+template <> struct LinkIO<LK_F32_8> {
+    typedef float real;
+    __device__ static __forceinline__ void load(const char *U8, int cs, int blk, int i, float u[18])
+    {
+        const char *p = U8 + (size_t)blk * 2 * cs * 16;
+        const uint32_t off = (uint32_t)i * 16u;
+        const flt4_t w0 = ld_off<flt4_t, true>(p, off);
+        const flt4_t w1 = ld_off<flt4_t, true>(p + (size_t)cs * 16, off);
+        const float a2r = w0.x, a2i = w0.y, a3r = w0.z, a3i = w0.w, b1r = w1.x, b1i = w1.y;
+        const int k = (int)(__float_as_uint(w1.z) & 3u);
+        const unsigned cb = __float_as_uint(w1.w) & 3u;
+        const bool swp = (cb & 1u) != 0, deg = (cb & 2u) != 0;
+        const float N = fmaT(a2r, a2r, fmaT(a2i, a2i, fmaT(a3r, a3r, a3i * a3i)));
+        const float ca = __builtin_amdgcn_cosf(w1.z), sa = __builtin_amdgcn_sinf(w1.z);
+        const float a1m = deg ? 1.0f : __builtin_sqrtf(fmaxf(1.0f - N, 0.0f));
+        const float c1m = __builtin_sqrtf(fmaxf(N - fmaT(b1r, b1r, b1i * b1i), 0.0f));
+        const float a1r = a1m * ca, a1i = a1m * sa;
+        const float c1r = c1m * __builtin_amdgcn_cosf(w1.w), c1i = c1m * __builtin_amdgcn_sinf(w1.w);
+        const float iN = __builtin_amdgcn_rcpf(N);
+        // t = a1* b1 and s = a1* c1
+        const float tr = fmaT(a1r, b1r, a1i * b1i), ti = fmaT(a1r, b1i, -a1i * b1r);
+        const float sr = fmaT(a1r, c1r, a1i * c1i), si = fmaT(a1r, c1i, -a1i * c1r);
+        float v[18];
+        v[0] = a1r; v[1] = a1i; v[2] = a2r; v[3] = a2i; v[4] = a3r; v[5] = a3i;
+        v[6] = b1r; v[7] = b1i;
+        // b2 = -(conj(c1 a3) + a2 t) / N
+        v[8] = -(fmaT(c1r, a3r, -c1i * a3i) + fmaT(a2r, tr, -a2i * ti)) * iN;
+        v[9] = -(-fmaT(c1r, a3i, c1i * a3r) + fmaT(a2r, ti, a2i * tr)) * iN;
+        // b3 = (conj(a2 c1) - a3 t) / N
+        v[10] = (fmaT(a2r, c1r, -a2i * c1i) - fmaT(a3r, tr, -a3i * ti)) * iN;
+        v[11] = (-fmaT(a2r, c1i, a2i * c1r) - fmaT(a3r, ti, a3i * tr)) * iN;
+        v[12] = c1r; v[13] = c1i;
+        // c2 = (conj(a3 b1) - a2 s) / N
+        v[14] = (fmaT(a3r, b1r, -a3i * b1i) - fmaT(a2r, sr, -a2i * si)) * iN;
+        v[15] = (-fmaT(a3r, b1i, a3i * b1r) - fmaT(a2r, si, a2i * sr)) * iN;
+        // c3 = -(conj(a2 b1) + a3 s) / N
+        v[16] = -(fmaT(a2r, b1r, -a2i * b1i) + fmaT(a3r, sr, -a3i * si)) * iN;
+        v[17] = -(-fmaT(a2r, b1i, a2i * b1r) + fmaT(a3r, si, a3i * sr)) * iN;
+        // block-diagonal U': row 1 (a1, 0, 0), W = [[p, q], [-a1* q*, a1* p*]]
+        // with (p, q) in the a2, a3 slots
+        {
+            const float d[18] = {a1r, a1i, 0.0f, 0.0f, 0.0f, 0.0f,
+                                 0.0f, 0.0f, a2r, a2i, a3r, a3i,
+                                 0.0f, 0.0f,
+                                 -fmaT(a1r, a3r, -a1i * a3i), -fmaT(-a1r, a3i, -a1i * a3r),
+                                 fmaT(a1r, a2r, -a1i * a2i), fmaT(-a1r, a2i, -a1i * a2r)};
+#pragma unroll
+            for (int e = 0; e < 18; e++) v[e] = deg ? d[e] : v[e];
+        }
+        // undo s P: rows 2 and 3 back, all signs back
+        const float sg = swp ? -1.0f : 1.0f;
+#pragma unroll
+        for (int e = 0; e < 6; e++) {
+            const float r2 = v[6 + e], r3 = v[12 + e];
+            v[e] *= sg;
+            v[6 + e] = sg * (swp ? r3 : r2);
+            v[12 + e] = sg * (swp ? r2 : r3);
+        }
+        // undo C_k: U_i,m = U'_i,(m - k) mod 3
+#pragma unroll
+        for (int row = 0; row < 3; row++)
+#pragma unroll
+            for (int m = 0; m < 3; m++)
+#pragma unroll
+                for (int ri = 0; ri < 2; ri++) {
+                    const float x0 = v[6 * row + 2 * m + ri], x1 = v[6 * row + 2 * ((m + 2) % 3) + ri],
+                                x2 = v[6 * row + 2 * ((m + 1) % 3) + ri];
+                    u[6 * row + 2 * m + ri] = k == 0 ? x0 : (k == 1 ? x1 : x2);
+                }
+    }
+};
+
 __host__ __device__ constexpr size_t link_bytes(int lk)
 {
     return lk == LK_F64_18 ? 144
-                           : (lk == LK_F64_12 ? 96 : (lk == LK_F32_12 ? 48 : (lk == LK_F16_12 ? 24 : 72)));
+                           : (lk == LK_F64_12 ? 96
+                                              : (lk == LK_F32_12 ? 48
+                                                                 : (lk == LK_F16_12 ? 24 : (lk == LK_F32_8 ? 32 : 72))));
 }
 
 // ---------------------------------------------------------------------------

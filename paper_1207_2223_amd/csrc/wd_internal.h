@@ -103,7 +103,7 @@ inline unsigned occ_lds_bytes(int occ) { return occ > 0 ? kLdsPerCU / (unsigned)
 
 hipError_t dslash_launch(const DslashArgs &a, int sp, int lk, int nr, int rl, int dag, int epi,
                          int block, int grid, hipStream_t s);
-bool dslash_shape_supported(int sp, int nr, int rl);
+bool dslash_shape_supported(int sp, int lk, int nr, int rl);
 // The LDS-staged t-walking stencil (tile orders kLdsOrder0 and up: work-groups
 // of 256 threads walking kLdsChunk[order - kLdsOrder0] t-planes of one
 // z-plane column, NR RHS per lane, one lane per site).
@@ -177,6 +177,7 @@ struct wd_ctx {
     char *links32 = nullptr;
     char *links16 = nullptr;
     char *links32r = nullptr;  // FP32 18-real
+    char *links8 = nullptr;    // FP32 8-real (flagged links in links32)
 
     // named, growable device workspaces
     std::map<std::string, std::pair<void *, size_t>> ws;

@@ -18,6 +18,7 @@ WD_OK, WD_ERR_ARG, WD_ERR_DIMS, WD_ERR_OOM, WD_ERR_HIP, WD_ERR_NOCONV, WD_ERR_NA
 WD_F64, WD_F32, WD_F16, WD_I16 = 0, 1, 2, 3
 WD_LINKS_F16 = 0x10
 WD_LINKS_R18 = 0x20
+WD_LINKS_R8 = 0x40
 WD_FULL, WD_EVEN, WD_ODD = 0, 1, 2
 WD_RECON_18, WD_RECON_12 = 0, 1
 

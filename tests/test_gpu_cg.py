@@ -44,12 +44,13 @@ def test_full_lattice_fp64_4444(wd, oracle):
     lat.close()
 
 
-@pytest.mark.parametrize("prec", ["F64", "F32", "F16", "F16L", "F16R", "I16", "I16L"])
+@pytest.mark.parametrize("prec", ["F64", "F32", "F16", "F16L", "F16R", "I16", "I16L", "F32R8", "F16R8"])
 @pytest.mark.parametrize("dims", [(8, 8, 8, 8), (6, 4, 4, 6)])
 def test_even_odd_solves(wd, oracle, prec, dims):
     code = {"F64": wd.WD_F64, "F32": wd.WD_F32, "F16": wd.WD_F16,
             "F16L": wd.WD_F16 | wd.WD_LINKS_F16, "F16R": wd.WD_F16 | wd.WD_LINKS_R18,
-            "I16": wd.WD_I16, "I16L": wd.WD_I16 | wd.WD_LINKS_F16}[prec]
+            "I16": wd.WD_I16, "I16L": wd.WD_I16 | wd.WD_LINKS_F16,
+            "F32R8": wd.WD_F32 | wd.WD_LINKS_R8, "F16R8": wd.WD_F16 | wd.WD_LINKS_R8}[prec]
     V = li.volume(dims)
     kappa = 0.155
     U = li.random_su3_field(dims, 0.5, seed=li.config_seed(1))

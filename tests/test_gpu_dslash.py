@@ -77,7 +77,9 @@ def test_dslash_fp64_full_lattice(wd, oracle, dims):
 # F32R 8.7e-8 / 1.25e-7, F16R 2.5e-4 / 3.3e-4, I16 2.8e-5 / 2.7e-5, I16L
 # 2.0e-4 / 2.4e-4.
 SLOPPY_TOL = {"F32": (2e-7, 3e-7), "F16": (6e-4, 8e-4), "F16L": (9e-4, 1.4e-3), "F32L": (4.5e-4, 6e-4),
-              "F32R": (2e-7, 3e-7), "F16R": (6e-4, 8e-4), "I16": (6e-5, 7e-5), "I16L": (4.5e-4, 6e-4)}
+              "F32R": (2e-7, 3e-7), "F16R": (6e-4, 8e-4), "I16": (6e-5, 7e-5), "I16L": (4.5e-4, 6e-4),
+              # 8-real FP32 links (measured: F32R8 2.7e-7 / 3.9e-7, F16R8 as F16)
+              "F32R8": (6e-7, 9e-7), "F16R8": (6e-4, 8e-4)}
 
 
 @pytest.mark.parametrize("prec", sorted(SLOPPY_TOL))
@@ -90,7 +92,8 @@ def test_dslash_sloppy_precisions(wd, oracle, prec):
     code = {"F32": wd.WD_F32, "F16": wd.WD_F16, "F16L": wd.WD_F16 | wd.WD_LINKS_F16,
             "F32L": wd.WD_F32 | wd.WD_LINKS_F16, "F32R": wd.WD_F32 | wd.WD_LINKS_R18,
             "F16R": wd.WD_F16 | wd.WD_LINKS_R18, "I16": wd.WD_I16,
-            "I16L": wd.WD_I16 | wd.WD_LINKS_F16}[prec]
+            "I16L": wd.WD_I16 | wd.WD_LINKS_F16,
+            "F32R8": wd.WD_F32 | wd.WD_LINKS_R8, "F16R8": wd.WD_F16 | wd.WD_LINKS_R8}[prec]
     V = li.volume(dims)
     U = li.random_su3_field(dims, 0.5, seed=5)
     lat = wd.Lattice(dims)
@@ -184,3 +187,32 @@ def test_pack_unpack_round_trip_bit_exact(wd, dims):
         got = host(x)
         assert np.array_equal(got.view(np.uint64), X0.view(np.uint64)), eo
         lat.close()
+
+
+@pytest.mark.parametrize("eps", [0.5, 0.05, 0.0])
+def test_eight_real_links(wd, oracle, eps):
+    """8-real FP32 links against the oracle on a random field (eps 0.5), a
+    field near the identity (eps 0.05: |a2|^2 + |a3|^2 ~ 1e-3 after the
+    pivot, the division by it must not cost accuracy) and U = 1 (every link
+    block-diagonal: reconstructed exactly, so the stencil equals the 12-real
+    one value for value)."""
+    dims = (8, 8, 8, 8)
+    V = li.volume(dims)
+    U = li.random_su3_field(dims, eps, seed=9) if eps > 0 else li.unit_field(dims)
+    lat = wd.Lattice(dims)
+    lat.gauge_load(dev(U), recon=12)
+    psi = li.gaussian_spinor(V // 2, seed=10)
+    # (measured: FP32 spinors 2.9e-7 relative and 4.4e-7 max-abs at worst, FP16 as with 12-real links)
+    for sp, tol in ((wd.WD_F32, 6e-7), (wd.WD_F16, 6e-4)):
+        for dag in (0, 1):
+            ref = oracle.hop_eo(dims, U, psi, 1, dagger=bool(dag))
+            out8, out12 = empty_like_dev(psi), empty_like_dev(psi)
+            lat.dslash(out8, dev(psi), wd.WD_ODD, dag, sp | wd.WD_LINKS_R8)
+            lat.dslash(out12, dev(psi), wd.WD_ODD, dag, sp)
+            g8, g12 = host(out8), host(out12)
+            e8, e12, m8 = rel_err(g8, ref), rel_err(g12, ref), maxabs_ratio(g8, ref)
+            note(f"8-real eps {eps} sp {sp} dag {dag}: rel {e8:.2e} (12-real {e12:.2e}), max-abs ratio {m8:.2e}")
+            assert e8 <= tol and m8 <= 2 * tol
+            if eps == 0.0:
+                assert np.array_equal(g8, g12)
+    lat.close()
