@@ -400,10 +400,13 @@ wd_status wd_tune(wd_ctx *c, int nrhs, int prec, char *report, size_t len);
 
 /* Stencil micro-benchmark: `iters` back-to-back sweeps of the stencil with
  * epilogue epi (0 plain D_oe, 1 xpay+norm D_eo, 2 fused CG residual update
- * D_eo: Ap = x + coef D in, r -= alpha Ap, |r|^2) on
+ * on D_eo^dag as the solver's fourth sweep runs it: Ap = x + coef D^dag in,
+ * r -= alpha Ap, |r|^2) on
  * nrhs synthetic fields of precision prec, with the tuned shape if tuned = 1
- * and one was kept, else the default.  *ms (HOST) receives the HIP-event
- * time per sweep, *bytes (HOST, may be NULL) its algorithmic bytes. */
+ * and one was kept, else the default.  The sweeps rotate over copies of the
+ * links and fields (at least 2 GiB in all), so that they do not run from the
+ * last-level cache.  *ms (HOST) receives the HIP-event time per sweep,
+ * *bytes (HOST, may be NULL) its algorithmic bytes. */
 wd_status wd_bench_dslash(wd_ctx *c, int nrhs, int prec, int epi, int iters, int tuned,
                           double *ms, double *bytes);
 

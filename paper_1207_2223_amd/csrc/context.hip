@@ -167,7 +167,7 @@ wd_status run_sweep(wd_ctx *c, const Sweep &sw, const TuneCfg *cfg)
     DslashArgs a;
     a.g = c->g;
     a.P = sw.P;
-    a.links = link_ptr(c, sw.lk);
+    a.links = sw.links ? sw.links : link_ptr(c, sw.lk);
     a.in = sw.in.base;
     a.in_rs = sw.in.rs;
     a.out = sw.out.base;

@@ -223,6 +223,7 @@ struct Sweep {
     int dag = 0;
     int epi = EPI_PLAIN;
     int P = 0;
+    const char *links = nullptr;  // another copy of the packed links (else the context's)
     Field in, out, x, r;
     const double *coef = nullptr;
     const double *alpha = nullptr;
