@@ -134,6 +134,10 @@ def parse():
                          "prints its rows as one JSON line")
     ap.add_argument("--tune-only", action="store_true",
                     help="autotune (filling WD_TUNE_CACHE when set) and exit")
+    ap.add_argument("--shapes", default=None,
+                    help="only the parity stencil D_oe and D_oe^dag on the workload's lattice, RHS count and "
+                         "precision, 3 sweeps in each listed launch shape ('block,nr,rl,order,cap;...'), for "
+                         "profiling the tuner's candidates; prints one JSON line")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one plain 1 GiB device copy (counter calibration)")
     a = ap.parse_args()
@@ -332,6 +336,11 @@ def bench_solve(args, wd, torch):
         torch.cuda.synchronize()
         log("[bench] copy probe: 1 GiB read + 1 GiB written by one copy kernel")
         del a, b
+    if args.shapes:
+        rows = shapes_section(wd, lat, int(np.prod(dims)) // 2, nrhs, args.prec, args.shapes)
+        print(json.dumps({"workload": args.workload, "shapes": rows}), flush=True)
+        lat.close()
+        return None
     if args.dslash_only:
         lat.close()
         rows, err = dslash_section(wd, Ud, dims, copy_bandwidth(torch), PRECS[args.prec], nrhs, tuned=args.tuned)
@@ -491,6 +500,33 @@ def dslash_section(wd, Ud, dims, stream_gbs, prec, nrhs, tuned=1):
                 f"({gbs / HBM_PEAK_GBS * 100:.1f} % of peak, {gbs / stream_gbs * 100:.1f} % of copy)")
     lat.close()
     return rows, err
+
+
+def shapes_section(wd, lat, Vh, nrhs, prec, spec):
+    """D_oe and D_oe^dag on nrhs Gaussian sources in each launch shape of
+    `spec` ('block,nr,rl,order,cap;...'), 3 sweeps each; the stencil kernel's
+    HIP-event time per sweep (the library's per-launch timing)."""
+    import torch
+    shapes = [tuple(int(v) for v in t.split(",")) for t in spec.split(";") if t.strip()]
+    g = torch.Generator(device="cuda").manual_seed(3)
+    psi = torch.complex(torch.randn((nrhs, Vh, 4, 3), dtype=torch.float64, device="cuda", generator=g),
+                        torch.randn((nrhs, Vh, 4, 3), dtype=torch.float64, device="cuda", generator=g))
+    out = torch.empty_like(psi)
+    rows = []
+    for dag in (0, 1):
+        for sh in shapes:
+            wd.wd_timing_enable(lat.ctx, True)
+            for _ in range(3):
+                wd.wd_dslash_shaped(lat.ctx, out, psi, wd.WD_ODD, dag, PRECS[prec], sh)
+            torch.cuda.synchronize()
+            rep = wd.wd_timing_report(lat.ctx)
+            wd.wd_timing_read(lat.ctx)  # (resets the counts)
+            wd.wd_timing_enable(lat.ctx, False)
+            for name, (n, ms, by, _) in rep.items():
+                rows.append({"dag": dag, "shape": list(sh), "kernel": name, "us": ms / n * 1e3,
+                             "GB_s": by / (ms * 1e-3) / 1e9})
+                log(f"[bench] shape {sh} dag {dag}: {name} {ms / n * 1e3:.1f} us")
+    return rows
 
 
 def shard_section(wd, Ud, dims, lt=8, tuned=1):

@@ -155,8 +155,13 @@ wd_status wd_dslash(wd_ctx *c, double *out, const double *in, int out_parity, in
  * kernel walking 4, 8 or 16 t-planes of a z-plane column per work-group, with
  * 256 threads, 1 lane per site, 1 or 2 RHS per lane, no cap, FP16 or FP32
  * spinors, where a plane of one parity holds a multiple of 64 sites up to
- * 512, Lz is a multiple of 8 and Lt of the chunk), work-groups per CU cap (0
- * or 2..8)}, or NULL for the default shape.  Every supported shape gives the
+ * 512, Lz is a multiple of 8 and Lt of the chunk; 11, 12, 13: the t-walking
+ * kernel, each work-group a tile of `threads` sites (64, 128 or 256 dividing
+ * the sites of a plane of one parity) walking 4, 8 or 16 t-planes with the t
+ * neighbours held in registers, 1 lane per site, 1 to 3 RHS per lane, FP16
+ * spinors with FP32 or FP16 12-real links, Lz a multiple of 8 and Lt of the
+ * chunk), work-groups per CU cap (0 or 2..8)}, or NULL for the default
+ * shape.  Every supported shape gives the
  * same bits; WD_ERR_ARG for a shape this lattice or precision does not
  * support (e.g. a slab tile order when the slab extent is not a multiple of
  * 8).  For checking launch shapes against a reference operator. */
@@ -382,9 +387,10 @@ wd_status wd_timing_report(wd_ctx *c, char *buf, size_t len);
 /* Autotune the launch shapes of the even-odd solver's four stencil sweeps for
  * nrhs right-hand sides in precision prec (wd_prec, | WD_LINKS_F16).  Every
  * supported shape (threads per work-group, RHS per lane, lanes per site, XCD
- * tile order, and where it applies the LDS-staged kernel, see
- * wd_dslash_shaped) is timed with HIP events on synthetic fields, then the
- * fastest with a cap of 2..8 work-groups per compute unit; a shape whose
+ * tile order, and where they apply the LDS-staged and the t-walking
+ * kernels, see wd_dslash_shaped) is timed with HIP events on synthetic
+ * fields, then the fastest with a cap of 2..8 work-groups per compute unit
+ * (not for an LDS-staged shape); a shape whose
  * vectors or norm partials are not bitwise identical to the reference shape
  * is rejected.  The fastest shapes are kept in the context and used by
  * solves with wd_solver_params.tuned = 1.  report: HOST buffer of len bytes

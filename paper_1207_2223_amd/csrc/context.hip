@@ -138,15 +138,16 @@ static wd_status timing_begin(wd_ctx *c, hipEvent_t *e0, hipEvent_t *e1)
     return WD_OK;
 }
 
-static void timing_end(wd_ctx *c, const Sweep &sw, hipEvent_t e1, bool lds, int nr, int rl)
+// kind: 0 dslash_kernel, 1 dslash_lds_kernel, 2 dslash_tw_kernel
+static void timing_end(wd_ctx *c, const Sweep &sw, hipEvent_t e1, int kind, int nr, int rl)
 {
     (void)hipEventRecord(e1, c->stream);
     const double b = sweep_bytes(c, sw);
     char name[96];
     // the kernel's template instance as profilers print it
-    if (lds)
-        snprintf(name, sizeof(name), "dslash_lds_kernel<%d, %d, %d, %s, %d>", sw.sp, sw.lk, nr,
-                 sw.dag ? "true" : "false", sw.epi);
+    if (kind != 0)
+        snprintf(name, sizeof(name), "dslash_%s_kernel<%d, %d, %d, %s, %d>", kind == 1 ? "lds" : "tw", sw.sp,
+                 sw.lk, nr, sw.dag ? "true" : "false", sw.epi);
     else
         snprintf(name, sizeof(name), "dslash_kernel<%d, %d, %d, %d, %s, %d>", sw.sp, sw.lk, nr, rl,
                  sw.dag ? "true" : "false", sw.epi);
@@ -200,6 +201,25 @@ wd_status run_sweep(wd_ctx *c, const Sweep &sw, const TuneCfg *cfg)
     a.tpp = 1;
     a.nzl = 1;
     a.nys = 1;
+    a.tch = 1;
+    if (is_tw_order(t.remap)) {
+        if (!tw_order_ok(c, sw.sp, sw.lk, nr, rl, t.block, t.remap))
+            return set_error(WD_ERR_ARG, "t-walking order %d does not apply here (sp %d lk %d nr %d rl %d block %d)",
+                             t.remap, sw.sp, sw.lk, nr, rl, t.block);
+        a.tpp = c->g.Lxh * c->g.L[1] / t.block;
+        a.nzl = c->g.L[2] / 8;
+        a.tch = tw_chunk(t.remap);
+        const long long grid = (long long)c->g.L[2] * a.tpp * a.G * (c->g.L[3] / a.tch) + a.fin_blocks;
+        if (grid > 0x7fffffffLL) return set_error(WD_ERR_ARG, "grid too large");
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (c->timing) WD_TRY(timing_begin(c, &e0, &e1));
+        hipError_t e = dslash_tw_launch(a, sw.sp, sw.lk, nr, sw.dag, sw.epi, t.block, (int)grid, c->stream);
+        if (e != hipSuccess)
+            return set_error(WD_ERR_HIP, "t-walking stencil launch (sp %d lk %d nr %d epi %d block %d): %s", sw.sp,
+                             sw.lk, nr, sw.epi, t.block, hipGetErrorString(e));
+        if (c->timing) timing_end(c, sw, e1, 2, nr, rl);
+        return WD_OK;
+    }
     if (is_lds_order(t.remap)) {
         if (!lds_order_ok(c, sw.sp, sw.lk, nr, t.remap) || rl != 1 || t.block != 256 || t.occ != 0)
             return set_error(WD_ERR_ARG, "LDS-staged order %d does not apply here (sp %d lk %d nr %d rl %d block %d "
@@ -214,7 +234,7 @@ wd_status run_sweep(wd_ctx *c, const Sweep &sw, const TuneCfg *cfg)
         if (e != hipSuccess)
             return set_error(WD_ERR_HIP, "LDS stencil launch (sp %d lk %d nr %d epi %d, %u bytes LDS): %s", sw.sp,
                              sw.lk, nr, sw.epi, a.lds, hipGetErrorString(e));
-        if (c->timing) timing_end(c, sw, e1, true, nr, rl);
+        if (c->timing) timing_end(c, sw, e1, 1, nr, rl);
         return WD_OK;
     }
     if (t.remap >= kTileOrders || t.remap < 0) return set_error(WD_ERR_ARG, "tile order %d unknown", t.remap);
@@ -234,7 +254,7 @@ wd_status run_sweep(wd_ctx *c, const Sweep &sw, const TuneCfg *cfg)
     if (e != hipSuccess)
         return set_error(WD_ERR_HIP, "stencil launch (sp %d lk %d nr %d rl %d epi %d block %d): %s",
                          sw.sp, sw.lk, nr, rl, sw.epi, t.block, hipGetErrorString(e));
-    if (c->timing) timing_end(c, sw, e1, false, nr, rl);
+    if (c->timing) timing_end(c, sw, e1, 0, nr, rl);
     return WD_OK;
 }
 
@@ -249,6 +269,14 @@ bool lds_order_ok(const wd_ctx *c, int sp, int lk, int nr, int remap)
     const int S = c->g.Lxh * c->g.L[1];
     return S % 64 == 0 && S <= 512 && c->g.L[2] % 8 == 0 && c->g.L[3] % lds_chunk(remap) == 0 &&
            (long long)lds_order_bytes(c, sp, nr) <= (long long)c->lds_max;
+}
+
+bool tw_order_ok(const wd_ctx *c, int sp, int lk, int nr, int rl, int block, int remap)
+{
+    if (!is_tw_order(remap) || !dslash_tw_supported(sp, lk, nr) || rl != 1) return false;
+    const int S = c->g.Lxh * c->g.L[1];
+    return (block == 64 || block == 128 || block == 256) && S % block == 0 && c->g.L[2] % 8 == 0 &&
+           c->g.L[3] % tw_chunk(remap) == 0;
 }
 
 bool slab_order_ok(const Geom &g, int spb, int remap)
@@ -524,8 +552,10 @@ wd_status wd_dslash_shaped(wd_ctx *c, double *out, const double *in, int nrhs, i
         t.remap = shape[3];
         t.occ = shape[4];
     }
-    const bool lds_ok = is_lds_order(t.remap) && lds_order_ok(c, sp, lk, t.nr, t.remap) && t.rl == 1 &&
-                        t.block == 256 && t.occ == 0;
+    const bool lds_ok = (is_lds_order(t.remap) && lds_order_ok(c, sp, lk, t.nr, t.remap) && t.rl == 1 &&
+                         t.block == 256 && t.occ == 0) ||
+                        (is_tw_order(t.remap) && tw_order_ok(c, sp, lk, t.nr, t.rl, t.block, t.remap) &&
+                         (t.occ == 0 || (t.occ >= 2 && t.occ <= kMaxOcc)));
     if (!lds_ok && (!dslash_shape_supported(sp, lk, t.nr, t.rl) || t.block < 64 || t.block > 256 || (t.block & 63) ||
                     t.remap < 0 || t.remap >= kTileOrders || (t.occ != 0 && (t.occ < 2 || t.occ > kMaxOcc)) ||
                     (t.remap >= 2 && !slab_order_ok(c->g, t.block / t.rl, t.remap))))

@@ -17,6 +17,22 @@ hipError_t dslash_lds_launch_f16_d1(const DslashArgs &a, int lk, int nr, int epi
 hipError_t dslash_lds_launch_f32_d0(const DslashArgs &a, int lk, int nr, int epi, int grid, unsigned lds_bytes, hipStream_t s);
 hipError_t dslash_lds_launch_f32_d1(const DslashArgs &a, int lk, int nr, int epi, int grid, unsigned lds_bytes, hipStream_t s);
 
+hipError_t dslash_tw_launch_f16_d0(const DslashArgs &a, int lk, int nr, int epi, int block, int grid, hipStream_t s);
+hipError_t dslash_tw_launch_f16_d1(const DslashArgs &a, int lk, int nr, int epi, int block, int grid, hipStream_t s);
+
+hipError_t dslash_tw_launch(const DslashArgs &a, int sp, int lk, int nr, int dag, int epi, int block, int grid,
+                            hipStream_t s)
+{
+    if (sp == SP_F16) return dag ? dslash_tw_launch_f16_d1(a, lk, nr, epi, block, grid, s)
+                         : dslash_tw_launch_f16_d0(a, lk, nr, epi, block, grid, s);
+    return hipErrorInvalidValue;
+}
+
+bool dslash_tw_supported(int sp, int lk, int nr)
+{
+    return sp == SP_F16 && (lk == LK_F32_12 || lk == LK_F16_12) && nr >= 1 && nr <= 3;
+}
+
 hipError_t dslash_lds_launch(const DslashArgs &a, int sp, int lk, int nr, int dag, int epi, int grid,
                              unsigned lds_bytes, hipStream_t s)
 {

@@ -504,8 +504,9 @@ __global__ void __launch_bounds__(256) dslash_kernel(DslashArgs a)
 // those of dslash_kernel, so the results are the same bits.
 //
 // XCD mapping: XCD x = block mod 8 takes the z-planes [x nzl, (x+1) nzl) (Lz
-// divisible by 8); its j-th block is z-plane j mod nzl (fastest), then the t
-// chunk, then the RHS group.
+// divisible by 8); its j-th block is z-plane j mod nzl (fastest), then the
+// RHS group, then the t chunk, so that the groups of one chunk, which read
+// the same links, run on one XCD at the same time.
 
 constexpr int kLdsThreads = 256;
 constexpr int kLdsMaxPlane = 512;
@@ -589,10 +590,10 @@ __global__ void __launch_bounds__(kLdsThreads) dslash_lds_kernel(DslashArgs a)
     const int Lz = a.g.L[2], Lt = a.g.L[3];
     const int S = a.g.Lxh * a.g.L[1];
     const int Tc = a.tpp;  // t planes per work-group
-    const int nzl = a.nzl, ntc = Lt / Tc;
+    const int nzl = a.nzl;
     const int x = bid & 7, jb = bid >> 3;
     const int zl = jb % nzl, rest = jb / nzl;
-    const int tc = rest % ntc, grp = rest / ntc;
+    const int grp = rest % a.G, tc = rest / a.G;
     const int z = x * nzl + zl, t0 = tc * Tc;
 
     int rid[NR];
@@ -659,6 +660,169 @@ __global__ void __launch_bounds__(kLdsThreads) dslash_lds_kernel(DslashArgs a)
     }
 }
 
+// ---------------------------------------------------------------------------
+// The t-walking variant: t neighbours held in registers
+// ---------------------------------------------------------------------------
+// Work-group (tile, z, RHS group, t chunk) computes one tile of B = blockDim
+// consecutive sites of the planes (z, t), t in [t0, t0 + Tc): lane l owns
+// the site column at checkerboard offset o = tile * B + l of each plane.  The
+// t neighbours of output site (x, y, z, t) are the input sites (x, y, z,
+// t +- 1), and since the halving of x does not depend on t their offset in
+// their planes is o as well: the lane loads the input spinors of its column
+// at t + 1 once, uses them for the forward t hop at t and keeps them in
+// registers for the backward t hop at t + 2.  Each input spinor is read from
+// memory once for the t hops of a work-group (plus the plane before and the
+// plane after the chunk), so the t neighbours, a whole slab of the lattice
+// away in memory, need not survive in L2 until the next t plane is swept.
+// The x, y and z neighbours come from global memory, where the lanes and
+// work-groups of the same and the adjacent planes have just loaded them.
+// The arithmetic, its order and the epilogue are those of dslash_kernel, so
+// the results are the same bits.
+//
+// XCD mapping: XCD x = block mod 8 takes the z-planes [x nzl, (x+1) nzl) (Lz
+// divisible by 8); its j-th block is tile j mod tpp (fastest), then the z
+// plane, then the RHS group, then the t chunk, so the work-groups of one t
+// chunk that share links (RHS groups) and neighbours (tiles, z-planes) run
+// on one XCD at the same time.
+
+// The input spinors of a lane's column in one t plane, as stored (FP16 and
+// the per-site norm), for the NR RHS of its group.
+template <int NR>
+struct ColF16 {
+    half8_t ch[NR][3];
+    float nrm[NR];
+};
+
+template <int NR>
+__device__ __forceinline__ void col_load_f16(const DslashArgs &a, const int rid[NR], int j, ColF16<NR> &C)
+{
+    const int cs = a.g.cs;
+#pragma unroll
+    for (int r = 0; r < NR; r++) {
+        const char *f = a.in + rid[r] * a.in_rs;
+        const uint32_t off = pin_v((uint32_t)j * 16u);
+#pragma unroll
+        for (int k = 0; k < 3; k++) C.ch[r][k] = ld_off<half8_t, true>(f + (size_t)k * cs * 16, off);
+        C.nrm[r] = ld_off<float, true>(f + (size_t)48 * cs, pin_v((uint32_t)j * 4u));
+    }
+}
+
+// Neighbour source of the t-walking kernel: t neighbours from the column
+// registers (bwd: plane t - 1, fwd: plane t + 1), the others from global
+// memory.
+template <int NR>
+struct TwNb {
+    const ColF16<NR> &bwd;
+    const ColF16<NR> &fwd;
+
+    template <int MU, int DIR>
+    __device__ __forceinline__ float half(const DslashArgs &a, int rid, int r, int j, _Float16 v[24]) const
+    {
+        if constexpr (MU == 3) {
+            const ColF16<NR> &C = DIR > 0 ? fwd : bwd;
+#pragma unroll
+            for (int k = 0; k < 3; k++)
+#pragma unroll
+                for (int e = 0; e < 8; e++) v[8 * k + e] = C.ch[r][k][e];
+            return C.nrm[r];
+        } else {
+            return GlobalNb<true>{}.template half<MU, DIR>(a, rid, r, j, v);
+        }
+    }
+    template <int MU, int DIR>
+    __device__ __forceinline__ float h2(const DslashArgs &a, int rid, int r, int j, h2_t v[12]) const
+    {
+        if constexpr (MU == 3) {
+            const ColF16<NR> &C = DIR > 0 ? fwd : bwd;
+#pragma unroll
+            for (int k = 0; k < 3; k++)
+#pragma unroll
+                for (int e = 0; e < 4; e++) v[4 * k + e] = h2_t{C.ch[r][k][2 * e], C.ch[r][k][2 * e + 1]};
+            return C.nrm[r];
+        } else {
+            return GlobalNb<true>{}.template h2<MU, DIR>(a, rid, r, j, v);
+        }
+    }
+};
+
+template <int SP, int LK, int NR, bool DAG, int EPI>
+__global__ void __launch_bounds__(256) dslash_tw_kernel(DslashArgs a)
+{
+    static_assert(SP == SP_F16, "t-walking stencil: FP16 spinors");
+    if ((int)blockIdx.x < a.fin_blocks) {
+        if (threadIdx.x < 64) {
+            const int rid = a.active[blockIdx.x];
+            const double s = fin_wave_sum(a.fin_partial + (size_t)rid * a.fin_pstride, a.fin_nw, (int)threadIdx.x);
+            if (threadIdx.x == 0) fin_alpha_update(s, rid, a.fin_rr, a.fin_alpha, a.fin_out);
+        }
+        return;
+    }
+    const int bid = (int)blockIdx.x - a.fin_blocks;
+    const int Lz = a.g.L[2], Lt = a.g.L[3];
+    const int S = a.g.Lxh * a.g.L[1];
+    const int Tc = a.tch;
+    const int x = bid & 7, jb = bid >> 3;
+    const int q = jb % a.tpp, r1 = jb / a.tpp;
+    const int zl = r1 % a.nzl, r2 = r1 / a.nzl;
+    const int grp = r2 % a.G, tc = r2 / a.G;
+    const int z = x * a.nzl + zl, t0 = tc * Tc;
+    const int o = q * (int)blockDim.x + (int)threadIdx.x;  // < S: whole tiles per plane
+
+    int rid[NR];
+    bool rv[NR];
+#pragma unroll
+    for (int r = 0; r < NR; r++) {
+        const int slot = grp * NR + r;
+        rv[r] = slot < a.nact;
+        rid[r] = __builtin_amdgcn_readfirstlane(rv[r] ? a.active[slot] : 0);
+    }
+    // first checkerboard index of plane (z, t), 0 <= t < Lt
+    auto pbase = [&](int t) { return S * (z + Lz * t); };
+    ColF16<NR> P0, P1, P2;  // the column at t - 1, t, t + 1
+    col_load_f16<NR>(a, rid, pbase(t0 == 0 ? Lt - 1 : t0 - 1) + o, P0);
+    col_load_f16<NR>(a, rid, pbase(t0) + o, P1);
+#pragma unroll 1
+    for (int tr = 0; tr < Tc; tr++) {
+        // The field bases and strides pass through an empty asm each plane,
+        // so that the scalar addresses derived from them (one per chunk
+        // array, RHS and link direction) are formed where they are used and
+        // not all hoisted out of the loop, where they would not fit the
+        // scalar registers (the compiler would spill them to vector lanes).
+        DslashArgs b = a;
+        asm volatile("" : "+s"(b.in), "+s"(b.in_rs), "+s"(b.links), "+s"(b.g.cs), "+s"(b.out), "+s"(b.out_rs),
+                     "+s"(b.x), "+s"(b.x_rs), "+s"(b.r), "+s"(b.r_rs));
+        const int t = t0 + tr;
+        // (the site indexes, too: otherwise every address derived from them
+        // becomes an induction variable held in vector registers)
+        int jn = pbase(t + 1 == Lt ? 0 : t + 1) + o, i = pbase(t) + o;
+        asm volatile("" : "+v"(jn), "+v"(i));
+        col_load_f16<NR>(b, rid, jn, P2);
+        typedef float real;
+        real acc[NR][24];
+#pragma unroll
+        for (int r = 0; r < NR; r++)
+#pragma unroll
+            for (int e = 0; e < 24; e++) acc[r][e] = 0;
+        // (every site is live; the test keeps the hops in a region of their
+        // own, as in dslash_kernel, which the compiler schedules with far
+        // fewer registers than the same code without it)
+        const bool live = i < b.g.Vh;
+        if (live) {
+            int c[4];
+            site_coords(b.g, i, b.P, c);
+            const GlobalNb<true> gnb;
+            hop_dir<0, SP, LK, NR, DAG>(b, gnb, i, c, rid, acc);
+            hop_dir<1, SP, LK, NR, DAG>(b, gnb, i, c, rid, acc);
+            hop_dir<2, SP, LK, NR, DAG>(b, gnb, i, c, rid, acc);
+            const TwNb<NR> tnb{P0, P2};
+            hop_dir<3, SP, LK, NR, DAG>(b, tnb, i, c, rid, acc);
+        }
+        dslash_epilogue<SP, NR, 1, EPI>(b, i, live, rid, rv, acc);
+        P0 = P1;
+        P1 = P2;
+    }
+}
+
 // Runtime -> template dispatch over the epilogue for one instance.
 #define WD_DSL_EPI(SP_, LK_, NR_, RL_, DAG_)                                                \
     switch (epi) {                                                                                \
@@ -711,6 +875,29 @@ __global__ void __launch_bounds__(kLdsThreads) dslash_lds_kernel(DslashArgs a)
     case EPI_XPAY: WD_DSL_LDS_ONE(SP_, LK_, NR_, DAG_, EPI_XPAY)                                   \
     case EPI_CGUPD: WD_DSL_LDS_ONE(SP_, LK_, NR_, DAG_, EPI_CGUPD)                                 \
     default: return hipErrorInvalidValue;                                                         \
+    }
+
+#define WD_DSL_TW_EPI(SP_, LK_, NR_, DAG_)                                                         \
+    switch (epi) {                                                                                \
+    case EPI_PLAIN:                                                                               \
+        hipLaunchKernelGGL((dslash_tw_kernel<SP_, LK_, NR_, DAG_, EPI_PLAIN>), dim3(grid), dim3(block), \
+                           a.lds, s, a);                                                          \
+        return hipGetLastError();                                                                 \
+    case EPI_XPAY:                                                                                \
+        hipLaunchKernelGGL((dslash_tw_kernel<SP_, LK_, NR_, DAG_, EPI_XPAY>), dim3(grid), dim3(block),  \
+                           a.lds, s, a);                                                          \
+        return hipGetLastError();                                                                 \
+    case EPI_CGUPD:                                                                               \
+        hipLaunchKernelGGL((dslash_tw_kernel<SP_, LK_, NR_, DAG_, EPI_CGUPD>), dim3(grid), dim3(block), \
+                           a.lds, s, a);                                                          \
+        return hipGetLastError();                                                                 \
+    default:                                                                                      \
+        return hipErrorInvalidValue;                                                              \
+    }
+
+#define WD_DSL_TW_SHAPE(SP_, LK_, NR_, DAG_)                                                       \
+    if (nr == NR_) {                                                                              \
+        WD_DSL_TW_EPI(SP_, LK_, NR_, DAG_)                                                        \
     }
 
 #define WD_DSL_LDS_SHAPE(SP_, LK_, NR_, DAG_)                                                      \

@@ -277,6 +277,23 @@ extern "C" wd_status wd_tune(wd_ctx *c, int nrhs, int prec, char *report, size_t
             q.remap = rm;
             cands.push_back(q);
         }
+    // the t-walking kernel with the t neighbours in registers: one lane per
+    // site, tiles of the largest of 256, 128, 64 sites that divides a plane,
+    // 1 to 3 RHS per lane, 4, 8 or 16 t-planes per work-group
+    {
+        const int S = c->g.Lxh * c->g.L[1];
+        const int tb = S % 256 == 0 ? 256 : (S % 128 == 0 ? 128 : 64);
+        for (int nr = 1; nr <= 3; nr++)
+            for (int rm = kTwOrder0; rm < kTwOrder0 + kTwOrders; rm++) {
+                if (!tw_order_ok(c, sp, lk, nr, 1, tb, rm) || (nr > 2 * nrhs && nr != 1)) continue;
+                TuneCfg q;
+                q.block = tb;
+                q.nr = nr;
+                q.rl = 1;
+                q.remap = rm;
+                cands.push_back(q);
+            }
+    }
 
     // (the solver's D_oe^dag sweep also finalizes alpha in extra work-groups:
     // timed here with them, on the partials and scalars of tn_fin)
@@ -406,7 +423,10 @@ extern "C" wd_status wd_tune(wd_ctx *c, int nrhs, int prec, char *report, size_t
                 dslash_shape_supported(sp, lk, cc.nr, cc.rl) && (cc.occ == 0 || (cc.occ >= 2 && cc.occ <= kMaxOcc)) &&
                 (is_lds_order(cc.remap)
                      ? (lds_order_ok(c, sp, lk, cc.nr, cc.remap) && cc.rl == 1 && cc.block == 256 && cc.occ == 0)
-                     : (cc.remap < 2 || slab_order_ok(c->g, cc.block / cc.rl, cc.remap)))) {
+                 : is_tw_order(cc.remap)
+                     ? tw_order_ok(c, sp, lk, cc.nr, cc.rl, cc.block, cc.remap)
+                     : (cc.remap >= 0 && cc.remap < kTileOrders &&
+                        (cc.remap < 2 || slab_order_ok(c->g, cc.block / cc.rl, cc.remap))))) {
                 std::vector<TuneCfg> vl = {cands[0], cc};
                 std::vector<char> ok;
                 std::vector<double> us;

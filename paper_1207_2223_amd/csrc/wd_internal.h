@@ -66,6 +66,7 @@ struct DslashArgs {
     int tpp;               // remap >= 2: tiles per (z, t) plane
     int nzl;               // remap 2-4: z planes per XCD; 5-6: t planes per XCD
     int nys;               // remap >= 2: stripes per plane (1, 2, 4 for remap 2, 3, 4)
+    int tch;               // t-walking orders: t planes per work-group
     double *partial;       // partial[rid*pstride + pw_off + site/16] = sum |out|^2 (or |r|^2)
     int pstride;
     int pw_off;
@@ -110,6 +111,12 @@ bool dslash_shape_supported(int sp, int lk, int nr, int rl);
 hipError_t dslash_lds_launch(const DslashArgs &a, int sp, int lk, int nr, int dag, int epi, int grid,
                              unsigned lds_bytes, hipStream_t s);
 bool dslash_lds_supported(int sp, int lk, int nr);
+// The t-walking stencil with the t neighbours in registers (tile orders
+// kTwOrder0 and up: work-groups of `block` threads, one lane per site of a
+// block-site tile of one (z, t) plane, walking tw_chunk(order) t-planes).
+hipError_t dslash_tw_launch(const DslashArgs &a, int sp, int lk, int nr, int dag, int epi, int block, int grid,
+                            hipStream_t s);
+bool dslash_tw_supported(int sp, int lk, int nr);
 
 // BLAS-1 / reductions (blas.hip).  All take an active-RHS list.
 enum { FIN_STORE = 0, FIN_ALPHA = 1, FIN_BETA = 2, FIN_RR = 3 };
@@ -263,6 +270,16 @@ inline int lds_chunk(int remap) { return 4 << (remap - kLdsOrder0); }
 inline bool is_lds_order(int remap) { return remap >= kLdsOrder0 && remap < kLdsOrder0 + kLdsOrders; }
 bool lds_order_ok(const wd_ctx *c, int sp, int lk, int nr, int remap);
 unsigned lds_order_bytes(const wd_ctx *c, int sp, int nr);
+// Tile orders kTwOrder0 .. kTwOrder0 + kTwOrders - 1: the t-walking kernel
+// with the t neighbours held in registers, tw_chunk(order) t-planes per
+// work-group.  It applies to FP16 spinors when a plane of one parity holds a
+// whole number of block-site tiles, Lz is a multiple of 8 and Lt of the
+// chunk; one lane per site (rl = 1); a cap on work-groups per CU is allowed.
+constexpr int kTwOrder0 = kLdsOrder0 + kLdsOrders;
+constexpr int kTwOrders = 3;
+inline int tw_chunk(int remap) { return 4 << (remap - kTwOrder0); }
+inline bool is_tw_order(int remap) { return remap >= kTwOrder0 && remap < kTwOrder0 + kTwOrders; }
+bool tw_order_ok(const wd_ctx *c, int sp, int lk, int nr, int rl, int block, int remap);
 inline int remap_stripes(int remap) { return remap <= 2 || remap >= 5 ? 1 : (remap == 3 ? 2 : 4); }
 inline int remap_slab_dim(int remap) { return (remap == 5 || remap == 6) ? 3 : 2; }
 const TuneCfg *tuned_cfg(const wd_ctx *c, const Sweep &sw);

@@ -51,15 +51,41 @@ def lds_candidates(dims, code, nrhs):
     return out
 
 
+def tw_candidates(dims, code, nrhs, blocks=None):
+    """The t-walking shapes (tile orders 11, 12, 13: 4, 8, 16 t-planes per
+    work-group, the t neighbours held in registers; one lane per site, 1 to 3
+    RHS per lane): FP16 spinors with FP32 or FP16 12-real links, where a plane
+    of one parity holds whole tiles of the block's sites, Lz % 8 == 0 and Lt
+    is divisible by the chunk.  The tuner tries the largest block of 256,
+    128, 64 that divides a plane; `blocks` lists others to include."""
+    base, links = code & 0xF, code & 0x30
+    if base != 2 or links not in (0, 0x10):
+        return []
+    S = dims[0] // 2 * dims[1]
+    tb = 256 if S % 256 == 0 else (128 if S % 128 == 0 else 64)
+    out = []
+    for b in (blocks or (tb,)):
+        if S % b != 0 or dims[2] % 8 != 0:
+            continue
+        for nr in (1, 2, 3):
+            if nr > 2 * nrhs and nr != 1:
+                continue
+            for rm, tc in ((11, 4), (12, 8), (13, 16)):
+                if dims[3] % tc == 0:
+                    out.append((b, nr, 1, rm, 0))
+    return out
+
+
 def _expected_candidates(dims, code, nrhs):
     """The tuner's candidate count: block {64,128,256} x RHS per lane x lanes
     per site x tile order {plain, XCD round-robin, z-slab with 1, 2, 4
     y-stripes, t-slab walked t-fastest in two orders, z-slab with the RHS
     groups outermost}, where the z-slab orders need Lz % 8 == 0, the t-slab
     orders Lt % 8 == 0, and all a whole number of tiles per plane and per
-    stripe; the LDS-staged shapes where they apply; then the best of these
-    with a cap of 2..8 work-groups per CU (7 more, unless the best is an
-    LDS-staged shape, which takes no cap: then the count is 7 less)."""
+    stripe; the LDS-staged and t-walking shapes where they apply; then the
+    best of these with a cap of 2..8 work-groups per CU (7 more, unless the
+    best is an LDS-staged shape, which takes no cap: then the count is 7
+    less)."""
     f64 = (code & 0xF) == 0
     shapes = [(1, 1), (2, 1), (1, 2), (2, 2), (1, 4), (2, 4)] if f64 else \
         [(nr, rl) for rl in (1, 2, 4) for nr in (1, 2, 3, 4)]
@@ -75,7 +101,7 @@ def _expected_candidates(dims, code, nrhs):
                 if rm >= 2 and not (slab % 8 == 0 and plane % spb == 0 and (plane // spb) % ns == 0):
                     continue
                 n += 1
-    return n + len(lds_candidates(dims, code, nrhs)) + 7
+    return n + len(lds_candidates(dims, code, nrhs)) + len(tw_candidates(dims, code, nrhs)) + 7
 
 
 @pytest.mark.parametrize("prec", ["F64", "F32", "F16", "F16L", "F16R", "I16"])
@@ -96,7 +122,7 @@ def test_tuner_all_shapes_bitwise_and_tuned_solve_identical(wd, oracle, prec, di
     nrhs = 5
     rows = wd.wd_tune(lat.ctx, nrhs, code)
     for r in rows:
-        want = _expected_candidates(dims, code, nrhs) - (7 if r["remap"] >= 8 else 0)
+        want = _expected_candidates(dims, code, nrhs) - (7 if 8 <= r["remap"] <= 10 else 0)
         assert r["candidates"] == want, (r, want)
     for r in rows:
         note(f"{prec} {r['sweep']}: block {r['block']} nr {r['nr']} rl {r['rl']} remap {r['remap']} "
