@@ -619,6 +619,12 @@ def bench_serving(args, wd, torch):
         summ["all_converged"] = all(s["status"] == wd.WD_OK for s in st)
         summ["max_true_resid"] = max(s["true_resid"] for s in st)
         summ["fp64_escalated_rhs"] = sum(1 for s in st if 0 < s["iters_fp64"] < s["iters"])
+        bad = [{"lattice": r.lattice, "kappa": float(k), "status": s["status"], "iters": s["iters"],
+                "true_resid": s["true_resid"]} for r in reqs for k, s in zip(r.kappa, r.stats)
+               if s["status"] != wd.WD_OK]
+        summ["not_converged"] = {"count": len(bad), "first": bad[:16]}
+        for b in bad[:16]:
+            log(f"[bench] not converged: {b}")
         return summ, merge_reports(reps)
 
     prec = PRECS[args.prec]
@@ -660,7 +666,8 @@ def bench_serving(args, wd, torch):
         for e in ex64.values():
             e.close()
         fp64 = {"solves_per_s": summ["solves_per_s"], "latency_p50_ms": summ["latency_p50_s"] * 1e3,
-                "latency_p99_ms": summ["latency_p99_s"] * 1e3, "all_converged": summ["all_converged"]}
+                "latency_p99_ms": summ["latency_p99_s"] * 1e3, "all_converged": summ["all_converged"],
+                "not_converged": summ["not_converged"]}
         log(f"[bench] fp64 saturation pass: {summ['solves_per_s']:.1f} solves/s")
 
     cpu = None
@@ -696,7 +703,8 @@ def bench_serving(args, wd, torch):
         "saturation": {"solves_per_s": value, "requests_per_s": req_rate,
                        "latency_p50_ms": sat[0]["latency_p50_s"] * 1e3,
                        "latency_p99_ms": sat[0]["latency_p99_s"] * 1e3, "peak_bytes": sat[0]["peak_bytes"],
-                       "fp64_escalated_rhs": sat[0]["fp64_escalated_rhs"], "steps": sat[0]["steps"]},
+                       "fp64_escalated_rhs": sat[0]["fp64_escalated_rhs"], "steps": sat[0]["steps"],
+                       "not_converged": sat[0]["not_converged"]},
         "load_sweep": sweep,
         "stencil": sten,
         "dominant_kernel": dom,

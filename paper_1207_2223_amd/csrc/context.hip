@@ -769,10 +769,10 @@ size_t wd_bytes_required(const int32_t dims[4], int nrhs, const wd_solver_params
     const int sp = p->prec_sloppy & 0xf;
     const size_t nsub = p->eo ? 1 : 2;
     // FP64: b, x, r, p, Ap, a full-size temporary and a one-parity temporary;
-    // even-odd: the ring of search directions of the lane that iterates
-    // (FP64, or the sloppy one)
-    const size_t ring = p->eo ? (size_t)(kMaxRing - 1) : 0;
-    size_t f64 = (6 * nsub + 1 + (sp == WD_F64 ? ring : 0)) * 192 * Vh;
+    // a mixed even-odd solve also holds the ring of sloppy search directions
+    // (an FP64 solve advances its solution every iteration)
+    const size_t ring = (p->eo && sp != WD_F64) ? (size_t)(kMaxRing - 1) : 0;
+    size_t f64 = (6 * nsub + 1) * 192 * Vh;
     size_t sl = 0;
     if (sp != WD_F64)
         sl = (4 + ring) * spinor_site_bytes(sp == WD_F32 ? SP_F32 : SP_F16) * Vh * nsub + 96 * Vh * nsub;

@@ -16,7 +16,8 @@
 // alpha and beta never leave the device; the host reads the residual norms
 // after every step of k iterations.  The solution is not touched by the
 // iteration itself: each iteration's p goes to its own slot of a ring of
-// kRing directions (and alpha to a matching history), and every kRing
+// kRing directions (and alpha to a matching history; in a mixed solve -- an
+// FP64 solve keeps a ring of one), and every kRing
 // iterations, and at the end of each step, the p update first adds
 // alpha_j p_j of the iterations since the last flush to x, in iteration
 // order -- the same roundings as x += alpha p once per iteration, with the
@@ -185,13 +186,14 @@ struct BatchSolver {
             WD_TRY(alloc_field(c, nm("xs"), xp, 1, cap, &xs));
             lane_s = Lane{sp, lk, xp, ps, rs, t2s, tos, xs, true, {ps}};
         }
-        // the ring slots 1 .. kRing-1 of the lane that carries the iteration
-        Lane &L = mixed ? lane_s : lane_d;
-        if (p.eo)
+        // the ring slots 1 .. kRing-1 of the sloppy lane; an FP64 solve keeps
+        // a ring of one (x advanced every iteration), which holds its memory
+        // per RHS at seven FP64 vectors for serving
+        if (p.eo && mixed)
             for (int j = 1; j < kRing; j++) {
                 Field f;
-                WD_TRY(alloc_field(c, ring_name(j), L.sp, 1, cap, &f));
-                L.Pr.push_back(f);
+                WD_TRY(alloc_field(c, ring_name(j), lane_s.sp, 1, cap, &f));
+                lane_s.Pr.push_back(f);
             }
         if (!mixed) lane_s = lane_d;
         if (hbuf) (void)hipHostFree(hbuf);
