@@ -313,10 +313,10 @@ def bench_solve(args, wd, torch):
         t = time.time()
         for code in {PRECS[args.prec], 0}:
             for row in wd.wd_tune(lat.ctx, nrhs, code):
-                tune_rows.append({k: row[k] for k in ("sweep", "sp", "block", "nr", "rl", "remap", "occ", "us",
+                tune_rows.append({k: row[k] for k in ("sweep", "sp", "block", "nr", "rl", "remap", "occ", "lnt", "us",
                                                       "candidates", "rejected", "source")})
                 log(f"[bench] tuned {code:#x} {row['sweep']}: block {row['block']} nr {row['nr']} "
-                    f"rl {row['rl']} remap {row['remap']} occ {row['occ']} {row['us']:.1f} us "
+                    f"rl {row['rl']} remap {row['remap']} occ {row['occ']} lnt {row['lnt']} {row['us']:.1f} us "
                     f"({row['source']}, {row['candidates']} candidates, {row['rejected']} rejected)")
         log(f"[bench] autotune {time.time() - t:.1f}s")
     if args.tune_only:

@@ -139,7 +139,7 @@ static wd_status timing_begin(wd_ctx *c, hipEvent_t *e0, hipEvent_t *e1)
 }
 
 // kind: 0 dslash_kernel, 1 dslash_lds_kernel, 2 dslash_tw_kernel
-static void timing_end(wd_ctx *c, const Sweep &sw, hipEvent_t e1, int kind, int nr, int rl)
+static void timing_end(wd_ctx *c, const Sweep &sw, hipEvent_t e1, int kind, int nr, int rl, int lk)
 {
     (void)hipEventRecord(e1, c->stream);
     const double b = sweep_bytes(c, sw);
@@ -149,7 +149,7 @@ static void timing_end(wd_ctx *c, const Sweep &sw, hipEvent_t e1, int kind, int 
         snprintf(name, sizeof(name), "dslash_%s_kernel<%d, %d, %d, %s, %d>", kind == 1 ? "lds" : "tw", sw.sp,
                  sw.lk, nr, sw.dag ? "true" : "false", sw.epi);
     else
-        snprintf(name, sizeof(name), "dslash_kernel<%d, %d, %d, %d, %s, %d>", sw.sp, sw.lk, nr, rl,
+        snprintf(name, sizeof(name), "dslash_kernel<%d, %d, %d, %d, %s, %d>", sw.sp, lk, nr, rl,
                  sw.dag ? "true" : "false", sw.epi);
     if (c->ev_info.size() < c->ev_used) c->ev_info.resize(c->ev_used);
     c->ev_info[c->ev_used - 1] = std::make_tuple(std::string(name), b, (double)c->Vh * sw.nact);
@@ -164,6 +164,10 @@ wd_status run_sweep(wd_ctx *c, const Sweep &sw, const TuneCfg *cfg)
     TuneCfg t = cfg ? *cfg : default_cfg(sw.sp);
     if (!dslash_shape_supported(sw.sp, sw.lk, t.nr, t.rl) || t.block < 64 || t.block > 256 || (t.block & 63))
         return set_error(WD_ERR_ARG, "unsupported launch shape block %d nr %d rl %d", t.block, t.nr, t.rl);
+    if (t.lnt != 0 && (t.lnt != 1 || !lnt_ok(sw.sp, sw.lk, t)))
+        return set_error(WD_ERR_ARG, "non-temporal links need FP32 12-real links, the register-tiled kernel, 1 lane "
+                         "per site and 1 or 2 RHS per lane (block %d nr %d rl %d order %d)", t.block, t.nr, t.rl,
+                         t.remap);
     const int nr = t.nr, rl = t.rl;
     DslashArgs a;
     a.g = c->g;
@@ -217,7 +221,7 @@ wd_status run_sweep(wd_ctx *c, const Sweep &sw, const TuneCfg *cfg)
         if (e != hipSuccess)
             return set_error(WD_ERR_HIP, "t-walking stencil launch (sp %d lk %d nr %d epi %d block %d): %s", sw.sp,
                              sw.lk, nr, sw.epi, t.block, hipGetErrorString(e));
-        if (c->timing) timing_end(c, sw, e1, 2, nr, rl);
+        if (c->timing) timing_end(c, sw, e1, 2, nr, rl, sw.lk);
         return WD_OK;
     }
     if (is_lds_order(t.remap)) {
@@ -234,7 +238,7 @@ wd_status run_sweep(wd_ctx *c, const Sweep &sw, const TuneCfg *cfg)
         if (e != hipSuccess)
             return set_error(WD_ERR_HIP, "LDS stencil launch (sp %d lk %d nr %d epi %d, %u bytes LDS): %s", sw.sp,
                              sw.lk, nr, sw.epi, a.lds, hipGetErrorString(e));
-        if (c->timing) timing_end(c, sw, e1, 1, nr, rl);
+        if (c->timing) timing_end(c, sw, e1, 1, nr, rl, sw.lk);
         return WD_OK;
     }
     if (t.remap >= kTileOrders || t.remap < 0) return set_error(WD_ERR_ARG, "tile order %d unknown", t.remap);
@@ -250,11 +254,13 @@ wd_status run_sweep(wd_ctx *c, const Sweep &sw, const TuneCfg *cfg)
     if (grid > 0x7fffffffLL) return set_error(WD_ERR_ARG, "grid too large");
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (c->timing) WD_TRY(timing_begin(c, &e0, &e1));
-    hipError_t e = dslash_launch(a, sw.sp, sw.lk, nr, rl, sw.dag, sw.epi, t.block, (int)grid, c->stream);
+    // (non-temporal links: the same packed field, read by the LK_F32_12N instance)
+    const int lk_run = t.lnt ? LK_F32_12N : sw.lk;
+    hipError_t e = dslash_launch(a, sw.sp, lk_run, nr, rl, sw.dag, sw.epi, t.block, (int)grid, c->stream);
     if (e != hipSuccess)
         return set_error(WD_ERR_HIP, "stencil launch (sp %d lk %d nr %d rl %d epi %d block %d): %s",
-                         sw.sp, sw.lk, nr, rl, sw.epi, t.block, hipGetErrorString(e));
-    if (c->timing) timing_end(c, sw, e1, 0, nr, rl);
+                         sw.sp, lk_run, nr, rl, sw.epi, t.block, hipGetErrorString(e));
+    if (c->timing) timing_end(c, sw, e1, 0, nr, rl, lk_run);
     return WD_OK;
 }
 
@@ -269,6 +275,12 @@ bool lds_order_ok(const wd_ctx *c, int sp, int lk, int nr, int remap)
     const int S = c->g.Lxh * c->g.L[1];
     return S % 64 == 0 && S <= 512 && c->g.L[2] % 8 == 0 && c->g.L[3] % lds_chunk(remap) == 0 &&
            (long long)lds_order_bytes(c, sp, nr) <= (long long)c->lds_max;
+}
+
+bool lnt_ok(int sp, int lk, const TuneCfg &t)
+{
+    return lk == LK_F32_12 && (sp == SP_F16 || sp == SP_F32) && t.rl == 1 && (t.nr == 1 || t.nr == 2) &&
+           t.remap >= 0 && t.remap < kTileOrders;
 }
 
 bool tw_order_ok(const wd_ctx *c, int sp, int lk, int nr, int rl, int block, int remap)

@@ -171,8 +171,9 @@ static wd_status compare(wd_ctx *c, const char *a, const char *b, size_t bytes, 
 
 // Tuning cache: a text file named by the environment variable
 // WD_TUNE_CACHE, one line per tuned sweep:
-//   Lx Ly Lz Lt nrhs sp lk dag epi block nr rl remap occ us
-// (lines without the occ field, from older files, read as occ = 0)
+//   Lx Ly Lz Lt nrhs sp lk dag epi block nr rl remap occ us [lnt]
+// (lines without the occ field, from older files, read as occ = 0; without
+// the trailing lnt field as lnt = 0)
 static std::string cache_key(const wd_ctx *c, int nrhs, int sp, int lk, int dag, int epi)
 {
     char b[128];
@@ -188,12 +189,16 @@ static bool cache_lookup(const char *path, const std::string &key, TuneCfg *cfg,
     char line[256];
     bool found = false;
     while (fgets(line, sizeof(line), f)) {
-        int d[9], b, nr, rl, rm, oc = 0;
+        int d[9], b, nr, rl, rm, oc = 0, nt = 0;
         double t;
-        double x[2];
-        const int nf = sscanf(line, "%d %d %d %d %d %d %d %d %d %d %d %d %d %lf %lf", &d[0], &d[1], &d[2],
-                              &d[3], &d[4], &d[5], &d[6], &d[7], &d[8], &b, &nr, &rl, &rm, &x[0], &x[1]);
-        if (nf == 15) {
+        double x[3];
+        const int nf = sscanf(line, "%d %d %d %d %d %d %d %d %d %d %d %d %d %lf %lf %lf", &d[0], &d[1], &d[2],
+                              &d[3], &d[4], &d[5], &d[6], &d[7], &d[8], &b, &nr, &rl, &rm, &x[0], &x[1], &x[2]);
+        if (nf == 16) {
+            oc = (int)x[0];
+            t = x[1];
+            nt = (int)x[2];
+        } else if (nf == 15) {
             oc = (int)x[0];
             t = x[1];
         } else if (nf == 14) {
@@ -209,6 +214,7 @@ static bool cache_lookup(const char *path, const std::string &key, TuneCfg *cfg,
             cfg->rl = rl;
             cfg->remap = rm;
             cfg->occ = oc;
+            cfg->lnt = nt;
             *us = t;
             found = true;
         }
@@ -221,7 +227,11 @@ static void cache_store(const char *path, const std::string &key, const TuneCfg 
 {
     FILE *f = fopen(path, "a");
     if (!f) return;
-    fprintf(f, "%s %d %d %d %d %d %.3f\n", key.c_str(), cfg.block, cfg.nr, cfg.rl, cfg.remap, cfg.occ, us);
+    if (cfg.lnt)
+        fprintf(f, "%s %d %d %d %d %d %.3f %d\n", key.c_str(), cfg.block, cfg.nr, cfg.rl, cfg.remap, cfg.occ, us,
+                cfg.lnt);
+    else
+        fprintf(f, "%s %d %d %d %d %d %.3f\n", key.c_str(), cfg.block, cfg.nr, cfg.rl, cfg.remap, cfg.occ, us);
     fclose(f);
 }
 
@@ -338,6 +348,7 @@ extern "C" wd_status wd_tune(wd_ctx *c, int nrhs, int prec, char *report, size_t
             best = 1e30;
             bestc = list[0];
             const size_t nfirst = list.size();
+            bool nt_tried = false;
             for (size_t q = 0;; q++) {
                 if (occ_pass && q == nfirst && best < 1e30 && !is_lds_order(bestc.remap))
                     for (int oc = 2; oc <= kMaxOcc; oc++) {
@@ -345,6 +356,14 @@ extern "C" wd_status wd_tune(wd_ctx *c, int nrhs, int prec, char *report, size_t
                         v.occ = oc;
                         list.push_back(v);
                     }
+                // then the best of all with its links loaded non-temporally
+                if (occ_pass && q == list.size() && q > nfirst && !nt_tried && best < 1e30 &&
+                    lnt_ok(sp, lk, bestc)) {
+                    TuneCfg v = bestc;
+                    v.lnt = 1;
+                    list.push_back(v);
+                    nt_tried = true;
+                }
                 if (q >= list.size()) break;
                 ok.resize(list.size(), 0);
                 us.resize(list.size(), 0.0);
@@ -391,8 +410,8 @@ extern "C" wd_status wd_tune(wd_ctx *c, int nrhs, int prec, char *report, size_t
                 }
                 us[q] = tbest * 1e3;
                 if (verbose)
-                    fprintf(stderr, "[wd tune] %s sp %d lk %d nrhs %d: block %d nr %d rl %d order %d cap %d: %.2f us\n",
-                            k.name, sp, lk, nrhs, cf.block, cf.nr, cf.rl, cf.remap, cf.occ, us[q]);
+                    fprintf(stderr, "[wd tune] %s sp %d lk %d nrhs %d: block %d nr %d rl %d order %d cap %d nt %d: %.2f us\n",
+                            k.name, sp, lk, nrhs, cf.block, cf.nr, cf.rl, cf.remap, cf.occ, cf.lnt, us[q]);
                 if (tbest < best) {
                     best = tbest;
                     bestc = cf;
@@ -408,9 +427,9 @@ extern "C" wd_status wd_tune(wd_ctx *c, int nrhs, int prec, char *report, size_t
         auto report_line = [&](const TuneCfg &b, double us, double gbs, size_t ncand, int nrej, const char *src) {
             char line[320];
             snprintf(line, sizeof(line),
-                     "%s;sp=%d;lk=%d;nrhs=%d;block=%d;nr=%d;rl=%d;remap=%d;occ=%d;us=%.2f;GB/s=%.1f;"
+                     "%s;sp=%d;lk=%d;nrhs=%d;block=%d;nr=%d;rl=%d;remap=%d;occ=%d;lnt=%d;us=%.2f;GB/s=%.1f;"
                      "candidates=%zu;rejected=%d;source=%s\n",
-                     k.name, sp, lk, nrhs, b.block, b.nr, b.rl, b.remap, b.occ, us, gbs, ncand, nrej, src);
+                     k.name, sp, lk, nrhs, b.block, b.nr, b.rl, b.remap, b.occ, b.lnt, us, gbs, ncand, nrej, src);
             rep += line;
         };
 
@@ -421,6 +440,7 @@ extern "C" wd_status wd_tune(wd_ctx *c, int nrhs, int prec, char *report, size_t
             double us_cached = 0;
             if (cache_lookup(cache, cache_key(c, nrhs, sp, lk, k.dag, k.epi), &cc, &us_cached) &&
                 dslash_shape_supported(sp, lk, cc.nr, cc.rl) && (cc.occ == 0 || (cc.occ >= 2 && cc.occ <= kMaxOcc)) &&
+                (cc.lnt == 0 || (cc.lnt == 1 && lnt_ok(sp, lk, cc))) &&
                 (is_lds_order(cc.remap)
                      ? (lds_order_ok(c, sp, lk, cc.nr, cc.remap) && cc.rl == 1 && cc.block == 256 && cc.occ == 0)
                  : is_tw_order(cc.remap)

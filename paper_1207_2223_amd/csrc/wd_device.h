@@ -28,6 +28,9 @@ enum { SP_F64 = 0, SP_F32 = 1, SP_F16 = 2, SP_I16 = 3 };
 // Formats that store a per-site FP32 norm next to 16-bit values.
 __host__ __device__ constexpr bool has_norm(int sp) { return sp == SP_F16 || sp == SP_I16; }
 enum { LK_F64_18 = 0, LK_F64_12 = 1, LK_F32_12 = 2, LK_F16_12 = 3, LK_F32_18 = 4, LK_F32_8 = 5 };
+// LK_F32_12 data read with non-temporal loads (a launch variant of the same
+// packed links, not a storage format of its own).
+enum { LK_F32_12N = 6 };
 
 typedef _Float16 half8_t __attribute__((ext_vector_type(8)));
 
@@ -69,6 +72,18 @@ __device__ __forceinline__ T ld_off(const char *base, uint32_t off)
     gchar *g = (gchar *)base;
     if constexpr (UNI) asm("" : "+s"(g));
     return *(gT *)(g + off);
+}
+
+// The same with a non-temporal hint (the value is the same; the caches are
+// asked not to keep the line).
+template <typename T, bool UNI>
+__device__ __forceinline__ T ld_off_nt(const char *base, uint32_t off)
+{
+    typedef const __attribute__((address_space(1))) char gchar;
+    typedef __attribute__((address_space(1))) T gT;
+    gchar *g = (gchar *)base;
+    if constexpr (UNI) asm("" : "+s"(g));
+    return __builtin_nontemporal_load((gT *)(g + off));
 }
 
 // Exact division by a runtime constant d for 0 <= n < 2^31 by a multiply and
@@ -383,7 +398,8 @@ template <> struct LinkIO<LK_F64_12> {
     }
 };
 
-template <> struct LinkIO<LK_F32_12> {
+template <bool NT>
+struct LinkIOF32x12 {
     typedef float real;
     static constexpr int nchunk = 3;
     static constexpr size_t chunk_bytes = 16;
@@ -393,7 +409,8 @@ template <> struct LinkIO<LK_F32_12> {
         const uint32_t off = (uint32_t)i * 16u;
 #pragma unroll
         for (int k = 0; k < 3; k++) {
-            const flt4_t w = ld_off<flt4_t, true>(p + (size_t)k * cs * 16, off);
+            const flt4_t w = NT ? ld_off_nt<flt4_t, true>(p + (size_t)k * cs * 16, off)
+                                : ld_off<flt4_t, true>(p + (size_t)k * cs * 16, off);
             u[4 * k] = w.x;
             u[4 * k + 1] = w.y;
             u[4 * k + 2] = w.z;
@@ -402,6 +419,11 @@ template <> struct LinkIO<LK_F32_12> {
         reconstruct_row3(u);
     }
 };
+template <> struct LinkIO<LK_F32_12> : LinkIOF32x12<false> {};
+// Each link is read once per sweep and RHS group: with one group (all RHS of
+// a site in one lane) the links are not read again, and loading them
+// non-temporally leaves the L2 to the neighbour spinors.
+template <> struct LinkIO<LK_F32_12N> : LinkIOF32x12<true> {};
 
 template <> struct LinkIO<LK_F16_12> {
     typedef float real;
@@ -540,7 +562,7 @@ __host__ __device__ constexpr size_t link_bytes(int lk)
 {
     return lk == LK_F64_18 ? 144
                            : (lk == LK_F64_12 ? 96
-                                              : (lk == LK_F32_12 ? 48
+                                              : (lk == LK_F32_12 || lk == LK_F32_12N ? 48
                                                                  : (lk == LK_F16_12 ? 24 : (lk == LK_F32_8 ? 32 : 72))));
 }
 

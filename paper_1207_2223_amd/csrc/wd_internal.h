@@ -94,7 +94,10 @@ struct TuneCfg {
     int rl = 1;
     int remap = 1;
     int occ = 0;  // 0, or at most occ work-groups per CU (enforced through dynamic LDS)
+    int lnt = 0;  // 1: FP32 12-real links loaded non-temporally (register-tiled kernel, rl 1, nr 1-2)
 };
+// Whether a shape of a sweep with links lk may take lnt = 1.
+bool lnt_ok(int sp, int lk, const TuneCfg &t);
 
 // LDS per CU on gfx950, and the dynamic LDS per work-group that lets at most
 // occ work-groups share a CU (occ in 2..kMaxOcc; 0 = no cap).

@@ -135,7 +135,7 @@ def test_every_launch_shape_and_tile_order(wd, oracle, dims):
 
 @pytest.mark.parametrize("prec", ["F16", "F64"])
 def test_tuner_rejects_nothing_at_16c32_12rhs(wd, prec):
-    from test_gpu_tune import _expected_candidates
+    from test_gpu_tune import _expected_candidates, nt_extra
     dims = (16, 16, 16, 32)
     code = wd.WD_F16 if prec == "F16" else wd.WD_F64
     U = li.random_su3_field(dims, 0.5, seed=1203)
@@ -144,7 +144,7 @@ def test_tuner_rejects_nothing_at_16c32_12rhs(wd, prec):
     rows = wd.wd_tune(lat.ctx, NRHS, code)
     for r in rows:
         # (the best shape is retried with 7 work-group caps unless it is LDS-staged)
-        want = _expected_candidates(dims, code, NRHS) - (7 if 8 <= r["remap"] <= 10 else 0)
+        want = _expected_candidates(dims, code, NRHS) - (7 if 8 <= r["remap"] <= 10 else 0) + nt_extra(code, r)
         note(f"{prec} {r['sweep']}: block {r['block']} nr {r['nr']} rl {r['rl']} remap {r['remap']} "
              f"occ {r['occ']}; {r['candidates']} candidates, {r['rejected']} rejected")
         assert r["source"] == "timed" and r["candidates"] == want and r["rejected"] == 0

@@ -76,6 +76,14 @@ def tw_candidates(dims, code, nrhs, blocks=None):
     return out
 
 
+def nt_extra(code, row):
+    """1 if the tuner retried the sweep's best shape with its links loaded
+    non-temporally: FP16 or FP32 spinors with FP32 12-real links, the
+    register-tiled kernel (orders 0-7), one lane per site, 1 or 2 RHS per
+    lane."""
+    return int(code in (1, 2) and row["rl"] == 1 and row["nr"] in (1, 2) and row["remap"] < 8)
+
+
 def _expected_candidates(dims, code, nrhs):
     """The tuner's candidate count: block {64,128,256} x RHS per lane x lanes
     per site x tile order {plain, XCD round-robin, z-slab with 1, 2, 4
@@ -122,13 +130,14 @@ def test_tuner_all_shapes_bitwise_and_tuned_solve_identical(wd, oracle, prec, di
     nrhs = 5
     rows = wd.wd_tune(lat.ctx, nrhs, code)
     for r in rows:
-        want = _expected_candidates(dims, code, nrhs) - (7 if 8 <= r["remap"] <= 10 else 0)
+        want = _expected_candidates(dims, code, nrhs) - (7 if 8 <= r["remap"] <= 10 else 0) + nt_extra(code, r)
         assert r["candidates"] == want, (r, want)
     for r in rows:
         note(f"{prec} {r['sweep']}: block {r['block']} nr {r['nr']} rl {r['rl']} remap {r['remap']} "
              f"occ {r['occ']} {r['candidates']} candidates, {r['rejected']} rejected")
         assert r["rejected"] == 0 and r["candidates"] > 1
         assert r["occ"] == 0 or 2 <= r["occ"] <= 8
+        assert r["lnt"] in (0, 1) and (r["lnt"] == 0 or nt_extra(code, r))
     if code != wd.WD_F64:
         wd.wd_tune(lat.ctx, nrhs, wd.WD_F64)
     B = li.gaussian_spinor(V // 2, seed=42, nrhs=nrhs)
@@ -185,6 +194,42 @@ def test_cached_shapes_with_work_group_cap(wd, tmp_path, monkeypatch):
     X1 = empty_like_dev(B)
     s0, st0 = lat.cg_solve(X0, dev(B), kap, wd.solver_params(prec=wd.WD_F16, tuned=0))
     s1, st1 = lat.cg_solve(X1, dev(B), kap, wd.solver_params(prec=wd.WD_F16, tuned=1))
+    assert s0 == wd.WD_OK and s1 == wd.WD_OK
+    assert [s["iters"] for s in st0] == [s["iters"] for s in st1]
+    assert np.array_equal(host(X0), host(X1))
+    lat.close()
+
+
+def test_cached_shapes_with_nontemporal_links(wd, tmp_path, monkeypatch):
+    """Cache lines with the trailing non-temporal-links field: the solve with
+    those shapes runs the LK_F32_12N instances (their names in the timing
+    report) and equals the default-shape solve bit for bit."""
+    dims = (8, 8, 8, 8)
+    V = li.volume(dims)
+    U = li.random_su3_field(dims, 0.5, seed=53)
+    lat = wd.Lattice(dims)
+    lat.gauge_load(dev(U), recon=12)
+    key = "8 8 8 8 2 2 2"  # dims, nrhs 2, FP16 spinors, FP32 12-real links
+    cache = tmp_path / "tune.txt"
+    cache.write_text(f"{key} 0 0 128 2 1 1 3 1.0 1\n"   # D_oe: nr 2, cap 3, non-temporal links
+                     f"{key} 0 1 256 1 2 1 0 1.0\n"     # xpay: rl 2 (no lnt field)
+                     f"{key} 1 0 64 1 1 1 0 1.0 1\n"    # D_oe^dag: nr 1, block 64, non-temporal links
+                     f"{key} 1 2 128 1 1 1 4 1.0 1\n")  # CG update: cap 4, non-temporal links
+    monkeypatch.setenv("WD_TUNE_CACHE", str(cache))
+    rows = wd.wd_tune(lat.ctx, 2, wd.WD_F16)
+    assert [r["lnt"] for r in rows] == [1, 0, 1, 1]
+    assert [r["source"] for r in rows] == ["cache-verified"] * 4 and all(r["rejected"] == 0 for r in rows)
+    B = li.gaussian_spinor(V // 2, seed=54, nrhs=2)
+    kap = [0.15, 0.156]
+    X0 = empty_like_dev(B)
+    X1 = empty_like_dev(B)
+    s0, st0 = lat.cg_solve(X0, dev(B), kap, wd.solver_params(prec=wd.WD_F16, tuned=0))
+    wd.wd_timing_enable(lat.ctx, True)
+    s1, st1 = lat.cg_solve(X1, dev(B), kap, wd.solver_params(prec=wd.WD_F16, tuned=1))
+    names = set(wd.wd_timing_report(lat.ctx))
+    wd.wd_timing_read(lat.ctx)
+    wd.wd_timing_enable(lat.ctx, False)
+    assert "dslash_kernel<2, 6, 2, 1, false, 0>" in names and "dslash_kernel<2, 6, 1, 1, true, 2>" in names, names
     assert s0 == wd.WD_OK and s1 == wd.WD_OK
     assert [s["iters"] for s in st0] == [s["iters"] for s in st1]
     assert np.array_equal(host(X0), host(X1))
