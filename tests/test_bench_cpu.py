@@ -41,18 +41,23 @@ def test_more_than_one_gpu_is_refused():
 
 def test_shape_table_lines_are_valid_launch_shapes():
     """The MI355X launch-shape table bench.py reuses: one line per sweep,
-    dims nrhs sp lk dag epi block nr rl remap occ us, every field in range."""
+    dims nrhs sp lk dag epi block nr rl remap occ us [lnt], every field in
+    range (tile orders 0-7 register-tiled, 8-10 LDS-staged, 11-13 t-walking;
+    lnt = 1 only for FP32 12-real links, one lane per site, 1-2 RHS per
+    lane, orders 0-7)."""
     import bench
     seen = set()
     for line in open(bench.SHAPE_TABLE):
         f = line.split()
-        assert len(f) == 15, line
+        assert len(f) in (15, 16), line
         d = [int(x) for x in f[:14]]
         lx, ly, lz, lt, nrhs, sp, lk, dag, epi, block, nr, rl, remap, occ = d
+        lnt = int(f[15]) if len(f) == 16 else 0
         assert all(L % 2 == 0 for L in (lx, ly, lz, lt)) and 1 <= nrhs <= 64
-        assert sp in (0, 1, 2, 3) and lk in (0, 1, 2, 3, 4) and dag in (0, 1) and epi in (0, 1, 2)
+        assert sp in (0, 1, 2, 3) and lk in (0, 1, 2, 3, 4, 5) and dag in (0, 1) and epi in (0, 1, 2)
         assert block in (64, 128, 256) and nr in (1, 2, 3, 4) and rl in (1, 2, 4)
-        assert 0 <= remap < 8 and (occ == 0 or 2 <= occ <= 8) and float(f[14]) > 0
+        assert 0 <= remap < 14 and (occ == 0 or 2 <= occ <= 8) and float(f[14]) > 0
+        assert lnt in (0, 1) and (lnt == 0 or (lk == 2 and rl == 1 and nr in (1, 2) and remap < 8)), line
         seen.add(tuple(d[:9]))
     # the four sweeps of the c3 workload's FP16 solve are all there
     assert all((32, 32, 32, 64, 12, 2, 2, dag, epi) in seen for dag, epi in ((0, 0), (0, 1), (1, 0), (1, 2)))
