@@ -165,9 +165,9 @@ wd_status run_sweep(wd_ctx *c, const Sweep &sw, const TuneCfg *cfg)
     if (!dslash_shape_supported(sw.sp, sw.lk, t.nr, t.rl) || t.block < 64 || t.block > 256 || (t.block & 63))
         return set_error(WD_ERR_ARG, "unsupported launch shape block %d nr %d rl %d", t.block, t.nr, t.rl);
     if (t.lnt != 0 && (t.lnt != 1 || !lnt_ok(sw.sp, sw.lk, t)))
-        return set_error(WD_ERR_ARG, "non-temporal links need FP32 12-real links, the register-tiled kernel, 1 lane "
-                         "per site and 1 or 2 RHS per lane (block %d nr %d rl %d order %d)", t.block, t.nr, t.rl,
-                         t.remap);
+        return set_error(WD_ERR_ARG, "non-temporal links need FP32 12- or 8-real or FP64 12-real links, the "
+                         "register-tiled kernel, 1 lane per site and 1 or 2 RHS per lane (block %d nr %d rl %d "
+                         "order %d)", t.block, t.nr, t.rl, t.remap);
     const int nr = t.nr, rl = t.rl;
     DslashArgs a;
     a.g = c->g;
@@ -255,7 +255,7 @@ wd_status run_sweep(wd_ctx *c, const Sweep &sw, const TuneCfg *cfg)
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (c->timing) WD_TRY(timing_begin(c, &e0, &e1));
     // (non-temporal links: the same packed field, read by the LK_F32_12N instance)
-    const int lk_run = t.lnt ? LK_F32_12N : sw.lk;
+    const int lk_run = t.lnt ? lnt_variant(sw.lk) : sw.lk;
     hipError_t e = dslash_launch(a, sw.sp, lk_run, nr, rl, sw.dag, sw.epi, t.block, (int)grid, c->stream);
     if (e != hipSuccess)
         return set_error(WD_ERR_HIP, "stencil launch (sp %d lk %d nr %d rl %d epi %d block %d): %s",
@@ -279,8 +279,9 @@ bool lds_order_ok(const wd_ctx *c, int sp, int lk, int nr, int remap)
 
 bool lnt_ok(int sp, int lk, const TuneCfg &t)
 {
-    return lk == LK_F32_12 && (sp == SP_F16 || sp == SP_F32) && t.rl == 1 && (t.nr == 1 || t.nr == 2) &&
-           t.remap >= 0 && t.remap < kTileOrders;
+    const bool fmt = (lk == LK_F64_12) ? sp == SP_F64
+                                       : ((lk == LK_F32_12 || lk == LK_F32_8) && (sp == SP_F16 || sp == SP_F32));
+    return fmt && t.rl == 1 && (t.nr == 1 || t.nr == 2) && t.remap >= 0 && t.remap < kTileOrders;
 }
 
 bool tw_order_ok(const wd_ctx *c, int sp, int lk, int nr, int rl, int block, int remap)

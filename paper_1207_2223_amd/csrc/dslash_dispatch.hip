@@ -67,7 +67,8 @@ hipError_t dslash_launch(const DslashArgs &a, int sp, int lk, int nr, int rl, in
 bool dslash_shape_supported(int sp, int lk, int nr, int rl)
 {
     if (rl != 1 && rl != 2 && rl != 4) return false;
-    if (lk == LK_F32_12N) return (sp == SP_F16 || sp == SP_F32) && rl == 1 && (nr == 1 || nr == 2);
+    if (lk == LK_F32_12N || lk == LK_F32_8N) return (sp == SP_F16 || sp == SP_F32) && rl == 1 && (nr == 1 || nr == 2);
+    if (lk == LK_F64_12N) return sp == SP_F64 && rl == 1 && (nr == 1 || nr == 2);
     if (sp == SP_F64 || lk == LK_F32_8) return nr == 1 || nr == 2;  // (8-real links: for few RHS)
     return nr >= 1 && nr <= 4;
 }

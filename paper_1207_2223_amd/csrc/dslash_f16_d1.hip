@@ -1,4 +1,4 @@
-// Stencil instantiations: FP16 spinors (per-site FP32 norm) with FP32 12-real, FP32 18-real, FP16 12-real or FP32 8-real links (and FP32 12-real links read non-temporally), adjoint hopping.
+// Stencil instantiations: FP16 spinors (per-site FP32 norm) with FP32 12-real, FP32 18-real, FP16 12-real or FP32 8-real links (and FP32 12- and 8-real links read non-temporally), adjoint hopping.
 #include "dslash_impl.h"
 
 namespace wd {
@@ -59,6 +59,10 @@ hipError_t dslash_launch_f16_d1(const DslashArgs &a, int lk, int nr, int rl, int
     if (lk == LK_F32_12N) {
         WD_DSL_SHAPE(SP_F16, LK_F32_12N, 1, 1, true)
         WD_DSL_SHAPE(SP_F16, LK_F32_12N, 2, 1, true)
+    }
+    if (lk == LK_F32_8N) {
+        WD_DSL_SHAPE(SP_F16, LK_F32_8N, 1, 1, true)
+        WD_DSL_SHAPE(SP_F16, LK_F32_8N, 2, 1, true)
     }
     return hipErrorInvalidValue;
 }

@@ -28,9 +28,9 @@ enum { SP_F64 = 0, SP_F32 = 1, SP_F16 = 2, SP_I16 = 3 };
 // Formats that store a per-site FP32 norm next to 16-bit values.
 __host__ __device__ constexpr bool has_norm(int sp) { return sp == SP_F16 || sp == SP_I16; }
 enum { LK_F64_18 = 0, LK_F64_12 = 1, LK_F32_12 = 2, LK_F16_12 = 3, LK_F32_18 = 4, LK_F32_8 = 5 };
-// LK_F32_12 data read with non-temporal loads (a launch variant of the same
-// packed links, not a storage format of its own).
-enum { LK_F32_12N = 6 };
+// FP32 12-real, FP64 12-real and FP32 8-real data read with non-temporal
+// loads (launch variants of the same packed links, not storage formats).
+enum { LK_F32_12N = 6, LK_F64_12N = 7, LK_F32_8N = 8 };
 
 typedef _Float16 half8_t __attribute__((ext_vector_type(8)));
 
@@ -381,22 +381,25 @@ template <> struct LinkIO<LK_F64_18> {
     }
 };
 
-template <> struct LinkIO<LK_F64_12> {
+template <bool NT>
+struct LinkIOF64x12 {
     typedef double real;
     static constexpr int nchunk = 6;
     static constexpr size_t chunk_bytes = 16;
     __device__ static __forceinline__ void load(const char *U, int cs, int blk, int i, double u[18])
     {
-        const double2 *p = reinterpret_cast<const double2 *>(U) + (size_t)blk * 6 * cs;
+        const dbl2_t *p = reinterpret_cast<const dbl2_t *>(U) + (size_t)blk * 6 * cs;
 #pragma unroll
         for (int k = 0; k < 6; k++) {
-            double2 w = p[(size_t)k * cs + i];
+            const dbl2_t w = ld_hint<NT>(p + (size_t)k * cs + i);
             u[2 * k] = w.x;
             u[2 * k + 1] = w.y;
         }
         reconstruct_row3(u);
     }
 };
+template <> struct LinkIO<LK_F64_12> : LinkIOF64x12<false> {};
+template <> struct LinkIO<LK_F64_12N> : LinkIOF64x12<true> {};
 
 template <bool NT>
 struct LinkIOF32x12 {
@@ -486,14 +489,16 @@ template <> struct LinkIO<LK_F32_18> {
 // link stores W's first row (p, q) in chunk 0, b1 = 0, and bit 1 of the
 // second phase set; then W = [[p, q], [-a1* q*, a1* p*]] (det W = a1*,
 // |a1| = 1).  Finally U = C_-k(s P U').
-template <> struct LinkIO<LK_F32_8> {
+template <bool NT>
+struct LinkIOF32x8 {
     typedef float real;
     __device__ static __forceinline__ void load(const char *U8, int cs, int blk, int i, float u[18])
     {
         const char *p = U8 + (size_t)blk * 2 * cs * 16;
         const uint32_t off = (uint32_t)i * 16u;
-        const flt4_t w0 = ld_off<flt4_t, true>(p, off);
-        const flt4_t w1 = ld_off<flt4_t, true>(p + (size_t)cs * 16, off);
+        const flt4_t w0 = NT ? ld_off_nt<flt4_t, true>(p, off) : ld_off<flt4_t, true>(p, off);
+        const flt4_t w1 = NT ? ld_off_nt<flt4_t, true>(p + (size_t)cs * 16, off)
+                            : ld_off<flt4_t, true>(p + (size_t)cs * 16, off);
         const float a2r = w0.x, a2i = w0.y, a3r = w0.z, a3i = w0.w, b1r = w1.x, b1i = w1.y;
         const int k = (int)(__float_as_uint(w1.z) & 3u);
         const unsigned cb = __float_as_uint(w1.w) & 3u;
@@ -557,13 +562,17 @@ template <> struct LinkIO<LK_F32_8> {
                 }
     }
 };
+template <> struct LinkIO<LK_F32_8> : LinkIOF32x8<false> {};
+template <> struct LinkIO<LK_F32_8N> : LinkIOF32x8<true> {};
 
 __host__ __device__ constexpr size_t link_bytes(int lk)
 {
     return lk == LK_F64_18 ? 144
-                           : (lk == LK_F64_12 ? 96
-                                              : (lk == LK_F32_12 || lk == LK_F32_12N ? 48
-                                                                 : (lk == LK_F16_12 ? 24 : (lk == LK_F32_8 ? 32 : 72))));
+                           : (lk == LK_F64_12 || lk == LK_F64_12N
+                                  ? 96
+                                  : (lk == LK_F32_12 || lk == LK_F32_12N
+                                         ? 48
+                                         : (lk == LK_F16_12 ? 24 : (lk == LK_F32_8 || lk == LK_F32_8N ? 32 : 72))));
 }
 
 // ---------------------------------------------------------------------------

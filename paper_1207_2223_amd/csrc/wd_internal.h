@@ -94,10 +94,15 @@ struct TuneCfg {
     int rl = 1;
     int remap = 1;
     int occ = 0;  // 0, or at most occ work-groups per CU (enforced through dynamic LDS)
-    int lnt = 0;  // 1: FP32 12-real links loaded non-temporally (register-tiled kernel, rl 1, nr 1-2)
+    int lnt = 0;  // 1: links loaded non-temporally (FP32 12/8-real, FP64 12-real; register-tiled, rl 1, nr 1-2)
 };
-// Whether a shape of a sweep with links lk may take lnt = 1.
+// Whether a shape of a sweep with links lk may take lnt = 1, and the
+// non-temporal launch variant of a link format (-1: none).
 bool lnt_ok(int sp, int lk, const TuneCfg &t);
+inline int lnt_variant(int lk)
+{
+    return lk == LK_F32_12 ? LK_F32_12N : (lk == LK_F64_12 ? LK_F64_12N : (lk == LK_F32_8 ? LK_F32_8N : -1));
+}
 
 // LDS per CU on gfx950, and the dynamic LDS per work-group that lets at most
 // occ work-groups share a CU (occ in 2..kMaxOcc; 0 = no cap).

@@ -43,7 +43,8 @@ def test_shape_table_lines_are_valid_launch_shapes():
     """The MI355X launch-shape table bench.py reuses: one line per sweep,
     dims nrhs sp lk dag epi block nr rl remap occ us [lnt], every field in
     range (tile orders 0-7 register-tiled, 8-10 LDS-staged, 11-13 t-walking;
-    lnt = 1 only for FP32 12-real links, one lane per site, 1-2 RHS per
+    lnt = 1 only for FP16 or FP32 spinors over FP32 12- or 8-real links and
+    FP64 spinors over FP64 12-real links, one lane per site, 1-2 RHS per
     lane, orders 0-7)."""
     import bench
     seen = set()
@@ -57,7 +58,8 @@ def test_shape_table_lines_are_valid_launch_shapes():
         assert sp in (0, 1, 2, 3) and lk in (0, 1, 2, 3, 4, 5) and dag in (0, 1) and epi in (0, 1, 2)
         assert block in (64, 128, 256) and nr in (1, 2, 3, 4) and rl in (1, 2, 4)
         assert 0 <= remap < 14 and (occ == 0 or 2 <= occ <= 8) and float(f[14]) > 0
-        assert lnt in (0, 1) and (lnt == 0 or (lk == 2 and rl == 1 and nr in (1, 2) and remap < 8)), line
+        nt_fmt = (lk in (2, 5) and sp in (1, 2)) or (lk == 1 and sp == 0)
+        assert lnt in (0, 1) and (lnt == 0 or (nt_fmt and rl == 1 and nr in (1, 2) and remap < 8)), line
         seen.add(tuple(d[:9]))
     # the four sweeps of the c3 workload's FP16 solve are all there
     assert all((32, 32, 32, 64, 12, 2, 2, dag, epi) in seen for dag, epi in ((0, 0), (0, 1), (1, 0), (1, 2)))

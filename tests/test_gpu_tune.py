@@ -32,7 +32,7 @@ def lds_candidates(dims, code, nrhs):
     links (1 RHS per lane), where a plane of one parity has a multiple of 64
     sites up to 512, Lz % 8 == 0, Lt divisible by the chunk and three input
     planes of the lane's RHS fit in LDS."""
-    base, links = code & 0xF, code & 0x30
+    base, links = code & 0xF, code & 0x70
     if base == 2 and links in (0, 0x10):
         nrs, sb = (1, 2), 52
     elif base == 1 and links == 0:
@@ -58,7 +58,7 @@ def tw_candidates(dims, code, nrhs, blocks=None):
     of one parity holds whole tiles of the block's sites, Lz % 8 == 0 and Lt
     is divisible by the chunk.  The tuner tries the largest block of 256,
     128, 64 that divides a plane; `blocks` lists others to include."""
-    base, links = code & 0xF, code & 0x30
+    base, links = code & 0xF, code & 0x70
     if base != 2 or links not in (0, 0x10):
         return []
     S = dims[0] // 2 * dims[1]
@@ -78,10 +78,11 @@ def tw_candidates(dims, code, nrhs, blocks=None):
 
 def nt_extra(code, row):
     """1 if the tuner retried the sweep's best shape with its links loaded
-    non-temporally: FP16 or FP32 spinors with FP32 12-real links, the
-    register-tiled kernel (orders 0-7), one lane per site, 1 or 2 RHS per
-    lane."""
-    return int(code in (1, 2) and row["rl"] == 1 and row["nr"] in (1, 2) and row["remap"] < 8)
+    non-temporally: FP16 or FP32 spinors with FP32 12- or 8-real links, or
+    FP64 spinors with FP64 12-real links; the register-tiled kernel (orders
+    0-7), one lane per site, 1 or 2 RHS per lane."""
+    fmt = (row["lk"] in (2, 5) and row["sp"] in (1, 2)) or (row["lk"] == 1 and row["sp"] == 0)
+    return int(fmt and row["rl"] == 1 and row["nr"] in (1, 2) and row["remap"] < 8)
 
 
 def _expected_candidates(dims, code, nrhs):
@@ -94,8 +95,8 @@ def _expected_candidates(dims, code, nrhs):
     best of these with a cap of 2..8 work-groups per CU (7 more, unless the
     best is an LDS-staged shape, which takes no cap: then the count is 7
     less)."""
-    f64 = (code & 0xF) == 0
-    shapes = [(1, 1), (2, 1), (1, 2), (2, 2), (1, 4), (2, 4)] if f64 else \
+    few = (code & 0xF) == 0 or (code & 0x40)  # FP64, or 8-real links: 1 or 2 RHS per lane
+    shapes = [(1, 1), (2, 1), (1, 2), (2, 2), (1, 4), (2, 4)] if few else \
         [(nr, rl) for rl in (1, 2, 4) for nr in (1, 2, 3, 4)]
     plane = dims[0] // 2 * dims[1]
     n = 0
@@ -112,7 +113,7 @@ def _expected_candidates(dims, code, nrhs):
     return n + len(lds_candidates(dims, code, nrhs)) + len(tw_candidates(dims, code, nrhs)) + 7
 
 
-@pytest.mark.parametrize("prec", ["F64", "F32", "F16", "F16L", "F16R", "I16"])
+@pytest.mark.parametrize("prec", ["F64", "F32", "F16", "F16L", "F16R", "F16R8", "I16"])
 @pytest.mark.parametrize("dims", [(6, 4, 4, 6), (16, 8, 8, 4), (16, 16, 8, 4), (8, 8, 4, 8)])
 def test_tuner_all_shapes_bitwise_and_tuned_solve_identical(wd, oracle, prec, dims):
     """(6,4,4,6): Vh = 288, a ragged last tile for every block size;
@@ -122,6 +123,7 @@ def test_tuner_all_shapes_bitwise_and_tuned_solve_identical(wd, oracle, prec, di
     t-slab orders are candidates."""
     code = {"F64": wd.WD_F64, "F32": wd.WD_F32, "F16": wd.WD_F16,
             "F16L": wd.WD_F16 | wd.WD_LINKS_F16, "F16R": wd.WD_F16 | wd.WD_LINKS_R18,
+            "F16R8": wd.WD_F16 | wd.WD_LINKS_R8,
             "I16": wd.WD_I16}[prec]
     V = li.volume(dims)
     U = li.random_su3_field(dims, 0.5, seed=41)
