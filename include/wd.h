@@ -391,8 +391,9 @@ wd_status wd_timing_report(wd_ctx *c, char *buf, size_t len);
  * kernels, see wd_dslash_shaped) is timed with HIP events on synthetic
  * fields, then the fastest with a cap of 2..8 work-groups per compute unit
  * (not for an LDS-staged shape), and the fastest of those, where it applies
- * (FP32 or FP16 spinors with FP32 12-real links, the register-tiled kernel,
- * one lane per site, 1 or 2 RHS per lane), with its links loaded
+ * (FP32 or FP16 spinors with FP32 12- or 8-real links, FP64 spinors with
+ * FP64 12-real links, the register-tiled kernel, one lane per site, 1 or 2
+ * RHS per lane), with its links loaded
  * non-temporally (report field lnt); a shape whose
  * vectors or norm partials are not bitwise identical to the reference shape
  * is rejected.  The fastest shapes are kept in the context and used by
