@@ -872,7 +872,9 @@ def bench_measure(args, wd, torch):
     value = 12 * args.steps / elapsed
     report, t_inst = instrumented(wd, torch, lat.ctx, lambda: measure(params))
     dom, roof, sten = kernel_roofline(report, t_inst)
-    roof["traffic"] = counter_traffic("c3_32c64_12rhs", args.prec, dom["name"])  # the same solve's kernels
+    # (counted for this workload's own launches only: as columns converge its
+    # launches carry fewer RHS than the c3 solve's, so that record does not apply)
+    roof["traffic"] = counter_traffic(args.workload, args.prec, dom["name"])
     meff = [float(np.log(corr[i] / corr[i + 1])) for i in range(min(12, len(corr) - 1))]
 
     # the even-site part of the 12 mixed-precision columns, for the oracle's check
