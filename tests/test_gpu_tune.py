@@ -202,36 +202,44 @@ def test_cached_shapes_with_work_group_cap(wd, tmp_path, monkeypatch):
     lat.close()
 
 
-def test_cached_shapes_with_nontemporal_links(wd, tmp_path, monkeypatch):
-    """Cache lines with the trailing non-temporal-links field: the solve with
-    those shapes runs the LK_F32_12N instances (their names in the timing
-    report) and equals the default-shape solve bit for bit."""
+@pytest.mark.parametrize("prec", ["F16", "F64", "F32R8", "F16R8"])
+def test_cached_shapes_with_nontemporal_links(wd, tmp_path, monkeypatch, prec):
+    """Cache lines with the trailing non-temporal-links field, for every link
+    format that has a non-temporal variant (FP32 12-real with FP16 spinors,
+    FP64 12-real with FP64 spinors, FP32 8-real with FP32 and FP16 spinors):
+    the solve with those shapes runs the non-temporal instances (their link
+    format codes 6, 7, 8 in the timing report's kernel names) and equals the
+    default-shape solve bit for bit."""
+    code, sp, lk, lkn = {"F16": (wd.WD_F16, 2, 2, 6), "F64": (wd.WD_F64, 0, 1, 7),
+                         "F32R8": (wd.WD_F32 | wd.WD_LINKS_R8, 1, 5, 8),
+                         "F16R8": (wd.WD_F16 | wd.WD_LINKS_R8, 2, 5, 8)}[prec]
     dims = (8, 8, 8, 8)
     V = li.volume(dims)
     U = li.random_su3_field(dims, 0.5, seed=53)
     lat = wd.Lattice(dims)
     lat.gauge_load(dev(U), recon=12)
-    key = "8 8 8 8 2 2 2"  # dims, nrhs 2, FP16 spinors, FP32 12-real links
+    key = f"8 8 8 8 2 {sp} {lk}"  # dims, nrhs 2, spinor and link format
     cache = tmp_path / "tune.txt"
     cache.write_text(f"{key} 0 0 128 2 1 1 3 1.0 1\n"   # D_oe: nr 2, cap 3, non-temporal links
                      f"{key} 0 1 256 1 2 1 0 1.0\n"     # xpay: rl 2 (no lnt field)
                      f"{key} 1 0 64 1 1 1 0 1.0 1\n"    # D_oe^dag: nr 1, block 64, non-temporal links
                      f"{key} 1 2 128 1 1 1 4 1.0 1\n")  # CG update: cap 4, non-temporal links
     monkeypatch.setenv("WD_TUNE_CACHE", str(cache))
-    rows = wd.wd_tune(lat.ctx, 2, wd.WD_F16)
+    rows = wd.wd_tune(lat.ctx, 2, code)
     assert [r["lnt"] for r in rows] == [1, 0, 1, 1]
     assert [r["source"] for r in rows] == ["cache-verified"] * 4 and all(r["rejected"] == 0 for r in rows)
     B = li.gaussian_spinor(V // 2, seed=54, nrhs=2)
     kap = [0.15, 0.156]
     X0 = empty_like_dev(B)
     X1 = empty_like_dev(B)
-    s0, st0 = lat.cg_solve(X0, dev(B), kap, wd.solver_params(prec=wd.WD_F16, tuned=0))
+    s0, st0 = lat.cg_solve(X0, dev(B), kap, wd.solver_params(prec=code, tuned=0))
     wd.wd_timing_enable(lat.ctx, True)
-    s1, st1 = lat.cg_solve(X1, dev(B), kap, wd.solver_params(prec=wd.WD_F16, tuned=1))
+    s1, st1 = lat.cg_solve(X1, dev(B), kap, wd.solver_params(prec=code, tuned=1))
     names = set(wd.wd_timing_report(lat.ctx))
     wd.wd_timing_read(lat.ctx)
     wd.wd_timing_enable(lat.ctx, False)
-    assert "dslash_kernel<2, 6, 2, 1, false, 0>" in names and "dslash_kernel<2, 6, 1, 1, true, 2>" in names, names
+    assert f"dslash_kernel<{sp}, {lkn}, 2, 1, false, 0>" in names, names
+    assert f"dslash_kernel<{sp}, {lkn}, 1, 1, true, 2>" in names, names
     assert s0 == wd.WD_OK and s1 == wd.WD_OK
     assert [s["iters"] for s in st0] == [s["iters"] for s in st1]
     assert np.array_equal(host(X0), host(X1))
