@@ -88,30 +88,43 @@ def stencil_source_hash():
     return h.hexdigest()[:16]
 
 
-def counter_traffic(workload, prec, kernel):
-    """HBM bytes per launch of `kernel` from the committed counter summaries
-    (profiles/*.md lines 'traffic-record: workload=.. prec=.. hash=..
-    bytes_per_launch=.. kernel=..'), or None when no record matches the
-    workload, precision, kernel and current stencil sources."""
+def counter_record(kind, field, workload, prec, kernel):
+    """A figure of `kernel` from the committed counter summaries
+    (profiles/*.md lines '<kind>-record: workload=.. ; prec=.. ; hash=.. ;
+    <field>=.. ; kernel=..'), or None when no record matches the workload,
+    precision, kernel and current stencil sources."""
     import glob
     h = stencil_source_hash()
+    tag = kind + "-record:"
     for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
         with open(path) as fh:
             for line in fh:
-                if not line.startswith("traffic-record:"):
+                if not line.startswith(tag):
                     continue
-                rec = dict(kv.split("=", 1) for kv in line[len("traffic-record:"):].strip().split(" ; "))
+                rec = dict(kv.split("=", 1) for kv in line[len(tag):].strip().split(" ; "))
                 if (rec.get("workload") == workload and rec.get("prec") == prec and rec.get("hash") == h
                         and rec.get("kernel") == kernel):
-                    return float(rec["bytes_per_launch"])
+                    return float(rec[field])
     return None
+
+
+def counter_traffic(workload, prec, kernel):
+    """HBM bytes per launch (FETCH_SIZE and WRITE_SIZE, calibrated)."""
+    return counter_record("traffic", "bytes_per_launch", workload, prec, kernel)
+
+
+def counter_valu_busy(workload, prec, kernel):
+    """Percent of the kernel's GPU time the vector ALUs were busy (rocprofv3
+    VALUBusy)."""
+    return counter_record("valu", "valu_busy_pct", workload, prec, kernel)
 
 
 def parse():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=None, help="timed steps (default 3; c5: 20 trajectories)")
-    ap.add_argument("--warmup", type=int, default=None, help="untimed steps (default 1; c5: 30 trajectories)")
+    ap.add_argument("--steps", type=int, default=None, help="timed steps (default 3; c5: 40 trajectories)")
+    ap.add_argument("--warmup", type=int, default=None, help="untimed steps (default 1; c5: 60 "
+                    "thermalisation trajectories)")
     ap.add_argument("--workload", default="c3_32c64_12rhs", choices=sorted(WORKLOADS))
     ap.add_argument("--prec", default="f16", choices=sorted(PRECS))
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison")
@@ -371,6 +384,7 @@ def bench_solve(args, wd, torch):
     log("[bench] kernels: " + "; ".join(f"{k}: {v[0]} x {v[1] / v[0] * 1e3:.1f} us" for k, v in report.items()))
     dom, roof, sten = kernel_roofline(report, t_inst)
     roof["traffic"] = counter_traffic(args.workload, args.prec, dom["name"])
+    dom["valu_busy_pct"] = counter_valu_busy(args.workload, args.prec, dom["name"])
 
     stream = dsl = dsl_err = shard = None
     if not args.no_dslash:
@@ -875,6 +889,7 @@ def bench_measure(args, wd, torch):
     # (counted for this workload's own launches only: as columns converge its
     # launches carry fewer RHS than the c3 solve's, so that record does not apply)
     roof["traffic"] = counter_traffic(args.workload, args.prec, dom["name"])
+    dom["valu_busy_pct"] = counter_valu_busy(args.workload, args.prec, dom["name"])
     meff = [float(np.log(corr[i] / corr[i + 1])) for i in range(min(12, len(corr) - 1))]
 
     # the even-site part of the 12 mixed-precision columns, for the oracle's check
