@@ -30,7 +30,9 @@ Workloads (--workload):
 
 Printed: one JSON line with the workload's rate (value), the FP64 rate on the
 same inputs, the dominant stencil kernel's roofline entry (HIP events on the
-context's stream) and the CPU oracle baseline.
+context's stream) and the CPU oracle baseline; for c1-c3 also the solve time
+against the CG iteration count (tolerances 1e-2 .. 1e-10: per-iteration time
+and per-solve overhead) and the stencil alone in every format.
 """
 import argparse
 import json
@@ -45,6 +47,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 LLC_BYTES = 256e6      # MI355X last-level (Infinity) cache
+SPINOR_BYTES = {0: 192, 1: 96, 2: 52, 3: 52}  # per site and RHS: FP64, FP32, FP16 + norm, int16 + norm
 METRIC = "Dslash HBM GB/s + GFLOP/s; M†M solves/s mixed vs FP64 at 1e-10, p99 latency"
 FLOP_SITE = 1320.0     # per output site and RHS of one hopping sweep
 
@@ -129,6 +132,8 @@ def parse():
     ap.add_argument("--workload", default="c3_32c64_12rhs", choices=sorted(WORKLOADS))
     ap.add_argument("--prec", default="f16", choices=sorted(PRECS))
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison")
+    ap.add_argument("--no-fit", action="store_true",
+                    help="c1-c3: skip the solve time against iteration count (tolerances 1e-2 .. 1e-10)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-dslash", action="store_true",
                     help="skip the stencil-alone section and the copy-bandwidth probe")
@@ -316,6 +321,29 @@ def base_record(args, value, unit, ms_per_step, dtype, config, higher=True):
 # c1 / c2 / c3: batched solves on one lattice
 # ---------------------------------------------------------------------------
 
+def solve_time_vs_iterations(wd, torch, solve, args):
+    """Solve time against CG iteration count (the paper's Fig. 1, Sec. 4, on
+    this GPU): the workload's batched solve to tolerances 1e-2 .. 1e-10, each
+    once untimed and once timed, and the least-squares line time = overhead
+    + per-iteration time x iterations."""
+    pts = []
+    for tol in (1e-2, 1e-4, 1e-6, 1e-8, 1e-10):
+        p = wd.solver_params(prec=PRECS[args.prec], eo=1, tol=tol, tuned=args.tuned, delta=args.delta)
+        solve(p)
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        st, stats = solve(p)
+        torch.cuda.synchronize()
+        pts.append((max(s["iters"] for s in stats), (time.perf_counter() - ts) * 1e3, st))
+        log(f"[bench] tol {tol:.0e}: {pts[-1][0]} iterations, {pts[-1][1]:.1f} ms, status {st}")
+    it = np.array([q[0] for q in pts], dtype=float)
+    ms = np.array([q[1] for q in pts])
+    slope, icpt = np.polyfit(it, ms, 1)
+    return {"tol": [1e-2, 1e-4, 1e-6, 1e-8, 1e-10], "iters": [int(q[0]) for q in pts],
+            "ms": [float(q[1]) for q in pts], "status": [int(q[2]) for q in pts],
+            "ms_per_iteration": float(slope), "overhead_ms": float(icpt)}
+
+
 def bench_solve(args, wd, torch):
     w = WORKLOADS[args.workload]
     dims, kappa, nrhs = w["dims"], w["kappa"], w["nrhs"]
@@ -418,6 +446,7 @@ def bench_solve(args, wd, torch):
                 "status": st64, "max_true_resid": max(s["true_resid"] for s in s64),
                 "ms_per_solve_runs": [t * 1e3 for t in t64s], "timing": "median of 3 after one warm-up solve"}
     iters64 = fp64["iters"] if fp64 else iters[-1]
+    tvi = None if args.no_fit else solve_time_vs_iterations(wd, torch, solve, args)
 
     cpu = oracle_res = None
     if not args.no_cpu:
@@ -448,6 +477,7 @@ def bench_solve(args, wd, torch):
         "roofline": roof,
         "tune": tune_rows,
         "fp64": fp64,
+        "solve_time_vs_iterations": tvi,
         "mixed_vs_fp64": (value / fp64["solves_per_s"]) if fp64 else None,
         "stream_copy_GB_s": stream,
         "dslash": dsl,
@@ -512,9 +542,13 @@ def dslash_section(wd, Ud, dims, stream_gbs, prec, nrhs, tuned=1):
         for epi, ename in ((0, "plain"), (2, "cg-update")):
             ms, by = wd.wd_bench_dslash(lat.ctx, n, code, epi=epi, iters=20, tuned=tuned)
             gbs = by / (ms * 1e-3) / 1e9
+            # (the naive count: every one of the 8 neighbour spinors counted
+            # as read from memory, 7 more than the algorithmic count)
+            naive = by + 7 * SPINOR_BYTES[code & 0xF] * Vh * n
             rows.append({"prec": name, "nrhs": n, "sweep": ename, "us": ms * 1e3, "bytes": by,
                          "rel_err_vs_fp64": err[name],
                          "GB_s": gbs, "frac_peak": gbs / HBM_PEAK_GBS, "frac_copy": gbs / stream_gbs,
+                         "GB_s_naive_every_neighbour": naive / (ms * 1e-3) / 1e9,
                          "GFLOP_s": FLOP_SITE * Vh * n / (ms * 1e-3) / 1e9})
             log(f"[bench] dslash {name} nrhs {n} {ename}: {ms * 1e3:.1f} us {gbs:.0f} GB/s "
                 f"({gbs / HBM_PEAK_GBS * 100:.1f} % of peak, {gbs / stream_gbs * 100:.1f} % of copy)")
