@@ -457,6 +457,20 @@ def bench_solve(args, wd, torch):
                          f"{nrhs} oracle applications of Mhat^dag Mhat on {dims} (median {t_apply:.3f} s on "
                          f"{cores} threads; one more on 1 thread: {t_one:.3f} s), each applied to one GPU "
                          f"solution to check it, times {iters64} CG iterations per solve (the FP64 CG's count)")
+        if len(B[0]) * 2 <= 16 * 16 * 16 * 32:
+            # small enough to time the oracle's whole solve: its own FP64 CG
+            # on Mhat^dag Mhat for the first RHS to 1e-10 (on all threads)
+            wdref, _ = oracle_host()
+            t = time.time()
+            _, it0, tr0, conv0 = wdref.cg(dims, U, kappa, B[0], eo=True, tol=1e-10)
+            tfull = time.time() - t
+            cpu["extrapolated_value"] = cpu["value"]
+            cpu["value"] = 1.0 / tfull
+            cpu["sample"] = (f"one whole oracle CG (FP64, Mhat^dag Mhat) on RHS 0 to 1e-10: {it0} iterations, "
+                             f"true residual {tr0:.2e}, {tfull:.2f} s on {cores} threads (extrapolated_value: "
+                             f"{nrhs} oracle applications, median {t_apply:.3f} s, times {iters64} iterations; "
+                             f"single_thread: one application on 1 thread, {t_one:.3f} s, times {iters64})")
+            ok &= bool(conv0)
         log(f"[bench] cpu oracle: {cpu['value']:.4g} solves/s on {cores} threads, "
             f"{cpu['single_thread']['value']:.4g} on 1")
     lat.close()
