@@ -424,7 +424,8 @@ def bench_solve(args, wd, torch):
     if not args.no_dslash:
         stream = copy_bandwidth(torch)
         dsl, dsl_err = dslash_section(wd, Ud, dims, stream, PRECS[args.prec], nrhs, tuned=args.tuned)
-        shard = shard_section(wd, Ud, dims, tuned=args.tuned)
+        # (a t-cut into slabs of 8 t-slices needs Lt > 8)
+        shard = shard_section(wd, Ud, dims, tuned=args.tuned) if dims[3] > 8 else None
 
     # the mixed solutions of the last timed step, for the oracle's check
     Xmixed = Xd.cpu().numpy() if not args.no_cpu else None
@@ -603,6 +604,8 @@ def shard_section(wd, Ud, dims, lt=8, tuned=1):
     interior kernel's upper bound), and the kernels a t-cut adds: packing
     both spin-projected t-faces and adding the received faces into the
     boundary slices.  Links are the first lt t-slices of the workload field."""
+    if dims[3] <= lt:
+        raise ValueError(f"a t-cut into slabs of {lt} t-slices needs Lt > {lt} (dims {dims})")
     sd = (dims[0], dims[1], dims[2], lt)
     Vs = int(np.prod(sd))
     lat = wd.Lattice(sd)
