@@ -6,6 +6,7 @@ import sys
 import os
 
 import numpy as np
+import pytest
 
 import lattice_inputs as li
 
@@ -84,3 +85,13 @@ def test_shape_table_is_used_through_a_private_copy(monkeypatch):
     monkeypatch.setattr(sys, "argv", ["bench.py", "--retune"])
     bench.use_shape_table(bench.parse())
     assert "WD_TUNE_CACHE" not in os.environ
+
+
+def test_t_cut_share_needs_more_than_one_slab():
+    """The one-GPU share of a t-cut lattice (slabs of 8 t-slices) is refused
+    on the host for Lt <= 8, before any library call."""
+    import bench
+    with pytest.raises(ValueError):
+        bench.shard_section(None, None, (4, 4, 4, 4))
+    with pytest.raises(ValueError):
+        bench.shard_section(None, None, (8, 8, 8, 8))
