@@ -210,3 +210,33 @@ def test_idle_slots_are_released_when_two_lattices_block_each_other():
     for r in reqs:
         assert np.array_equal(r.x, 2 * r.phi)
     assert adm.peak <= 440 and adm.in_use == 0
+
+
+@pytest.mark.parametrize("seed", range(60))
+def test_random_streams_complete_within_a_tight_budget(seed):
+    """Random streams (2-4 lattices of different slot sizes, 1-8 RHS per
+    request, Poisson arrivals) under a budget that fits the largest request
+    alone plus at most 300 bytes: every request completes with its own
+    results, the budget is never exceeded and everything is given back."""
+    rng = np.random.default_rng(seed)
+    nl = int(rng.integers(2, 5))
+    sb = {f"L{i}": int(rng.choice([50, 100, 200])) for i in range(nl)}
+    ex = {k: FakeExecutor(8, slot_bytes=v, step_time=0.0005) for k, v in sb.items()}
+    budget = max(8 * v + 80 for v in sb.values()) + int(rng.integers(0, 300))
+    adm = Admission(budget)
+    srv = Server(ex, adm, k_iters=8)
+    reqs, t = [], 0.0
+    for i in range(16):
+        n = int(rng.integers(1, 9))
+        t += float(rng.exponential(0.002))
+        reqs.append(Request(i, f"L{int(rng.integers(nl))}", rng.standard_normal((n, 4, 4, 3)) + 0j,
+                            list(rng.uniform(0.14, 0.157, n)), arrival=t))
+    out = {}
+    th = threading.Thread(target=lambda: out.update(summ=srv.run(reqs)), daemon=True)
+    th.start()
+    th.join(timeout=30)
+    assert not th.is_alive(), f"scheduler stalled (budget {budget}, slot bytes {sb})"
+    assert out["summ"]["completed"] == len(reqs)
+    for r in reqs:
+        assert np.array_equal(r.x, 2 * r.phi)
+    assert adm.peak <= budget and adm.in_use == 0
