@@ -445,7 +445,8 @@ extern "C" wd_status wd_tune(wd_ctx *c, int nrhs, int prec, char *report, size_t
                      ? (lds_order_ok(c, sp, lk, cc.nr, cc.remap) && cc.rl == 1 && cc.block == 256 && cc.occ == 0)
                  : is_tw_order(cc.remap)
                      ? tw_order_ok(c, sp, lk, cc.nr, cc.rl, cc.block, cc.remap)
-                     : (cc.remap >= 0 && cc.remap < kTileOrders &&
+                     : (cc.remap >= 0 && cc.remap < kTileOrders && cc.block >= 64 && cc.block <= 256 &&
+                        (cc.block & 63) == 0 &&
                         (cc.remap < 2 || slab_order_ok(c->g, cc.block / cc.rl, cc.remap))))) {
                 std::vector<TuneCfg> vl = {cands[0], cc};
                 std::vector<char> ok;

@@ -244,3 +244,55 @@ def test_cached_shapes_with_nontemporal_links(wd, tmp_path, monkeypatch, prec):
     assert [s["iters"] for s in st0] == [s["iters"] for s in st1]
     assert np.array_equal(host(X0), host(X1))
     lat.close()
+
+
+def test_invalid_launch_shapes_are_refused_before_any_launch(wd):
+    """wd_dslash_shaped refuses, with WD_ERR_ARG and the output untouched,
+    every shape the stencil kernels do not support on this lattice (8x8x4x8:
+    32 sites per plane of one parity, Lz = 4 so no z-slab order)."""
+    import torch
+    dims = (8, 8, 4, 8)
+    V = li.volume(dims)
+    lat = wd.Lattice(dims)
+    lat.gauge_load(dev(li.random_su3_field(dims, 0.5, seed=61)), recon=12)
+    inp = dev(li.gaussian_spinor(V // 2, seed=62, nrhs=2))
+    out = torch.full_like(inp, 7 + 7j)
+    bad = [(wd.WD_F16, (96, 1, 1, 0, 0)),     # threads not a multiple of 64
+           (wd.WD_F16, (320, 1, 1, 0, 0)),    # more than 256 threads
+           (wd.WD_F16, (128, 5, 1, 0, 0)),    # 5 RHS per lane
+           (wd.WD_F16, (128, 1, 3, 0, 0)),    # 3 lanes per site
+           (wd.WD_F16, (128, 1, 1, 18, 0)),   # no such tile order
+           (wd.WD_F16, (128, 1, 1, 2, 0)),    # z-slab order with Lz = 4
+           (wd.WD_F16, (128, 1, 1, 1, 1)),    # cap of 1 work-group per CU
+           (wd.WD_F16, (128, 1, 1, 1, 9)),    # cap of 9
+           (wd.WD_F16, (256, 1, 2, 8, 0)),    # LDS-staged with 2 lanes per site
+           (wd.WD_F16, (128, 1, 1, 11, 0)),   # t-walking tile larger than a plane
+           (wd.WD_F32, (64, 1, 1, 11, 0)),    # t-walking with FP32 spinors
+           (wd.WD_F64, (128, 3, 1, 0, 0))]    # FP64 with 3 RHS per lane
+    for code, shape in bad:
+        with pytest.raises(wd.WDError) as e:
+            wd.wd_dslash_shaped(lat.ctx, out, inp, wd.WD_ODD, 0, code, shape)
+        assert e.value.status == wd.WD_ERR_ARG, (code, shape)
+        assert bool((out == 7 + 7j).all()), (code, shape)
+    lat.close()
+
+
+def test_invalid_cache_lines_are_not_adopted(wd, tmp_path, monkeypatch):
+    """Cache lines the lattice or the link format cannot run (non-temporal
+    links with 18-real links, a z-slab order with Lz = 4, 96 threads) are
+    ignored and those sweeps are timed afresh; the valid line is verified and
+    adopted."""
+    dims = (8, 8, 4, 8)
+    lat = wd.Lattice(dims)
+    lat.gauge_load(dev(li.random_su3_field(dims, 0.5, seed=63)), recon=12)
+    key = "8 8 4 8 2 2 4"  # dims, nrhs 2, FP16 spinors, FP32 18-real links
+    cache = tmp_path / "tune.txt"
+    cache.write_text(f"{key} 0 0 128 1 1 1 0 1.0 1\n"   # D_oe: lnt with 18-real links
+                     f"{key} 0 1 128 1 1 2 0 1.0\n"     # xpay: z-slab order, Lz = 4
+                     f"{key} 1 0 96 1 1 1 0 1.0\n"      # D_oe^dag: 96 threads
+                     f"{key} 1 2 128 1 1 1 3 1.0\n")    # CG update: valid
+    monkeypatch.setenv("WD_TUNE_CACHE", str(cache))
+    rows = wd.wd_tune(lat.ctx, 2, wd.WD_F16 | wd.WD_LINKS_R18)
+    assert [r["source"] for r in rows] == ["timed", "timed", "timed", "cache-verified"], rows
+    assert all(r["rejected"] == 0 for r in rows) and rows[3]["occ"] == 3
+    lat.close()
