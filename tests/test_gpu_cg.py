@@ -235,3 +235,33 @@ def test_initial_guess(wd, oracle):
     assert [s["iters"] for s in s3] == [s["iters"] for s in s0]
     assert torch.equal(Xz, X0)
     lat.close()
+
+
+@pytest.mark.parametrize("prec", ["F64", "F16"])
+@pytest.mark.parametrize("poll", [1, 5, 13])
+def test_poll_intervals_off_the_ring_length(wd, oracle, prec, poll):
+    """Residual checks every 1, 5 or 13 iterations, i.e. steps that end
+    before, inside or after a ring of 8 search directions (the solution is
+    flushed at the end of each ring and of each step): every RHS meets 1e-10
+    by the oracle's operator, and the step replayed as a captured graph gives
+    the eager launches' bits."""
+    code = {"F64": wd.WD_F64, "F16": wd.WD_F16}[prec]
+    dims = (8, 8, 8, 8)
+    V = li.volume(dims)
+    U = li.random_su3_field(dims, 0.5, seed=71)
+    B = li.gaussian_spinor(V // 2, seed=72, nrhs=3)
+    kap = [0.15, 0.153, 0.156]
+    lat = wd.Lattice(dims)
+    lat.gauge_load(dev(U), recon=12)
+    X = {}
+    for graphs in (1, 0):
+        X[graphs] = empty_like_dev(B)
+        st, stats = lat.cg_solve(X[graphs], dev(B), kap, wd.solver_params(prec=code, poll=poll, graphs=graphs))
+        assert st == wd.WD_OK, (graphs, stats)
+    Xh = host(X[1])
+    assert np.array_equal(Xh, host(X[0]))
+    for j in range(3):
+        tr = true_resid(oracle, dims, U, kap[j], Xh[j], B[j], eo=True)
+        note(f"poll {poll} {prec} rhs {j}: iters {stats[j]['iters']} oracle {tr:.3e}")
+        assert tr <= 1.01e-10
+    lat.close()
