@@ -9,8 +9,7 @@
  * GPU"), not for speed: full 4x4 gamma matrices, full 3x3 links, the even-odd
  * blocks taken as restrictions of the full operator.
  *
- * Conventions (the paper leaves them open; the readings are listed in the
- * design notes and restated here):
+ * Conventions (the paper leaves them open; the readings taken are these):
  *   lattice   dims (Lx,Ly,Lz,Lt), all even; lex = x + Lx*(y + Ly*(z + Lz*t));
  *             parity = (x+y+z+t) & 1; checkerboard index cb = lex >> 1;
  *             periodic in all four directions (Sec. 1 lattice, Sec. 3
