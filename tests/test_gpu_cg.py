@@ -91,6 +91,34 @@ def test_multi_rhs_equals_single(wd, prec):
     lat.close()
 
 
+@pytest.mark.parametrize("prec", ["F64", "F16"])
+def test_large_batch_equals_single(wd, oracle, prec):
+    """70 right-hand sides in one solve (more than the 64 the tuner takes, 70
+    RHS groups in the default shape): sampled RHS equal their single solves
+    bit for bit, and every RHS meets 1e-10 by the oracle's operator."""
+    dims = (6, 4, 4, 6)
+    code = {"F64": wd.WD_F64, "F16": wd.WD_F16}[prec]
+    V = li.volume(dims)
+    U = li.random_su3_field(dims, 0.5, seed=23)
+    n = 70
+    B = li.gaussian_spinor(V // 2, seed=24, nrhs=n)
+    kappas = [(0.14, 0.15, 0.155, 0.157, 0.156)[j % 5] for j in range(n)]
+    lat = wd.Lattice(dims)
+    lat.gauge_load(dev(U), recon=12)
+    X = empty_like_dev(B)
+    st, stats = lat.cg_solve(X, dev(B), kappas, wd.solver_params(prec=code))
+    assert st == wd.WD_OK
+    Xb = host(X)
+    for j in range(n):
+        assert true_resid(oracle, dims, U, kappas[j], Xb[j], B[j], eo=True) <= 1.01e-10, j
+    for j in (0, 33, 69):
+        x1 = empty_like_dev(B[j])
+        s1, st1 = lat.cg_solve(x1, dev(B[j]), kappas[j], wd.solver_params(prec=code))
+        assert s1 == wd.WD_OK and st1[0]["iters"] == stats[j]["iters"]
+        assert np.array_equal(host(x1), Xb[j]), j
+    lat.close()
+
+
 def test_noconv_and_nan_and_zero(wd):
     dims = (4, 4, 4, 4)
     V = li.volume(dims)
