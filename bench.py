@@ -126,7 +126,7 @@ def counter_valu_busy(workload, prec, kernel):
 def parse():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=None, help="timed steps (default 3; c5: 40 trajectories)")
+    ap.add_argument("--steps", type=int, default=None, help="timed steps (default 20; c5: 40 trajectories)")
     ap.add_argument("--warmup", type=int, default=None, help="untimed steps (default 1; c5: 60 "
                     "thermalisation trajectories)")
     ap.add_argument("--workload", default="c3_32c64_12rhs", choices=sorted(WORKLOADS))
@@ -160,7 +160,7 @@ def parse():
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one plain 1 GiB device copy (counter calibration)")
     a = ap.parse_args()
-    ds, dw = DEFAULT_STEPS.get(a.workload, (3, 1))
+    ds, dw = DEFAULT_STEPS.get(a.workload, (20, 1))
     a.steps = ds if a.steps is None else a.steps
     a.warmup = dw if a.warmup is None else a.warmup
     return a
