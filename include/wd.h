@@ -123,7 +123,9 @@ void wd_solver_defaults(wd_solver_params *p);
  * handle.  WD_ERR_DIMS for an odd or too small extent, or V >= 2^31. */
 wd_status wd_create(wd_ctx **c, const int32_t dims[4], int device, void *hip_stream);
 
-/* Free the context and everything it owns.  NULL is accepted. */
+/* Free the context and everything it owns.  NULL is accepted.  Solver
+ * sessions created on it must be destroyed first: WD_ERR_STATE (nothing
+ * freed) while any is open. */
 wd_status wd_destroy(wd_ctx *c);
 
 /* Bind a different stream for subsequent work (NULL = null stream). */
@@ -218,7 +220,8 @@ typedef struct wd_session wd_session;
  * wd_session_resize changes the number later. */
 wd_status wd_session_create(wd_ctx *c, int max_rhs, const wd_solver_params *p, wd_session **s);
 
-/* Free the session and its device state.  NULL is accepted. */
+/* Free the session and its device state (before its context).  NULL is
+ * accepted. */
 wd_status wd_session_destroy(wd_session *s);
 
 /* Add nrhs right-hand sides phi ([nrhs][sites][4][3] device, sites = Vh for

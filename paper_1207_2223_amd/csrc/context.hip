@@ -417,6 +417,9 @@ wd_status wd_create(wd_ctx **out, const int32_t dims[4], int device, void *hip_s
 wd_status wd_destroy(wd_ctx *c)
 {
     if (!c) return WD_OK;
+    if (c->sessions > 0)
+        return set_error(WD_ERR_STATE, "%d solver session(s) still open on this context: destroy them first",
+                         c->sessions);
     (void)hipSetDevice(c->device);
     (void)hipStreamSynchronize(c->stream);
     for (auto &kv : c->ws) (void)hipFree(kv.second.first);

@@ -870,6 +870,7 @@ extern "C" wd_status wd_session_create(wd_ctx *c, int max_rhs, const wd_solver_p
         return st;
     }
     s->t0 = std::chrono::steady_clock::now();
+    c->sessions++;
     *out = s;
     return WD_OK;
 }
@@ -877,10 +878,12 @@ extern "C" wd_status wd_session_create(wd_ctx *c, int max_rhs, const wd_solver_p
 extern "C" wd_status wd_session_destroy(wd_session *s)
 {
     if (!s) return WD_OK;
-    (void)hipSetDevice(s->bs.c->device);
-    (void)hipStreamSynchronize(s->bs.c->stream);
+    wd_ctx *c = s->bs.c;
+    (void)hipSetDevice(c->device);
+    (void)hipStreamSynchronize(c->stream);
     s->bs.release();
     delete s;
+    c->sessions--;
     return WD_OK;
 }
 

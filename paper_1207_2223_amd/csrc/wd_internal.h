@@ -187,12 +187,13 @@ struct wd_ctx {
     wd::Geom g{};
 
     bool have_gauge = false;
+    int sessions = 0;  // solver sessions open on this context
     int lk64 = wd::LK_F64_18;
     char *links64 = nullptr;
     char *links32 = nullptr;
     char *links16 = nullptr;
     char *links32r = nullptr;  // FP32 18-real
-    char *links8 = nullptr;    // FP32 8-real (flagged links in links32)
+    char *links8 = nullptr;    // FP32 8-real
 
     // named, growable device workspaces
     std::map<std::string, std::pair<void *, size_t>> ws;

@@ -99,6 +99,12 @@ def test_session_errors(wd):
     wd.wd_session_take(s, slots[0], x)
     states, _ = wd.wd_session_poll(s, 2)
     assert states[slots[0]] == 0 and states[slots[1]] == 2
+    # the context refuses to go while a session on it is open, and the
+    # session still works afterwards
+    with pytest.raises(wd.WDError) as e:
+        wd.wd_destroy(lat.ctx)
+    assert e.value.status == wd.WD_ERR_STATE
+    wd.wd_session_take(s, slots[1], x)
     wd.wd_session_destroy(s)
     lat.close()
 
