@@ -93,6 +93,13 @@ std::string sweep_key(int sp, int lk, int dag, int epi)
 const TuneCfg *tuned_cfg(const wd_ctx *c, const Sweep &sw)
 {
     auto it = c->tuned.find(sweep_key(sw.sp, sw.lk, sw.dag, sw.epi));
+    if (it == c->tuned.end() && sw.dag && sw.epi == EPI_XPAY)
+        // D_eo^dag with the xpay epilogue (the last sweep of a whole
+        // Mhat^dag Mhat application, as in a reliable update) is not one of
+        // the solver's four sweeps the tuner times: it takes the shape tuned
+        // for D_eo^dag with the CG update, the same stencil direction (every
+        // shape gives the same bits)
+        it = c->tuned.find(sweep_key(sw.sp, sw.lk, 1, EPI_CGUPD));
     return it == c->tuned.end() ? nullptr : &it->second;
 }
 
