@@ -95,3 +95,23 @@ def test_t_cut_share_needs_more_than_one_slab():
         bench.shard_section(None, None, (4, 4, 4, 4))
     with pytest.raises(ValueError):
         bench.shard_section(None, None, (8, 8, 8, 8))
+
+
+def test_line_contract_keys_and_cache_note():
+    """The JSON line's fixed keys, the roofline entry's keys, and the
+    cache-resident note only for launches that fit the last-level cache."""
+    import argparse
+    import bench
+    args = argparse.Namespace(steps=20, warmup=1)
+    rec = bench.base_record(args, 22.0, "solves/s", 545.0, "f16+norm/f32", {"workload": "w"})
+    for k in ("metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step", "higher_is_better",
+              "scaling", "vs_baseline", "dtype", "data", "config"):
+        assert k in rec, k
+    assert rec["n_gpus"] == 1 and rec["vs_baseline"] is None and rec["config"]["workload"] == "w"
+    big = {"k": (10, 7.4, 10 * 3.02e9, 10 * 12582912.0)}
+    small = {"k": (10, 0.35, 10 * 1.34e8, 10 * 524288.0)}
+    _, rb, _ = bench.kernel_roofline(big)
+    _, rs, _ = bench.kernel_roofline(small)
+    for r in (rb, rs):
+        assert {"bound", "achieved", "peak", "unit", "frac", "traffic"} <= set(r)
+    assert "note" not in rb and rs["note"].startswith("cache-resident")
