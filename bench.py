@@ -32,7 +32,8 @@ Printed: one JSON line with the workload's rate (value), the FP64 rate on the
 same inputs, the dominant stencil kernel's roofline entry (HIP events on the
 context's stream) and the CPU oracle baseline; for c1-c3 also the solve time
 against the CG iteration count (tolerances 1e-2 .. 1e-10: per-iteration time
-and per-solve overhead) and the stencil alone in every format.
+and per-solve overhead) and the stencil alone in every format; the full c3 line also carries the c2
+workload in brief (`also`).
 """
 import argparse
 import json
@@ -132,6 +133,8 @@ def parse():
     ap.add_argument("--workload", default="c3_32c64_12rhs", choices=sorted(WORKLOADS))
     ap.add_argument("--prec", default="f16", choices=sorted(PRECS))
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison")
+    ap.add_argument("--no-also", action="store_true",
+                    help="c3: skip the brief c2 result the full line carries (also skipped with --no-dslash)")
     ap.add_argument("--no-fit", action="store_true",
                     help="c1-c3: skip the solve time against iteration count (tolerances 1e-2 .. 1e-10)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
@@ -1042,6 +1045,29 @@ def use_shape_table(args):
     atexit.register(shutil.rmtree, d, True)
 
 
+def also_c2(args, wd, torch):
+    """The c2 workload (16^3 x 32, 8 RHS, kappa 0.155) in brief, run after the
+    c3 line's own measurements so that one default run records both: its
+    solve rate and the FP64 rate on the same inputs, the oracle's residuals
+    of its solutions, its CPU baseline and its dominant kernel's roofline
+    entry (cache-resident at this size)."""
+    import copy
+    a = copy.copy(args)
+    a.workload, a.steps, a.warmup = "c2_16c32", 20, 1
+    a.no_dslash, a.no_fit, a.shapes, a.dslash_only, a.tune_only, a.copy_probe = True, True, None, False, False, False
+    try:
+        r = bench_solve(a, wd, torch)
+    except Exception as e:  # the c3 line stands on its own
+        return {"error": f"{type(e).__name__}: {e}"}
+    out = {k: r.get(k) for k in ("value", "unit", "ms_per_step", "iters", "converged", "max_true_resid",
+                                 "oracle_max_true_resid", "latency_ms", "mixed_vs_fp64", "roofline")}
+    out["fp64_solves_per_s"] = r["fp64"]["solves_per_s"] if r.get("fp64") else None
+    out["dominant_kernel"] = {k: r["dominant_kernel"][k] for k in ("name", "avg_us", "bytes_per_launch")}
+    cpu = r.get("cpu_baseline")
+    out["cpu_baseline"] = {k: cpu[k] for k in ("value", "unit", "cores", "sample")} if cpu else None
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -1060,6 +1086,9 @@ def main():
         out = bench_measure(args, wd, torch)
     else:
         out = bench_solve(args, wd, torch)
+        # the full default c3 line also carries the c2 workload in brief
+        if out is not None and args.workload == "c3_32c64_12rhs" and not (args.no_also or args.no_dslash):
+            out["also"] = {"c2_16c32": also_c2(args, wd, torch)}
     if out is not None:
         print(json.dumps(out), flush=True)
 
